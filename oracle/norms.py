@@ -1,0 +1,68 @@
+"""Oracle: norms used for parity, stopping and error reporting (paper Sec. 5).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+* ``spectral_norm``: ||x||^2 = sum_n |x_{0,n}|^2 + 2 sum_{m>=1,n} |x_{m,n}|^2,
+  which by Parseval equals the area-weighted mean of x^2 over the sphere.  For
+  Phi the (0,0) coefficient is excluded (the norm is taken of Phi').
+  Pinned against the grid quadrature of x^2 in tests.
+* ``rel_err``: per field ||a - b|| / ||b|| (parity metric).
+* ``max_increment``: stopping test, max over fields and slices of
+  ||U^{k+1}_n - U^k_n|| / ||U^{k+1}_n||.
+* ``spectral_maxnorm_error``: the paper's E_{psi,R} -- the largest modulus of
+  the coefficient difference over m <= n <= R, divided by the largest
+  reference modulus over the same modes (Sec. 5, eq. error_definition).
+"""
+
+import numpy as np
+
+
+def _weights(M, exclude_mean):
+    w = np.empty((M + 1) * (M + 2) // 2)
+    k = 0
+    for m in range(M + 1):
+        K = M - m + 1
+        w[k:k + K] = 1.0 if m == 0 else 2.0
+        k += K
+    if exclude_mean:
+        w[0] = 0.0
+    return w
+
+
+def spectral_norm(x, M, exclude_mean=False):
+    w = _weights(M, exclude_mean)
+    return float(np.sqrt(np.sum(w * np.abs(x) ** 2)))
+
+
+def field_norms(U, M):
+    """Norms of (Phi', xi, delta) for a state U[3, ncoef]."""
+    return np.array([spectral_norm(U[0], M, True), spectral_norm(U[1], M),
+                     spectral_norm(U[2], M)])
+
+
+def rel_err(A, B, M):
+    """Per-field relative L2 error of A against reference B."""
+    d = field_norms(A - B, M)
+    r = field_norms(B, M)
+    return d / np.where(r > 0, r, 1.0)
+
+
+def max_increment(new, old, M):
+    """max over slices n >= 1 and fields of ||new_n - old_n|| / ||new_n||."""
+    worst = 0.0
+    for n in range(1, len(new)):
+        worst = max(worst, float(np.max(rel_err(new[n], old[n], M))))
+    return worst
+
+
+def spectral_maxnorm_error(x, ref, M, R):
+    num = 0.0
+    den = 0.0
+    k = 0
+    for m in range(M + 1):
+        for n in range(m, M + 1):
+            if m <= R and n <= R:
+                num = max(num, abs(x[k] - ref[k]))
+                den = max(den, abs(ref[k]))
+            k += 1
+    return num / den if den > 0 else num

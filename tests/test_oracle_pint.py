@@ -1,0 +1,117 @@
+"""Pins of the oracle's Parareal and MGRIT drivers (paper Sec. 3 and 4.2)."""
+
+import numpy as np
+import pytest
+
+from oracle import pint
+from oracle.norms import rel_err
+from oracle.swe import Model
+from paper_2306_09497_amd import workloads
+
+
+def imex_amp(xl, xn):
+    """Scalar IMEX amplification: CN half steps around a Heun step."""
+    ai = (4 + xl) / (4 - xl)
+    return ai * (1 + xn + 0.5 * xn * xn) * ai
+
+
+@pytest.mark.parametrize("k", [0, 1, 3, 7])
+def test_parareal_stability_function(k):
+    """P13: on u' = (lam_L + lam_N) u, the Parareal iterate equals
+    sum_{i<=k} C(n,i) (F-R)^i R^(n-i) u0 (Sec. 4.2, eq. recurrence_parareal)."""
+    lamL, lamN = 2.5e-3j, -1e-5 + 4e-5j
+    dtf, nf, m = 60.0, 30, 10
+    dtc, nc = dtf * m, 3
+    F = imex_amp(lamL * dtf, lamN * dtf) ** nf
+    R = imex_amp(lamL * dtc, lamN * dtc) ** nc
+    N = 12
+    u0 = 1.0 + 0.5j
+    U, _ = pint.parareal(u0, N, lambda u: F * u, lambda u: R * u, k)
+    for n in range(N + 1):
+        want = pint.parareal_stability(n, k, R, F) * u0
+        assert abs(U[n] - want) <= 1e-13 * abs(want) + 1e-15
+
+
+def test_parareal_finite_termination_scalar():
+    """P14: after N iterations Parareal reproduces the serial fine solution."""
+    F, R = 0.99 + 0.05j, 0.97 + 0.1j
+    U, _ = pint.parareal(1.0 + 0j, 9, lambda u: F * u, lambda u: R * u, 9)
+    ser = pint.serial(1.0 + 0j, 9, lambda u: F * u)
+    for a, b in zip(U, ser):
+        assert abs(a - b) < 1e-15
+
+
+def test_mgrit_recurrence_scalar():
+    """Two-level MGRIT F(CF)^nu on the scalar equation follows the paper's
+    overlapping-Parareal relation (eq. parareal_FCF_nrelax):
+    u^k_n = G u^k_{n-1} + F^(nu+1) u^{k-1}_{n-nu-1} - G F^nu u^{k-1}_{n-nu-1},
+    where the C-relaxation at the first nu C-points starts from u_0."""
+    f, g, m = 0.995 + 0.02j, 0.98 + 0.06j, 4
+    F = f ** m
+    N1 = 10
+    for nu in (0, 1, 2):
+        prev = [g ** n for n in range(N1 + 1)]          # iteration 0
+        for k in range(1, 5):
+            C, _ = pint.mgrit2(1.0 + 0j, N1, m, lambda u: f * u, lambda u: g * u, nu, k)
+            cur = [1.0 + 0j]
+            for n in range(1, N1 + 1):
+                j = n - nu - 1
+                if j >= 0:
+                    src, p = prev[j], nu
+                else:                       # relaxation chain starts at u_0
+                    src, p = 1.0 + 0j, n - 1
+                cur.append(g * cur[n - 1] + F ** (p + 1) * src - g * F ** p * src)
+            for a, b in zip(C, cur):
+                assert abs(a - b) < 1e-14
+            prev = cur
+
+
+def test_mgrit_nu0_is_parareal_scalar():
+    """P15 (scalar): MGRIT with (levels, nu) = (2, 0) is Parareal with
+    F = Phi_0^m and G = Phi_1, bitwise."""
+    f, g, m = 0.999 + 0.01j, 0.99 + 0.04j, 5
+    for k in range(0, 6):
+        C, _ = pint.mgrit2(1.0 + 0j, 8, m, lambda u: f * u, lambda u: g * u, 0, k)
+        P, _ = pint.parareal(1.0 + 0j, 8, lambda u: (((( f * u) * f) * f) * f) * f,
+                             lambda u: g * u, k)
+        assert all(a == b for a, b in zip(C, P))
+
+
+@pytest.fixture(scope="module")
+def c1_small():
+    """A shortened C1 problem: T21, 4 slices of 20 min, fine 60 s, coarse 600 s."""
+    md = Model(21, 64, 32, phibar=2.94e4)
+    U0 = workloads.solid_body(21, noise=1e-6, seed=0)
+    fine = lambda u: md.propagate(u, 60.0, 20)
+    coarse = lambda u: md.propagate(u, 600.0, 2)
+    return md, U0, fine, coarse
+
+
+def test_parareal_exact_swe(c1_small):
+    """P14: Parareal with k = N reproduces the serial fine states (bitwise in
+    this deterministic oracle)."""
+    md, U0, fine, coarse = c1_small
+    N = 4
+    U, _ = pint.parareal(U0, N, fine, coarse, N)
+    ser = pint.serial(U0, N, fine)
+    for a, b in zip(U, ser):
+        assert np.array_equal(a, b)
+
+
+def test_mgrit_swe(c1_small):
+    """P15/P16 on the SWE: MGRIT(2,0) equals Parareal bitwise (fine = 20 steps
+    of Phi_0), and MGRIT FCF is exact after ceil(N_1/2) iterations."""
+    md, U0, fine, coarse = c1_small
+    phi0 = lambda u: md.propagate(u, 60.0, 1)
+    for k in (1, 2):
+        C, _ = pint.mgrit2(U0, 4, 20, phi0, coarse, 0, k)
+        P, _ = pint.parareal(U0, 4, fine, coarse, k)
+        for a, b in zip(C, P):
+            assert np.array_equal(a, b)
+    C, _ = pint.mgrit2(U0, 4, 20, phi0, coarse, 1, 2)
+    ser = pint.serial(U0, 4, fine)
+    for a, b in zip(C, ser):
+        assert np.max(rel_err(a, b, 21)) < 1e-13
+    # and not yet exact after one FCF iteration
+    C1, _ = pint.mgrit2(U0, 4, 20, phi0, coarse, 1, 1)
+    assert np.max(rel_err(C1[4], ser[4], 21)) > 1e-9
