@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X shallow-water PinT path on one GPU.
+
+One step = one two-level MGRIT iteration with FCF relaxation (Sec. 3.2) over
+one T255 slice group: 64 C-intervals x cfactor 4 = 256 fine time points,
+fine IMEX dt = 45 s, coarse IMEX dt = 180 s with 4th-order hyperviscosity
+nu = 1e17 m^4/s on the coarse level (paper's table for IMEX coarse levels).
+Each step runs every row of the hot path: the batched fine propagator (CN
+solve, Legendre synthesis GEMM, ring FFT + tendencies, Legendre analysis
+GEMM, RK assembly, viscosity) over the 64 intervals for the F- and
+C-relaxations and the fine propagation, the batched coarse propagator on the
+relaxed C-points, the serial coarse correction sweep and the increment norms.
+
+value = fine slice-steps executed / wall time of the timed steps.
+Inputs are synthetic (jet + height bump shaped like the paper's unstable-jet
+test), generated on the device before timing.  The dominant kernel's
+roofline figure is timed live with HIP events on the library's stream; the
+CPU baseline is the FP64 oracle timed on this host on a bounded sample.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+M, NLON, NLAT = 255, 768, 384
+GROUP = 64                  # C-intervals per slice group (one launch batch)
+CFACTOR = 4
+DT_FINE, DT_COARSE = 45.0, 180.0
+NU_COARSE, Q_COARSE = 1.0e17, 4
+PHIBAR = 9.80616e4          # g * 10 km mean depth
+PEAK_FP64 = 78.6e12         # MI355X dense FP64 (matrix and vector), FLOP/s
+PEAK_HBM = 8.0e12           # MI355X HBM3E, B/s
+
+
+def algorithmic_work(kind, B):
+    """Algorithmic FLOPs and HBM bytes of one launch over B states (T255).
+
+    Legendre GEMMs (N/S folded): rows n = m..M+1 per m, parity-split, against
+    the nlat/2 northern latitudes; synthesis has 6 fields x (re, im) columns
+    per state, analysis 4.  Bytes: table once + operands + result once.
+    """
+    nrows = (M + 1) * (M + 4) // 2          # sum_m (M - m + 2)
+    nl2 = NLAT // 2
+    if kind == "legendre_synth":
+        cols = 12 * B
+        flops = 2.0 * nl2 * nrows * cols
+        byts = 8.0 * (nrows * nl2 + nrows * cols + 2 * (M + 1) * nl2 * cols)
+    elif kind == "legendre_anal":
+        cols = 8 * B
+        flops = 2.0 * nl2 * nrows * cols
+        byts = 8.0 * (nrows * nl2 + (M + 1) * NLAT * cols + nrows * cols)
+    elif kind == "ring_tendency":
+        # read the E/O synthesis rows once, write the 4 analysis fields once
+        flops = 0.0
+        byts = 8.0 * (2 * (M + 1) * nl2 * 12 * B + (M + 1) * NLAT * 8 * B)
+    else:
+        flops, byts = 0.0, 0.0
+    return flops, byts
+
+
+def cpu_baseline(seconds):
+    """The FP64 oracle on this host: fine IMEX steps of one T255 slice."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle.swe import Model
+    from paper_2306_09497_amd import workloads
+
+    md = Model(M, NLON, NLAT, phibar=PHIBAR)
+    G = workloads.jet_bump_grid(md.grid.mu, NLON, phibar=PHIBAR, **workloads.jet_bump_params(0))
+    U = np.stack([md.grid.anal(G[f]) for f in range(3)])
+    md.imex_step(U, DT_FINE)                  # untimed: builds the per-m LU factors
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        U = md.imex_step(U, DT_FINE)
+        n += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return {"value": n / dt, "unit": "fine slice-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} fine IMEX steps (dt {DT_FINE:g} s) of one T255 768x384 jet+bump "
+                      f"slice after LU setup, {dt:.1f} s; host has "
+                      f"{len(os.sched_getaffinity(0))} cores available"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the whole PinT problem on a "
+              "single MI355X (time slices are the batch dimension); --gpus must be 1.",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_2306_09497_amd import pint, workloads
+
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    plan = pint.Plan(M, NLON, NLAT, phibar=PHIBAR, max_batch=GROUP)
+    # synthetic jet + bump initial state, analysed on the device
+    mu, _ = plan.grid_coords()
+    G = workloads.jet_bump_grid(mu, NLON, phibar=PHIBAR, **workloads.jet_bump_params(0))
+    grid = torch.from_numpy(np.ascontiguousarray(G)).cuda()
+    u0 = torch.zeros((1, 3, plan.ncoef, 2), dtype=torch.float64, device="cuda")
+    plan.analysis(grid, u0, 3)
+    slices = torch.zeros((GROUP + 1, 3, plan.ncoef, 2), dtype=torch.float64, device="cuda")
+    fine = pint.stepper(DT_FINE, 2, 0.0, pint.T_ALL)
+    coarse = pint.stepper(DT_COARSE, Q_COARSE, NU_COARSE, pint.T_ALL)
+    plan.solve(pint.params(pint.MGRIT, GROUP, fine, CFACTOR, coarse, 1, nrelax=1, max_iter=0),
+               u0, slices)                                     # initial coarse sweep
+    it = pint.params(pint.MGRIT, GROUP, fine, CFACTOR, coarse, 1, nrelax=1, max_iter=1,
+                     resume=True)
+    for _ in range(args.warmup):
+        plan.solve(it, u0, slices)
+    torch.cuda.synchronize()
+
+    # timed region: exactly `steps` MGRIT iterations; the batched launches of
+    # the three transform kernels are bracketed by HIP events
+    plan.profile(["legendre_synth", "ring_tendency", "legendre_anal"], min_batch=GROUP)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fine_steps = 0
+    incr = []
+    for _ in range(args.steps):
+        rep = plan.solve(it, u0, slices)
+        fine_steps += rep.fine_slice_steps
+        incr.append(rep.incr[0])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = plan.profile_read()
+    plan.profile([])
+    elapsed = t1 - t0
+    value = fine_steps / elapsed
+
+    # dominant kernel of the timed region and its roofline
+    per_kind = {}
+    for (kind, b), (n, ms) in prof.items():
+        if b == GROUP:
+            per_kind[kind] = (n, ms)
+    dom = max(per_kind, key=lambda k: per_kind[k][1])
+    n_launch, tot_ms = per_kind[dom]
+    avg_s = tot_ms / n_launch * 1e-3
+    flops, byts = algorithmic_work(dom, GROUP)
+    if flops > 0:
+        roof = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": PEAK_FP64 / 1e12,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": PEAK_HBM / 1e9,
+                "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["avg_launch_ms"] = tot_ms / n_launch
+
+    kernels = {}
+    for kind, (n, ms) in sorted(per_kind.items()):
+        f, b = algorithmic_work(kind, GROUP)
+        avg = ms / n * 1e-3
+        kernels[kind] = {"launches": n, "avg_ms": ms / n,
+                         "share_of_step": ms * 1e-3 / elapsed,
+                         "tflops": f / avg / 1e12 if f else None,
+                         "gbps_algorithmic": b / avg / 1e9}
+
+    out = {
+        "metric": "fine slice-steps/s at T255",
+        "value": value,
+        "unit": "slice-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "T255 768x384, two-level MGRIT FCF iteration over one slice group: "
+                        "64 C-intervals x cfactor 4, fine IMEX dt 45 s, coarse IMEX dt 180 s "
+                        "with q=4 nu=1e17, jet + height bump initial state",
+            "truncation": M, "nlon": NLON, "nlat": NLAT, "batch": GROUP,
+            "fine_slice_steps_per_step": fine_steps // args.steps,
+            "parallelism": "time slices as the batch dimension, 1 GPU",
+        },
+        "roofline": roof,
+        "kernels": kernels,
+        "mgrit_increment": incr,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    plan.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

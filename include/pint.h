@@ -1,0 +1,210 @@
+/*
+ * pint.h -- C ABI of the MI355X spherical-harmonic shallow-water propagator
+ * and its parallel-in-time drivers (arXiv 2306.09497).
+ *
+ * The library computes, on one AMD Instinct MI355X (gfx950), the IMEX time
+ * step of the rotating shallow-water equations in vorticity/divergence/
+ * geopotential form (Sec. 2.1, eq. swe_sphere), discretised with spherical
+ * harmonics under triangular truncation on a Gauss grid (Sec. 2.2), and runs
+ * it batched over many time slices inside Parareal (Sec. 3.1) and two-level
+ * MGRIT (Sec. 3.2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Spectral coefficients: Y_{m,n} = Pbar_n^m(mu) exp(i m lambda), mu = sin(lat),
+ *   Pbar normalised to 1/2 int Pbar^2 dmu = 1, no Condon-Shortley phase; real
+ *   fields keep m >= 0.  Packed m-major: idx(m,n) = m(2M+3-m)/2 + (n-m),
+ *   0 <= m <= n <= M; ncoef = (M+1)(M+2)/2.  Each coefficient is complex,
+ *   stored as two doubles (re, im).
+ * State: three fields ordered (Phi, xi, delta) -- geopotential (in full: its
+ *   (0,0) coefficient is the area mean), vorticity, divergence.  A batch of B
+ *   states is [B][3][ncoef][2] doubles, batch-major.
+ * Grid: lambda_k = 2 pi k / nlon; Gauss latitudes ordered north to south.  A
+ *   batch of B grid fields is [B][nlat][nlon] doubles.
+ * Memory: every state/grid pointer is DEVICE memory owned by the caller
+ *   (e.g. a torch tensor's data_ptr); sizes are element counts as stated.
+ *   Arrays passed to one call must not overlap unless said otherwise.
+ * Streams: `stream` is a hipStream_t (NULL = the null stream).  All work is
+ *   enqueued on it and the call returns without waiting, except where a call
+ *   says it synchronises.
+ * Errors: every call returns a pint_status and never aborts; a message for
+ *   the calling thread is available from pint_last_error().  A plan is not
+ *   thread-safe; distinct plans may be used from distinct threads.
+ */
+#ifndef PINT_H
+#define PINT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PINT_OK = 0,
+  PINT_E_INVAL = -1,    /* invalid argument: message says which            */
+  PINT_E_NOMEM = -2,    /* device allocation failed                         */
+  PINT_E_HIP = -3,      /* a HIP runtime call failed                        */
+  PINT_E_DIVERGED = -4, /* NaN/Inf or blow-up detected in a PinT iteration  */
+  PINT_E_NOTCONV = -5   /* tolerance not reached within max_iter            */
+} pint_status;
+
+/* Operator switches (tests only; production uses PINT_T_ALL). */
+enum {
+  PINT_T_LG = 1,    /* linear gravity  L_G = (-Phibar delta, 0, -lap Phi)   */
+  PINT_T_LC = 2,    /* linear Coriolis L_C = (0, -div(fV), k.curl(fV))      */
+  PINT_T_NL = 4,    /* nonlinear N = N_A + N_R                              */
+  PINT_T_VISC = 8,  /* backward-Euler (hyper)viscosity                      */
+  PINT_T_ALL = 15
+};
+
+/* Truncation, grid and planet.  Requires M >= 1, nlat even, nlat >= M+2,
+ * nlon >= 2M+2, nlon = 2^a 3^b 5^c <= 1024; the 3/2 rule (nlon >= 3M+3,
+ * nlat >= (3M+3)/2) makes the quadratic terms alias-free (Sec. 2.2).
+ * phibar is the constant mean geopotential Phibar of L_G (Sec. 2.1).
+ * max_batch bounds the number of states one internal launch processes; the
+ * plan's workspace is sized for it (larger calls are split into chunks).  */
+typedef struct {
+  int M, nlon, nlat;
+  double a, omega, g, phibar;
+  int max_batch;
+} pint_config;
+
+/* One time stepper: IMEX step of size dt (Sec. 2.3.1, eq. IMEX), followed by
+ * backward-Euler viscosity of even order q >= 2 and coefficient nu >= 0
+ * (App. A; nu = 0 disables it).  `terms` is a PINT_T_* mask.  */
+typedef struct {
+  double dt;
+  int visc_order;
+  double visc_nu;
+  unsigned terms;
+} pint_stepper;
+
+typedef struct pint_plan pint_plan;
+
+typedef struct {
+  int M, nlon, nlat, ncoef, max_batch;
+  size_t state_doubles;        /* 3 * ncoef * 2: doubles per state           */
+  size_t workspace_bytes;      /* device memory the plan holds               */
+} pint_info;
+
+/* Create a plan: Gauss nodes and weights (Newton iteration), normalised
+ * associated Legendre tables and FFT twiddles are generated on the device in
+ * FP64 (Sec. 2.2), and workspace for max_batch states is allocated.  The call
+ * synchronises `stream` before returning.  On error *out is NULL.  */
+pint_status pint_plan_create(const pint_config* cfg, void* stream, pint_plan** out);
+pint_status pint_plan_destroy(pint_plan* plan);
+pint_status pint_plan_info(const pint_plan* plan, pint_info* info);
+
+/* Copy the Gauss latitudes to HOST memory: mu[nlat] (sin of latitude, north
+ * to south) and w[nlat] (weights, sum 2).  Synchronises `stream`.  */
+pint_status pint_grid_coords(pint_plan* plan, double* mu_host, double* w_host, void* stream);
+
+/* Scalar spherical-harmonic transforms of B fields (Sec. 2.2: FFT in
+ * longitude, Legendre transform in latitude).
+ * synthesis: spec[B][ncoef][2] -> grid[B][nlat][nlon]
+ * analysis:  grid[B][nlat][nlon] -> spec[B][ncoef][2]
+ *            s_{m,n} = 1/2 sum_j w_j Pbar_n^m(mu_j) (1/nlon) sum_k s_jk e^{-i m lambda_k}  */
+pint_status pint_synthesis(pint_plan* plan, const double* spec, double* grid, int B, void* stream);
+pint_status pint_analysis(pint_plan* plan, const double* grid, double* spec, int B, void* stream);
+
+/* Nonlinear tendencies N(U) = N_A(U) + N_R(U) (Sec. 2.1) of B states,
+ * pseudospectral on the plan's grid (Sec. 2.2): u[B][3][ncoef][2] ->
+ * n_out[B][3][ncoef][2].  The (0,0) coefficients of N_xi and N_delta are 0.  */
+pint_status pint_tendency(pint_plan* plan, const double* u, double* n_out, int B, void* stream);
+
+/* Crank-Nicolson half step of the linear terms (Sec. 2.3.1, eq.
+ * IMEX_implicit): solves (I - dt/4 L) x = (I + dt/4 L) u, L = L_G + L_C
+ * restricted by st->terms, with the Coriolis term implicit (per zonal
+ * wavenumber two tridiagonal chains); then, if st->terms has PINT_T_VISC,
+ * applies the viscosity factor 1/(1 + dt nu (n(n+1)/a^2)^(q/2)).
+ * u and x are [B][3][ncoef][2]; x may alias u.  */
+pint_status pint_implicit(pint_plan* plan, const pint_stepper* st, const double* u, double* x,
+                          int B, void* stream);
+
+/* The fine/coarse propagator, the hot path: nsteps IMEX steps (eq. IMEX,
+ * CN half step, Heun explicit stage, CN half step, viscosity) applied
+ * independently to each of B states (time slices).  u_in and u_out are
+ * [B][3][ncoef][2]; u_out may alias u_in.  Results for a state do not depend
+ * on B or on the other states (bitwise).  */
+pint_status pint_step(pint_plan* plan, const pint_stepper* st, const double* u_in, double* u_out,
+                      int B, int nsteps, void* stream);
+
+/* Parallel-in-time solve of dU/dt = L U + N(U) on [0, n_intervals * DT].
+ * method 0 = Parareal (Sec. 3.1): slices of length DT = fine.dt *
+ *   fine_steps = coarse.dt * coarse_steps; fine propagator = fine_steps
+ *   fine steps, coarse propagator = coarse_steps coarse steps.
+ * method 1 = two-level MGRIT with F(CF)^nrelax relaxation and FAS (Sec. 3.2):
+ *   fine level = fine.dt, cfactor = fine_steps fine steps per C-interval,
+ *   coarse level = coarse_steps coarse steps per C-interval.
+ *   With nrelax = 0 it is identical to Parareal.
+ * Iterates until the largest relative L2 increment of a slice state is
+ * <= tol, or max_iter iterations (tol = 0: exactly max_iter).  The increment
+ * of a slice is the larger of the relative changes of Phi' (Phi without its
+ * mean) and of the wind (vorticity and divergence through the velocity they
+ * induce), both area-weighted L2 norms (see pint_rel_diff).  u_slices[(n_intervals+1)][3][ncoef][2] receives the
+ * states at the slice (C-point) boundaries; u0 is its initial state.
+ * Synchronises `stream` once per iteration (to read the increment).  */
+typedef struct {
+  int method;             /* 0 Parareal, 1 MGRIT two-level                    */
+  int n_intervals;        /* N slices / C-intervals                           */
+  pint_stepper fine;      /* fine propagator step                             */
+  int fine_steps;         /* fine steps per slice (= MGRIT cfactor)            */
+  pint_stepper coarse;    /* coarse propagator step                           */
+  int coarse_steps;       /* coarse steps per slice                           */
+  int nrelax;             /* MGRIT F(CF)^nrelax; ignored by Parareal          */
+  int max_iter;
+  double tol;
+  int resume;             /* 1: u_slices already holds an iterate (all
+                             n_intervals+1 states, e.g. a checkpoint); skip
+                             the initial coarse sweep and continue from it  */
+} pint_pint_params;
+
+typedef struct {
+  int iters;                     /* iterations performed                      */
+  double incr[128];              /* max relative increment per iteration      */
+  double seconds[128];           /* wall time per iteration                   */
+  long long fine_slice_steps;    /* fine IMEX steps executed (sum over slices)*/
+  long long coarse_steps;        /* coarse IMEX steps executed                */
+} pint_report;
+
+pint_status pint_solve(pint_plan* plan, const pint_pint_params* p, const double* u0,
+                       double* u_slices, pint_report* report, void* stream);
+
+/* Relative L2 differences used by the stopping test: for each of B state
+ * pairs, out[b] = { ||dPhi'||/||Phi'||, ||dxi||/||xi||, ||ddelta||/||delta||,
+ * ||dV||/||V|| } of a_b against c_b (d = a - c, norms of a), with the
+ * area-weighted spectral norm (Parseval; Phi without its (0,0) coefficient)
+ * and the wind norm ||V||^2 = sum_{n>=1} w a^2/(n(n+1)) (|xi|^2 + |delta|^2),
+ * w = 1 for m = 0, 2 for m > 0.  a, c are device [B][3][ncoef][2]; out is
+ * HOST [B][4].  Synchronises `stream`.  */
+pint_status pint_rel_diff(pint_plan* plan, const double* a, const double* c, double* out_host,
+                          int B, void* stream);
+
+/* Kernel timing for measurement.  While enabled, every kernel launch of the
+ * plan whose kind is in kind_mask (bit 1 << kind) and that processes at least
+ * min_batch states is bracketed by HIP events on its stream (kind_mask = 0
+ * disables timing); pint_profile_read
+ * synchronises `stream`, sums the elapsed times per (kind, batch) and resets
+ * the record.  kind: 0 spectral prep, 1 Legendre synthesis GEMM, 2 ring
+ * FFT + tendencies, 3 Legendre analysis GEMM, 4 tendency assembly + RK
+ * combine, 5 Crank-Nicolson solve, 6 layout conversion, 7 PinT update and
+ * norms, 8 scalar-transform rings.  out has room for cap entries; *n
+ * receives the number written.  */
+typedef struct {
+  int kind;
+  int batch;             /* states per launch                                 */
+  long long launches;
+  double total_ms;
+} pint_prof_entry;
+
+pint_status pint_profile_enable(pint_plan* plan, unsigned kind_mask, int min_batch);
+pint_status pint_profile_read(pint_plan* plan, pint_prof_entry* out, int cap, int* n,
+                              void* stream);
+
+const char* pint_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PINT_H */

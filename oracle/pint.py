@@ -95,6 +95,7 @@ def mgrit2(u0, n_coarse, m, phi0, phi1, nu, n_iter, record=False,
         return last
 
     for _ in range(n_iter):
+        C_start = C
         last = f_relax(C)
         for _ in range(nu):
             # C-relaxation then F-relaxation
@@ -107,7 +108,7 @@ def mgrit2(u0, n_coarse, m, phi0, phi1, nu, n_iter, record=False,
             Gw = Gv[i] if i == 0 else phi1(W[i])
             W[i + 1] = (Gw - Gv[i]) + Fv[i]
         if incr_fn is not None:
-            incrs.append(incr_fn(W, C))
+            incrs.append(incr_fn(W, C_start))
         C = W
         if record:
             history.append(list(C))

@@ -49,9 +49,9 @@ def m_slice(M, m):
     return slice(s, s + (M - m + 1))
 
 
-def eps(m, n):
+def eps(m, n, dtype=np.float64):
     """eps_n^m = sqrt((n^2 - m^2) / (4 n^2 - 1)); zero for n <= m."""
-    n = np.asarray(n, dtype=np.float64)
+    n = np.asarray(n, dtype=dtype)
     val = (n * n - m * m) / (4.0 * n * n - 1.0)
     return np.sqrt(np.where(n > m, val, 0.0))
 
@@ -65,13 +65,16 @@ def _legendre_pair(n, x):
     return p1, p0
 
 
-def gauss_nodes(nlat):
+def gauss_nodes(nlat, with_coslat2=False, extended=False):
     """Gauss-Legendre nodes mu_j (north to south) and weights w_j (sum 2).
 
     Starts from numpy's ``leggauss`` nodes, polishes them with Newton steps on
     P_nlat in x87 extended precision and evaluates the weights there with
     w = 2 / ((1 - x^2) P'_nlat(x)^2).  (numpy's own weights lose about three
-    digits at nlat = 384.)
+    digits at nlat = 384.)  With ``with_coslat2`` also returns 1 - mu^2,
+    formed in extended precision (in float64 it cancels near the poles).
+    ``extended`` returns x87 extended-precision arrays (used only to
+    calibrate the rounding floor of the float64 path).
     """
     x0, _ = np.polynomial.legendre.leggauss(nlat)
     x = x0.astype(np.longdouble)
@@ -82,10 +85,14 @@ def gauss_nodes(nlat):
     pn, pn1 = _legendre_pair(nlat, x)
     dp = nlat * (x * pn - pn1) / (x * x - 1)
     w = 2 / ((1 - x * x) * dp * dp)
-    return x[::-1].astype(np.float64), w[::-1].astype(np.float64)
+    dt = np.longdouble if extended else np.float64
+    mu, w = x[::-1].astype(dt), w[::-1].astype(dt)
+    if with_coslat2:
+        return mu, w, (1 - x * x)[::-1].astype(dt)
+    return mu, w
 
 
-def pbar_table(nmax, mu):
+def pbar_table(nmax, mu, coslat2=None):
     """Normalised associated Legendre functions.
 
     Returns a list P with P[m] of shape (nmax-m+1, nlat): rows n = m..nmax.
@@ -94,20 +101,22 @@ def pbar_table(nmax, mu):
     recurrence mu Pbar_n = eps_{n+1} Pbar_{n+1} + eps_n Pbar_{n-1} solved for
     Pbar_{n+1}.
     """
-    mu = np.asarray(mu, dtype=np.float64)
-    s = np.sqrt(1.0 - mu * mu)
+    mu = np.asarray(mu)
+    if mu.dtype != np.longdouble:
+        mu = mu.astype(np.float64)
+    s = np.sqrt(1.0 - mu * mu if coslat2 is None else coslat2)
     out = []
     pmm = np.ones_like(mu)
     for m in range(nmax + 1):
         if m > 0:
-            pmm = np.sqrt((2.0 * m + 1.0) / (2.0 * m)) * s * pmm
-        rows = np.zeros((nmax - m + 1, mu.size))
+            pmm = np.sqrt(mu.dtype.type(2 * m + 1) / mu.dtype.type(2 * m)) * s * pmm
+        rows = np.zeros((nmax - m + 1, mu.size), dtype=mu.dtype)
         rows[0] = pmm
         if m + 1 <= nmax:
-            rows[1] = np.sqrt(2.0 * m + 3.0) * mu * pmm
+            rows[1] = np.sqrt(mu.dtype.type(2 * m + 3)) * mu * pmm
         for n in range(m + 2, nmax + 1):
             rows[n - m] = (mu * rows[n - m - 1]
-                           - eps(m, n - 1) * rows[n - m - 2]) / eps(m, n)
+                           - eps(m, n - 1, mu.dtype) * rows[n - m - 2]) / eps(m, n, mu.dtype)
         out.append(rows)
     return out
 
@@ -119,11 +128,11 @@ def hbar_table(P, mu, nmax):
     """
     out = []
     for m in range(nmax):
-        rows = np.zeros((nmax - m, mu.size))
+        rows = np.zeros((nmax - m, mu.size), dtype=mu.dtype)
         for n in range(m, nmax):
             h = -n * mu * P[m][n - m]
             if n > m:
-                h = h + (2 * n + 1) * eps(m, n) * P[m][n - m - 1]
+                h = h + (2 * n + 1) * eps(m, n, mu.dtype) * P[m][n - m - 1]
             rows[n - m] = h
         out.append(rows)
     return out
@@ -132,15 +141,17 @@ def hbar_table(P, mu, nmax):
 class Grid:
     """Gauss grid plus Legendre tables for truncation M (Sec. 2.2)."""
 
-    def __init__(self, M, nlon, nlat, a=6.37122e6):
+    def __init__(self, M, nlon, nlat, a=6.37122e6, extended=False):
         if nlat < M + 1 or nlon < 2 * M + 1:
             raise ValueError("grid too small for truncation M")
-        self.M, self.nlon, self.nlat, self.a = M, nlon, nlat, float(a)
-        self.mu, self.w = gauss_nodes(nlat)
-        self.coslat2 = 1.0 - self.mu * self.mu
+        self.rdt = np.longdouble if extended else np.float64
+        self.cdt = np.clongdouble if extended else np.complex128
+        self.M, self.nlon, self.nlat = M, nlon, nlat
+        self.a = self.rdt(a)
+        self.mu, self.w, self.coslat2 = gauss_nodes(nlat, with_coslat2=True, extended=extended)
         self.lam = 2.0 * np.pi * np.arange(nlon) / nlon
         # Pbar for n <= M+1 (the vector transforms need one extra degree)
-        self.P = pbar_table(M + 1, self.mu)
+        self.P = pbar_table(M + 1, self.mu, self.coslat2)
         self.H = hbar_table(self.P, self.mu, M + 1)   # n = m..M
         self.nc = ncoef(M)
         self.n_of = np.zeros(self.nc, dtype=np.int64)
@@ -149,15 +160,15 @@ class Grid:
             sl = m_slice(M, m)
             self.m_of[sl] = m
             self.n_of[sl] = np.arange(m, M + 1)
-        nn = self.n_of.astype(np.float64)
+        nn = self.n_of.astype(self.rdt)
         self.lap = -nn * (nn + 1.0) / self.a ** 2          # Laplacian eigenvalue
-        self.invlap = np.zeros(self.nc)
+        self.invlap = np.zeros(self.nc, dtype=self.rdt)
         self.invlap[nn > 0] = 1.0 / self.lap[nn > 0]
 
     # ---- Fourier (longitude) part -------------------------------------
     def fourier_to_grid(self, fhat):
         """fhat[..., j, m] (m = 0..M) -> real grid [..., j, k]."""
-        spec = np.zeros(fhat.shape[:-1] + (self.nlon // 2 + 1,), dtype=np.complex128)
+        spec = np.zeros(fhat.shape[:-1] + (self.nlon // 2 + 1,), dtype=self.cdt)
         spec[..., :self.M + 1] = fhat
         return self.nlon * np.fft.irfft(spec, n=self.nlon, axis=-1)
 
@@ -169,7 +180,7 @@ class Grid:
     def legendre_synth(self, c, table=None):
         """packed coefficients c[ncoef] -> Fourier coefficients [nlat, M+1]."""
         table = self.P if table is None else table
-        out = np.zeros((self.nlat, self.M + 1), dtype=np.complex128)
+        out = np.zeros((self.nlat, self.M + 1), dtype=self.cdt)
         for m in range(self.M + 1):
             K = self.M - m + 1
             out[:, m] = c[m_slice(self.M, m)] @ table[m][:K]
@@ -180,7 +191,7 @@ class Grid:
         s_{m,n} = 1/2 sum_j wq_j T_n^m(mu_j) fhat_m(mu_j), wq = w (default)."""
         table = self.P if table is None else table
         wq = self.w if weight is None else weight
-        out = np.zeros(self.nc, dtype=np.complex128)
+        out = np.zeros(self.nc, dtype=self.cdt)
         for m in range(self.M + 1):
             K = self.M - m + 1
             out[m_slice(self.M, m)] = 0.5 * (table[m][:K] @ (wq * fhat[:, m]))
@@ -195,7 +206,7 @@ class Grid:
 
     def im(self):
         """i*m for every packed coefficient (longitude derivative)."""
-        return 1j * self.m_of.astype(np.float64)
+        return 1j * self.m_of.astype(self.rdt)
 
     # ---- vector transforms (integration by parts in mu) ----------------
     def div_curl_from_fourier(self, A_hat, B_hat):
@@ -206,8 +217,8 @@ class Grid:
         curl_{m,n} = 1/(2a) sum_j w_j/(1-mu_j^2) [ i m B_m Pbar_n + A_m Hbar_n ]
         """
         wq = self.w / self.coslat2
-        div = np.zeros(self.nc, dtype=np.complex128)
-        curl = np.zeros(self.nc, dtype=np.complex128)
+        div = np.zeros(self.nc, dtype=self.cdt)
+        curl = np.zeros(self.nc, dtype=self.cdt)
         for m in range(self.M + 1):
             K = self.M - m + 1
             P = self.P[m][:K]

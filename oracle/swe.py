@@ -54,10 +54,13 @@ class Model:
     """Planet constants, grid and operators for one truncation."""
 
     def __init__(self, M, nlon, nlat, a=6.37122e6, omega=7.292e-5, g=9.80616,
-                 phibar=2.94e4):
-        self.grid = Grid(M, nlon, nlat, a)
-        self.M, self.a, self.omega, self.g = M, float(a), float(omega), float(g)
-        self.phibar = float(phibar)
+                 phibar=2.94e4, extended=False):
+        """``extended`` evaluates the tendencies in x87 extended precision; it
+        only serves to measure the rounding floor of the float64 path."""
+        self.grid = Grid(M, nlon, nlat, a, extended=extended)
+        rdt = self.grid.rdt
+        self.M, self.a, self.omega, self.g = M, rdt(a), rdt(omega), rdt(g)
+        self.phibar = rdt(phibar)
         self._galerkin = None
         self._lu_cache = {}
 

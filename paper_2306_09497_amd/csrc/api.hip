@@ -1,0 +1,386 @@
+// Public C entry points, the batched IMEX propagator and the PinT drivers.
+#include <chrono>
+#include <math.h>
+#include <string.h>
+
+#include "pint_internal.h"
+
+namespace pint {
+
+#define PINT_TRY(x)                  \
+  do {                               \
+    pint_status st_ = (x);           \
+    if (st_ != PINT_OK) return st_;  \
+  } while (0)
+
+static pint_status check_stepper(const Plan& p, const pint_stepper* st) {
+  if (!st) {
+    set_error("null stepper");
+    return PINT_E_INVAL;
+  }
+  if (!(st->dt > 0.0) || !isfinite(st->dt)) {
+    set_error("stepper dt must be positive and finite (got %g)", st->dt);
+    return PINT_E_INVAL;
+  }
+  if ((st->terms & PINT_T_VISC) && st->visc_nu > 0.0 &&
+      (st->visc_order < 2 || (st->visc_order & 1) || st->visc_order > 16)) {
+    set_error("viscosity order q must be even, 2 <= q <= 16 (got %d)", st->visc_order);
+    return PINT_E_INVAL;
+  }
+  if (!(st->visc_nu >= 0.0) || !isfinite(st->visc_nu)) {
+    set_error("viscosity coefficient must be >= 0 and finite");
+    return PINT_E_INVAL;
+  }
+  if (st->terms & ~15u) {
+    set_error("unknown bits in terms mask 0x%x", st->terms);
+    return PINT_E_INVAL;
+  }
+  (void)p;
+  return PINT_OK;
+}
+
+// nsteps IMEX steps (Sec. 2.3.1, eq. IMEX) on a work-layout batch uw (in/out):
+//   Ua = CN(U); Ub = Ua + dt N(Ua); Ub = Ua + dt/2 (N(Ua) + N(Ub)); U = D_nu CN(Ub)
+pint_status imex_steps(Plan& p, const pint_stepper& st, double* uw, int B, int nsteps,
+                       hipStream_t s) {
+  const CnFactors* f = nullptr;
+  PINT_TRY(cn_factors(p, st.dt, st.terms, s, &f));
+  const bool nl = (st.terms & PINT_T_NL) != 0;
+  for (int k = 0; k < nsteps; ++k) {
+    PINT_TRY(cn_apply(p, *f, st.dt, st.terms & ~PINT_T_VISC, st.visc_order, 0.0, uw, p.Ua, B, s));
+    const double* uc = p.Ua;
+    if (nl) {
+      PINT_TRY(nl_eval(p, p.Ua, p.Ub, p.Ua, p.N1, st.dt, 1, B, s));
+      PINT_TRY(nl_eval(p, p.Ub, p.Ub, p.Ua, p.N1, st.dt, 2, B, s));
+      uc = p.Ub;
+    }
+    PINT_TRY(cn_apply(p, *f, st.dt, st.terms, st.visc_order, st.visc_nu, uc, uw, B, s));
+  }
+  return PINT_OK;
+}
+
+// Propagate B public-layout states by nsteps, in chunks of max_batch.
+static pint_status propagate(Plan& p, const pint_stepper& st, const double* in, double* out,
+                             int B, int nsteps, hipStream_t s) {
+  const size_t sd = (size_t)3 * p.ncoef * 2;
+  for (int b0 = 0; b0 < B; b0 += p.max_batch) {
+    const int nb = (B - b0) < p.max_batch ? (B - b0) : p.max_batch;
+    PINT_TRY(to_work(p, in + b0 * sd, p.Uw, nb, s));
+    PINT_TRY(imex_steps(p, st, p.Uw, nb, nsteps, s));
+    PINT_TRY(from_work(p, p.Uw, out + b0 * sd, nb, s));
+  }
+  return PINT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// PinT drivers.  States are public layout, one per slice boundary.
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  double* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  pint_status alloc(size_t n) {
+    if (hipMalloc(&p, n * sizeof(double)) != hipSuccess) {
+      set_error("hipMalloc(%zu bytes) failed in pint_solve", n * sizeof(double));
+      return PINT_E_NOMEM;
+    }
+    return PINT_OK;
+  }
+};
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+static pint_status check_params(const Plan& p, const pint_pint_params* q) {
+  if (!q) {
+    set_error("null params");
+    return PINT_E_INVAL;
+  }
+  PINT_TRY(check_stepper(p, &q->fine));
+  PINT_TRY(check_stepper(p, &q->coarse));
+  if (q->method != 0 && q->method != 1) {
+    set_error("method must be 0 (Parareal) or 1 (MGRIT)");
+    return PINT_E_INVAL;
+  }
+  if (q->n_intervals < 1 || q->fine_steps < 1 || q->coarse_steps < 1 || q->max_iter < 0 ||
+      q->max_iter > 128 || q->nrelax < 0 || q->nrelax > 8 || !(q->tol >= 0.0) ||
+      (q->resume != 0 && q->resume != 1)) {
+    set_error("need n_intervals, fine_steps, coarse_steps >= 1, 0 <= max_iter <= 128, "
+              "0 <= nrelax <= 8, tol >= 0, resume in {0, 1}");
+    return PINT_E_INVAL;
+  }
+  const double DTf = q->fine.dt * q->fine_steps, DTc = q->coarse.dt * q->coarse_steps;
+  if (fabs(DTf - DTc) > 1e-9 * DTf) {
+    set_error("fine (%g s) and coarse (%g s) propagators must span the same interval", DTf, DTc);
+    return PINT_E_INVAL;
+  }
+  return PINT_OK;
+}
+
+static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, double* U,
+                         pint_report* rep, hipStream_t s) {
+  PINT_TRY(check_params(p, q));
+  const int N = q->n_intervals;
+  const size_t sd = (size_t)3 * p.ncoef * 2;
+  const size_t sb = sd * sizeof(double);
+  pint_report local;
+  pint_report* r = rep ? rep : &local;
+  memset(r, 0, sizeof *r);
+  DevBuf Gold, Fv, Uprev, Gtmp;
+  PINT_TRY(Gold.alloc(sd * N));
+  PINT_TRY(Fv.alloc(sd * N));
+  PINT_TRY(Uprev.alloc(sd * (N + 1)));
+  PINT_TRY(Gtmp.alloc(sd));
+  std::vector<double> incr((size_t)N * 4);
+
+  const bool mgrit = q->method == 1;
+  const int nrelax = mgrit ? q->nrelax : 0;
+  if (q->resume) {
+    // continue from the iterate held in U; the coarse values of its slice
+    // starts are recomputed (bitwise what the previous sweep produced)
+    if (nrelax == 0) {
+      PINT_TRY(propagate(p, q->coarse, U, Gold.p, N, q->coarse_steps, s));
+      r->coarse_steps += (long long)N * q->coarse_steps;
+    }
+  } else {
+    if (U != u0) PINT_HIP(hipMemcpyAsync(U, u0, sb, hipMemcpyDeviceToDevice, s));
+    // iteration 0: serial coarse sweep, G_n = phi_c(U_n), U_{n+1} = G_n
+    for (int n = 0; n < N; ++n) {
+      PINT_TRY(propagate(p, q->coarse, U + n * sd, Gold.p + n * sd, 1, q->coarse_steps, s));
+      PINT_HIP(hipMemcpyAsync(U + (n + 1) * sd, Gold.p + n * sd, sb, hipMemcpyDeviceToDevice, s));
+      r->coarse_steps += q->coarse_steps;
+    }
+  }
+  pint_status result = PINT_OK;
+  for (int k = 0; k < q->max_iter; ++k) {
+    const double t0 = now_s();
+    // slices before `first` are already exact (Parareal); MGRIT recomputes all
+    const int first = (mgrit || q->resume) ? 0 : (k < N ? k : N);
+    if (first >= N) break;
+    PINT_HIP(hipMemcpyAsync(Uprev.p, U, sb * (N + 1), hipMemcpyDeviceToDevice, s));
+    const double* src = U;   // C-points the fine propagation starts from
+    if (nrelax > 0) {
+      // F(CF)^nu: each CF pass replaces C-point i+1 by Phi_0^m of C-point i
+      for (int it = 0; it < nrelax; ++it) {
+        PINT_TRY(propagate(p, q->fine, U, Fv.p, N, q->fine_steps, s));
+        PINT_HIP(hipMemcpyAsync(U + sd, Fv.p, sb * N, hipMemcpyDeviceToDevice, s));
+        r->fine_slice_steps += (long long)N * q->fine_steps;
+      }
+      // coarse values of the relaxed C-points, Phi_1(v_i)
+      PINT_TRY(propagate(p, q->coarse, U, Gold.p, N, q->coarse_steps, s));
+      r->coarse_steps += (long long)N * q->coarse_steps;
+    }
+    // fine propagation of every active slice (the parallel part)
+    PINT_TRY(propagate(p, q->fine, src + first * sd, Fv.p + first * sd, N - first, q->fine_steps,
+                       s));
+    r->fine_slice_steps += (long long)(N - first) * q->fine_steps;
+    // serial correction sweep: U_{n+1} = (G(U_n^new) - G(U_n^old)) + F(U_n^old)
+    for (int n = first; n < N; ++n) {
+      const double* gnew = Gold.p + n * sd;          // unchanged input at n == first
+      if (n > first) {
+        PINT_TRY(propagate(p, q->coarse, U + n * sd, Gtmp.p, 1, q->coarse_steps, s));
+        r->coarse_steps += q->coarse_steps;
+        gnew = Gtmp.p;
+      }
+      PINT_TRY(pr_update(p, gnew, Gold.p + n * sd, Fv.p + n * sd, U + (n + 1) * sd, sd, s));
+      if (n > first)
+        PINT_HIP(hipMemcpyAsync(Gold.p + n * sd, Gtmp.p, sb, hipMemcpyDeviceToDevice, s));
+    }
+    // increments (synchronises)
+    PINT_TRY(rel_diff(p, U + sd, Uprev.p + sd, incr.data(), N, s));
+    // stopping measure: Phi' and the wind (entries 0 and 3 of each slice)
+    double worst = 0.0;
+    bool bad = false;
+    for (int n = 0; n < N; ++n) {
+      for (int f = 0; f < 4; ++f) {
+        const double v = incr[(size_t)n * 4 + f];
+        if (!isfinite(v)) bad = true;
+        else if ((f == 0 || f == 3) && v > worst) worst = v;
+      }
+    }
+    r->incr[k] = bad ? NAN : worst;
+    r->seconds[k] = now_s() - t0;
+    r->iters = k + 1;
+    if (bad || worst > 1e6) {
+      set_error("PinT iteration %d diverged (increment %g)", k, worst);
+      return PINT_E_DIVERGED;
+    }
+    if (q->tol > 0.0 && worst <= q->tol) return PINT_OK;
+  }
+  if (q->tol > 0.0 && r->iters > 0 && r->incr[r->iters - 1] > q->tol) {
+    set_error("tolerance %g not reached in %d iterations (last increment %g)", q->tol, r->iters,
+              r->incr[r->iters - 1]);
+    result = PINT_E_NOTCONV;
+  }
+  return result;
+}
+
+}  // namespace pint
+
+using namespace pint;
+
+#define API_GUARD(plan)                         \
+  if (!(plan)) {                                \
+    set_error("null plan");                     \
+    return PINT_E_INVAL;                        \
+  }
+
+static pint_status check_batch(int B, const void* a, const void* b) {
+  if (B < 0) {
+    set_error("batch must be >= 0");
+    return PINT_E_INVAL;
+  }
+  if (B > 0 && (!a || !b)) {
+    set_error("null array");
+    return PINT_E_INVAL;
+  }
+  return PINT_OK;
+}
+
+extern "C" {
+
+pint_status pint_plan_create(const pint_config* cfg, void* stream, pint_plan** out) {
+  return create(cfg, (hipStream_t)stream, out);
+}
+
+pint_status pint_plan_destroy(pint_plan* plan) {
+  API_GUARD(plan);
+  destroy(plan);
+  return PINT_OK;
+}
+
+pint_status pint_plan_info(const pint_plan* plan, pint_info* info) {
+  API_GUARD(plan);
+  if (!info) {
+    set_error("null info");
+    return PINT_E_INVAL;
+  }
+  const Plan& p = plan->p;
+  info->M = p.M;
+  info->nlon = p.nlon;
+  info->nlat = p.nlat;
+  info->ncoef = p.ncoef;
+  info->max_batch = p.max_batch;
+  info->state_doubles = (size_t)3 * p.ncoef * 2;
+  info->workspace_bytes = p.ws_bytes;
+  return PINT_OK;
+}
+
+pint_status pint_grid_coords(pint_plan* plan, double* mu, double* w, void* stream) {
+  API_GUARD(plan);
+  if (!mu || !w) {
+    set_error("null output");
+    return PINT_E_INVAL;
+  }
+  Plan& p = plan->p;
+  hipStream_t s = (hipStream_t)stream;
+  PINT_HIP(hipMemcpyAsync(mu, p.mu, p.nlat * sizeof(double), hipMemcpyDeviceToHost, s));
+  PINT_HIP(hipMemcpyAsync(w, p.w, p.nlat * sizeof(double), hipMemcpyDeviceToHost, s));
+  PINT_HIP(hipStreamSynchronize(s));
+  return PINT_OK;
+}
+
+pint_status pint_synthesis(pint_plan* plan, const double* spec, double* grid, int B, void* stream) {
+  API_GUARD(plan);
+  PINT_TRY(check_batch(B, spec, grid));
+  if (B == 0) return PINT_OK;
+  return scalar_synthesis(plan->p, spec, grid, B, (hipStream_t)stream);
+}
+
+pint_status pint_analysis(pint_plan* plan, const double* grid, double* spec, int B, void* stream) {
+  API_GUARD(plan);
+  PINT_TRY(check_batch(B, spec, grid));
+  if (B == 0) return PINT_OK;
+  return scalar_analysis(plan->p, grid, spec, B, (hipStream_t)stream);
+}
+
+pint_status pint_tendency(pint_plan* plan, const double* u, double* n_out, int B, void* stream) {
+  API_GUARD(plan);
+  PINT_TRY(check_batch(B, u, n_out));
+  Plan& p = plan->p;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t sd = (size_t)3 * p.ncoef * 2;
+  for (int b0 = 0; b0 < B; b0 += p.max_batch) {
+    const int nb = (B - b0) < p.max_batch ? (B - b0) : p.max_batch;
+    PINT_TRY(to_work(p, u + b0 * sd, p.Uw, nb, s));
+    PINT_TRY(nl_eval(p, p.Uw, p.Ua, nullptr, nullptr, 0.0, 0, nb, s));
+    PINT_TRY(from_work(p, p.Ua, n_out + b0 * sd, nb, s));
+  }
+  return PINT_OK;
+}
+
+pint_status pint_implicit(pint_plan* plan, const pint_stepper* st, const double* u, double* x,
+                          int B, void* stream) {
+  API_GUARD(plan);
+  PINT_TRY(check_batch(B, u, x));
+  Plan& p = plan->p;
+  PINT_TRY(check_stepper(p, st));
+  hipStream_t s = (hipStream_t)stream;
+  const CnFactors* f = nullptr;
+  PINT_TRY(cn_factors(p, st->dt, st->terms, s, &f));
+  const size_t sd = (size_t)3 * p.ncoef * 2;
+  for (int b0 = 0; b0 < B; b0 += p.max_batch) {
+    const int nb = (B - b0) < p.max_batch ? (B - b0) : p.max_batch;
+    PINT_TRY(to_work(p, u + b0 * sd, p.Uw, nb, s));
+    PINT_TRY(cn_apply(p, *f, st->dt, st->terms, st->visc_order, st->visc_nu, p.Uw, p.Ua, nb, s));
+    PINT_TRY(from_work(p, p.Ua, x + b0 * sd, nb, s));
+  }
+  return PINT_OK;
+}
+
+pint_status pint_step(pint_plan* plan, const pint_stepper* st, const double* u_in, double* u_out,
+                      int B, int nsteps, void* stream) {
+  API_GUARD(plan);
+  PINT_TRY(check_batch(B, u_in, u_out));
+  PINT_TRY(check_stepper(plan->p, st));
+  if (nsteps < 0) {
+    set_error("nsteps must be >= 0");
+    return PINT_E_INVAL;
+  }
+  return propagate(plan->p, *st, u_in, u_out, B, nsteps, (hipStream_t)stream);
+}
+
+pint_status pint_solve(pint_plan* plan, const pint_pint_params* prm, const double* u0,
+                       double* u_slices, pint_report* report, void* stream) {
+  API_GUARD(plan);
+  if (!u0 || !u_slices) {
+    set_error("null state array");
+    return PINT_E_INVAL;
+  }
+  return solve(plan->p, prm, u0, u_slices, report, (hipStream_t)stream);
+}
+
+pint_status pint_rel_diff(pint_plan* plan, const double* a, const double* c, double* out_host,
+                          int B, void* stream) {
+  API_GUARD(plan);
+  PINT_TRY(check_batch(B, a, c));
+  if (!out_host && B > 0) {
+    set_error("null output");
+    return PINT_E_INVAL;
+  }
+  return rel_diff(plan->p, a, c, out_host, B, (hipStream_t)stream);
+}
+
+pint_status pint_profile_enable(pint_plan* plan, unsigned kind_mask, int min_batch) {
+  API_GUARD(plan);
+  plan->p.prof_on = kind_mask != 0;
+  plan->p.prof_mask = kind_mask;
+  plan->p.prof_min_batch = min_batch;
+  return PINT_OK;
+}
+
+pint_status pint_profile_read(pint_plan* plan, pint_prof_entry* out, int cap, int* n,
+                              void* stream) {
+  API_GUARD(plan);
+  if (cap < 0) {
+    set_error("cap must be >= 0");
+    return PINT_E_INVAL;
+  }
+  return profile_read(plan->p, out, cap, n, (hipStream_t)stream);
+}
+
+const char* pint_last_error(void) { return last_error(); }
+
+}  // extern "C"

@@ -1,0 +1,228 @@
+// Internal declarations of the MI355X shallow-water propagator library.
+//
+// Index spaces used by the kernels (M = truncation, nlat2 = nlat / 2):
+//  * packed coefficient index  idx(m,n) = m(2M+3-m)/2 + (n-m), n <= M
+//  * "row space": every (m, n) with n <= M+1 (one extra degree needed by the
+//    vector transforms), grouped per zonal wavenumber m and per parity
+//    p = (n-m) mod 2: row = rowoff[2m+p] + (n-m-p)/2.  The Legendre table,
+//    the synthesis inputs and the analysis outputs all live in row space, so
+//    every (m, p) block is one dense GEMM operand.
+//  * work layout of a batch of B states: element (idx, b, field) at
+//    ((idx*B + b)*3 + field) complex, i.e. batch innermost, so that one
+//    (m, n) row of the GEMM operands is contiguous across the batch.
+//  * GEMM column c = (b*nf + f)*2 + reim, nf = 6 fields in synthesis
+//    (xi, delta, Phi', G, U, V) and 4 in analysis (N_Phi, K, A, B).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/pint.h"
+
+namespace pint {
+
+constexpr int kSynFields = 6;
+constexpr int kAnaFields = 4;
+constexpr int kMaxNlon = 1024;
+constexpr int kGemmTR = 64;      // Legendre GEMM tile rows
+constexpr int kGemmTC = 64;      // Legendre GEMM tile columns
+constexpr int kGemmTK = 16;      // Legendre GEMM k-slab staged in LDS
+constexpr int kRingThreads = 512;
+constexpr int kFftMaxBf = 2;     // FFT butterflies per thread per pass
+
+void set_error(const char* fmt, ...);
+
+#define PINT_HIP(call)                                                        \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess) {                                                   \
+      ::pint::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                  \
+      return PINT_E_HIP;                                                      \
+    }                                                                         \
+  } while (0)
+
+struct CnFactors {       // Thomas factors of (I - dt/4 L) for one (dt, terms)
+  double2* lower = nullptr;    // [2 chains][nrows_cn]
+  double2* cprime = nullptr;
+  double2* invpiv = nullptr;
+};
+
+struct GemmTiles {       // (problem, row tile) list of one ragged batched GEMM
+  int* dev = nullptr;    // int2 {problem p = 2m+par, row0} per row tile
+  int count = 0;
+};
+
+enum ProfKind {
+  PK_PREP = 0, PK_SYNTH, PK_RING, PK_ANAL, PK_ASSEMBLE, PK_CN, PK_LAYOUT, PK_PINT, PK_SRING,
+  PK_COUNT
+};
+
+struct ProfRec {
+  int kind, batch;
+  hipEvent_t a, b;
+};
+
+struct Plan {
+  int M, nlon, nlat, nlat2, ncoef, nrows, max_batch;
+  double a, omega, g, phibar;
+  // device tables
+  double* mu = nullptr;        // [nlat] north to south
+  double* w = nullptr;         // [nlat]
+  double* c2 = nullptr;        // [nlat] 1 - mu^2 (= sin^2 colatitude)
+  double* ptab = nullptr;      // [nrows][nlat2] Pbar_n^m(mu_j), north half
+  int* rowoff = nullptr;       // [2(M+1)+1] device copy
+  int* rowinfo = nullptr;      // [nrows] packed (m << 16 | n)
+  int* coefmn = nullptr;       // [ncoef] packed (m << 16 | n)
+  double2* twid = nullptr;     // [nlon] exp(-2 pi i t / nlon)
+  double4* cnco = nullptr;     // [ncoef] linear-operator coefficients (A/W, B/W, C/W, n(n+1)/a^2)
+  std::vector<int> h_rowoff;   // host copy
+  int nradix = 0;
+  int radix[16];
+  GemmTiles syn_tiles, ana_tiles;
+  // workspace (sized for max_batch)
+  double* S = nullptr;         // [nrows][12 B]   synthesis GEMM input
+  double* F = nullptr;         // [2(M+1) nlat2][12 B] synthesis output (E/O)
+  double* G = nullptr;         // [(M+1) nlat][8 B] ring output
+  double* Q = nullptr;         // [nrows][8 B]    analysis output
+  double* Uw = nullptr;        // work-layout states, 5 buffers of [ncoef][B][3] complex
+  double* Ua = nullptr;
+  double* Ub = nullptr;
+  double* N1 = nullptr;
+  double* T0 = nullptr;
+  double* red = nullptr;       // reduction scratch
+  double* h_red = nullptr;     // pinned host mirror
+  size_t ws_bytes = 0;
+  std::map<std::pair<double, unsigned>, CnFactors> cn_cache;
+  // kernel timing (pint_profile_enable)
+  bool prof_on = false;
+  unsigned prof_mask = 0;
+  int prof_min_batch = 0;
+  std::vector<ProfRec> prof;       // launches recorded since the last read
+  std::vector<hipEvent_t> ev_pool; // reusable events
+  size_t prof_used = 0;
+};
+
+// Bracket one kernel launch with events when profiling is enabled.
+int prof_begin(Plan& p, int kind, int batch, hipStream_t s);
+pint_status profile_read(Plan& p, pint_prof_entry* out, int cap, int* n, hipStream_t s);
+void prof_end(Plan& p, int rec, hipStream_t s);
+
+struct ProfScope {
+  Plan& p;
+  hipStream_t s;
+  int rec;
+  ProfScope(Plan& pl, int kind, int batch, hipStream_t st) : p(pl), s(st) {
+    const int nb = batch < 0 ? -batch : batch;
+    rec = (pl.prof_on && ((pl.prof_mask >> kind) & 1u) && nb >= pl.prof_min_batch)
+              ? prof_begin(pl, kind, batch, st)
+              : -1;
+  }
+  ~ProfScope() {
+    if (rec >= 0) prof_end(p, rec, s);
+  }
+};
+
+const char* last_error();
+pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out);
+void destroy(pint_plan* pp);
+
+// ---- kernels / launchers (each returns PINT_OK or an error) ----
+pint_status build_tables(Plan& p, hipStream_t s);
+pint_status cn_factors(Plan& p, double dt, unsigned terms, hipStream_t s, const CnFactors** out);
+
+// layout conversion: public [B][3][ncoef] <-> work [ncoef][B][3] (complex)
+pint_status to_work(Plan& p, const double* pub, double* work, int B, hipStream_t s);
+pint_status from_work(Plan& p, const double* work, double* pub, int B, hipStream_t s);
+
+// nonlinear evaluation on work-layout states; stage: 0 = write N to out,
+// 1 = N1 := N, out := ua + dt N, 2 = out := ua + dt/2 (N1 + N)
+pint_status nl_eval(Plan& p, const double* u, double* out, const double* ua, double* n1,
+                    double dt, int stage, int B, hipStream_t s);
+pint_status cn_apply(Plan& p, const CnFactors& f, double dt, unsigned terms, int q, double nu,
+                     const double* y, double* x, int B, hipStream_t s);
+pint_status imex_steps(Plan& p, const pint_stepper& st, double* uw, int B, int nsteps,
+                       hipStream_t s);
+
+// transforms on the GEMM workspace
+pint_status legendre_synth(Plan& p, int B, int nf, hipStream_t s);
+pint_status legendre_anal(Plan& p, int B, int nf, hipStream_t s);
+pint_status ring_tendency(Plan& p, int B, hipStream_t s);
+
+// scalar transforms (public layout)
+pint_status scalar_synthesis(Plan& p, const double* spec, double* grid, int B, hipStream_t s);
+pint_status scalar_analysis(Plan& p, const double* grid, double* spec, int B, hipStream_t s);
+
+// elementwise helpers (public layout, n doubles)
+pint_status pr_update(Plan& p, const double* gnew, const double* gold, const double* f,
+                      double* out, size_t n, hipStream_t s);
+pint_status rel_diff(Plan& p, const double* a, const double* c, double* out_host, int B,
+                     hipStream_t s);
+
+inline __host__ __device__ int coef_idx(int M, int m, int n) {
+  return m * (2 * M + 3 - m) / 2 + (n - m);
+}
+
+// ---- small device helpers shared by the kernels ----
+// Workgroups are dispatched round-robin over the 8 XCDs (block L on XCD L mod
+// 8), each with its own L2.  Remap the hardware block index so that every XCD
+// works through one contiguous range of logical blocks: logically adjacent
+// blocks (which share operand rows) then share an L2.
+constexpr int kNumXcd = 8;
+__device__ inline int xcd_remap(int L, int T) {
+  const int q = T / kNumXcd, r = T % kNumXcd;
+  const int x = L % kNumXcd, i = L / kNumXcd;
+  return x * q + (x < r ? x : r) + i;
+}
+
+__device__ inline double2 cmul(double2 x, double2 y) {
+  return make_double2(x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x);
+}
+__device__ inline double2 cinv(double2 x) {
+  const double d = x.x * x.x + x.y * x.y;
+  return make_double2(x.x / d, -x.y / d);
+}
+
+// eps_n^m = sqrt((n^2 - m^2) / (4 n^2 - 1)), zero for n <= m
+__device__ inline double eps_nm(int n, int m) {
+  if (n <= m) return 0.0;
+  return sqrt(((double)n * n - (double)m * m) / (4.0 * n * n - 1.0));
+}
+
+// inverse-Laplacian factor: psi_k = s_k xi_k, s_k = -a^2/(k(k+1)), s_0 = 0
+__device__ inline double s_of(int k, double a) {
+  return k > 0 ? -a * a / ((double)k * (k + 1)) : 0.0;
+}
+
+
+// Coefficients of the linear operator in the per-m chain form (see cn_factors).
+struct CnCoef {
+  double A, B, C, lap;
+};
+
+__device__ inline CnCoef cn_coef(int m, int n, int M, double a, double W, bool lg) {
+  CnCoef c;
+  const double Wa = W / (a * a);
+  const double en = eps_nm(n, m);
+  c.A = -W * en + Wa * (n - 1) * en * s_of(n - 1, a);
+  c.B = -Wa * m * s_of(n, a);
+  if (n < M) {
+    const double e1 = eps_nm(n + 1, m);
+    c.C = -W * e1 - Wa * (n + 2) * e1 * s_of(n + 1, a);
+  } else {
+    c.C = 0.0;
+  }
+  c.lap = lg ? (double)n * (n + 1) / (a * a) : 0.0;
+  return c;
+}
+
+}  // namespace pint
+
+struct pint_plan {
+  pint::Plan p;
+};

@@ -1,0 +1,239 @@
+"""ctypes binding of libpint.so (the C ABI in include/pint.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device arrays are torch tensors (float64, contiguous, on the GPU);
+complex coefficients are stored as (re, im) pairs, so a batch of B states is a
+float64 tensor of shape (B, 3, ncoef, 2) (or any tensor with that many
+elements).  The library must have been built (``python -m
+paper_2306_09497_amd.build``); importing this module without it raises.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpint.so")
+
+T_LG, T_LC, T_NL, T_VISC, T_ALL = 1, 2, 4, 8, 15
+PARAREAL, MGRIT = 0, 1
+
+STATUS = {0: "PINT_OK", -1: "PINT_E_INVAL", -2: "PINT_E_NOMEM", -3: "PINT_E_HIP",
+          -4: "PINT_E_DIVERGED", -5: "PINT_E_NOTCONV"}
+
+EXPORTS = ["pint_plan_create", "pint_plan_destroy", "pint_plan_info", "pint_grid_coords",
+           "pint_synthesis", "pint_analysis", "pint_tendency", "pint_implicit", "pint_step",
+           "pint_solve", "pint_rel_diff", "pint_profile_enable", "pint_profile_read",
+           "pint_last_error"]
+
+PROF_KINDS = ["prep", "legendre_synth", "ring_tendency", "legendre_anal", "assemble_rk",
+              "cn_solve", "layout", "pint_ops", "scalar_ring"]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int), ("nlon", ctypes.c_int), ("nlat", ctypes.c_int),
+                ("a", ctypes.c_double), ("omega", ctypes.c_double), ("g", ctypes.c_double),
+                ("phibar", ctypes.c_double), ("max_batch", ctypes.c_int)]
+
+
+class Stepper(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("visc_order", ctypes.c_int),
+                ("visc_nu", ctypes.c_double), ("terms", ctypes.c_uint)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int), ("nlon", ctypes.c_int), ("nlat", ctypes.c_int),
+                ("ncoef", ctypes.c_int), ("max_batch", ctypes.c_int),
+                ("state_doubles", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t)]
+
+
+class PintParams(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int), ("n_intervals", ctypes.c_int),
+                ("fine", Stepper), ("fine_steps", ctypes.c_int),
+                ("coarse", Stepper), ("coarse_steps", ctypes.c_int),
+                ("nrelax", ctypes.c_int), ("max_iter", ctypes.c_int), ("tol", ctypes.c_double),
+                ("resume", ctypes.c_int)]
+
+
+class ProfEntry(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("batch", ctypes.c_int),
+                ("launches", ctypes.c_longlong), ("total_ms", ctypes.c_double)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("incr", ctypes.c_double * 128),
+                ("seconds", ctypes.c_double * 128), ("fine_slice_steps", ctypes.c_longlong),
+                ("coarse_steps", ctypes.c_longlong)]
+
+
+class PintError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libpint.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not built: run python -m paper_2306_09497_amd.build")
+    # torch ships its own HIP runtime; load it first so that libpint binds to
+    # the same libamdhip64 instance (one runtime per process).
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+    lib.pint_plan_create.argtypes = [ctypes.POINTER(Config), vp, ctypes.POINTER(vp)]
+    lib.pint_plan_destroy.argtypes = [vp]
+    lib.pint_plan_info.argtypes = [vp, ctypes.POINTER(Info)]
+    lib.pint_grid_coords.argtypes = [vp, dp, dp, vp]
+    lib.pint_synthesis.argtypes = [vp, vp, vp, ip, vp]
+    lib.pint_analysis.argtypes = [vp, vp, vp, ip, vp]
+    lib.pint_tendency.argtypes = [vp, vp, vp, ip, vp]
+    lib.pint_implicit.argtypes = [vp, ctypes.POINTER(Stepper), vp, vp, ip, vp]
+    lib.pint_step.argtypes = [vp, ctypes.POINTER(Stepper), vp, vp, ip, ip, vp]
+    lib.pint_solve.argtypes = [vp, ctypes.POINTER(PintParams), vp, vp, ctypes.POINTER(Report), vp]
+    lib.pint_rel_diff.argtypes = [vp, vp, vp, dp, ip, vp]
+    lib.pint_profile_enable.argtypes = [vp, ctypes.c_uint, ip]
+    lib.pint_profile_read.argtypes = [vp, ctypes.POINTER(ProfEntry), ip,
+                                      ctypes.POINTER(ctypes.c_int), vp]
+    lib.pint_last_error.argtypes = []
+    lib.pint_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS[:-1]:
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != 0:
+        msg = _lib.pint_last_error().decode(errors="replace")
+        raise PintError(status, msg)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError("device arrays must be contiguous float64 CUDA/HIP tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def stepper(dt, visc_order=2, visc_nu=0.0, terms=T_ALL):
+    return Stepper(float(dt), int(visc_order), float(visc_nu), int(terms))
+
+
+class Plan:
+    """A truncation / grid / planet and the device tables and workspace."""
+
+    def __init__(self, M, nlon, nlat, a=6.37122e6, omega=7.292e-5, g=9.80616,
+                 phibar=2.94e4, max_batch=64, stream=None):
+        lib = load()
+        self.cfg = Config(M, nlon, nlat, a, omega, g, phibar, max_batch)
+        h = ctypes.c_void_p()
+        _check(lib.pint_plan_create(ctypes.byref(self.cfg), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        info = Info()
+        _check(lib.pint_plan_info(h, ctypes.byref(info)))
+        self.M, self.nlon, self.nlat, self.ncoef = M, nlon, nlat, info.ncoef
+        self.max_batch = info.max_batch
+        self.workspace_bytes = info.workspace_bytes
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pint_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- helpers ------------------------------------------------------
+    def state_numel(self, B=1):
+        return B * 3 * self.ncoef * 2
+
+    def grid_coords(self, stream=None):
+        import numpy as np
+        mu = np.zeros(self.nlat)
+        w = np.zeros(self.nlat)
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(load().pint_grid_coords(self._h, mu.ctypes.data_as(dp), w.ctypes.data_as(dp),
+                                       _stream(stream)))
+        return mu, w
+
+    # ---- entry points -------------------------------------------------
+    def synthesis(self, spec, grid, B, stream=None):
+        _check(load().pint_synthesis(self._h, _ptr(spec), _ptr(grid), int(B), _stream(stream)))
+
+    def analysis(self, grid, spec, B, stream=None):
+        _check(load().pint_analysis(self._h, _ptr(grid), _ptr(spec), int(B), _stream(stream)))
+
+    def tendency(self, u, out, B, stream=None):
+        _check(load().pint_tendency(self._h, _ptr(u), _ptr(out), int(B), _stream(stream)))
+
+    def implicit(self, st, u, x, B, stream=None):
+        _check(load().pint_implicit(self._h, ctypes.byref(st), _ptr(u), _ptr(x), int(B),
+                                    _stream(stream)))
+
+    def step(self, st, u_in, u_out, B, nsteps, stream=None):
+        _check(load().pint_step(self._h, ctypes.byref(st), _ptr(u_in), _ptr(u_out), int(B),
+                                int(nsteps), _stream(stream)))
+
+    def solve(self, params, u0, u_slices, stream=None):
+        rep = Report()
+        _check(load().pint_solve(self._h, ctypes.byref(params), _ptr(u0), _ptr(u_slices),
+                                 ctypes.byref(rep), _stream(stream)))
+        return rep
+
+    def solve_status(self, params, u0, u_slices, stream=None):
+        """Like solve() but returns (status, report, message) instead of raising."""
+        rep = Report()
+        st = load().pint_solve(self._h, ctypes.byref(params), _ptr(u0), _ptr(u_slices),
+                               ctypes.byref(rep), _stream(stream))
+        msg = load().pint_last_error().decode(errors="replace") if st else ""
+        return st, rep, msg
+
+    def profile(self, kinds=None, min_batch=0):
+        """Time kernel launches of the given kinds (names from PROF_KINDS; None =
+        all, [] = off) processing at least min_batch states."""
+        if kinds is None:
+            mask = (1 << len(PROF_KINDS)) - 1
+        else:
+            mask = 0
+            for k in kinds:
+                mask |= 1 << PROF_KINDS.index(k)
+        _check(load().pint_profile_enable(self._h, mask, int(min_batch)))
+
+    def profile_read(self, stream=None):
+        """{(kind name, batch): (launches, total_ms)} since the last read."""
+        buf = (ProfEntry * 64)()
+        n = ctypes.c_int(0)
+        _check(load().pint_profile_read(self._h, buf, 64, ctypes.byref(n), _stream(stream)))
+        return {(PROF_KINDS[e.kind], e.batch): (e.launches, e.total_ms) for e in buf[:n.value]}
+
+    def rel_diff(self, a, c, B, stream=None):
+        import numpy as np
+        out = np.zeros((B, 4))
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(load().pint_rel_diff(self._h, _ptr(a), _ptr(c), out.ctypes.data_as(dp), int(B),
+                                    _stream(stream)))
+        return out
+
+
+def params(method, n_intervals, fine, fine_steps, coarse, coarse_steps, nrelax=0, max_iter=1,
+           tol=0.0, resume=False):
+    return PintParams(int(method), int(n_intervals), fine, int(fine_steps), coarse,
+                      int(coarse_steps), int(nrelax), int(max_iter), float(tol), int(resume))

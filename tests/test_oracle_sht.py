@@ -145,3 +145,17 @@ def test_solid_body_velocity():
     U, V = g.uv_fourier_from_psichi(psi, np.zeros_like(psi))
     assert np.max(np.abs(U[:, 0] - u0 * (1 - g.mu ** 2))) < 1e-13 * u0
     assert np.max(np.abs(U[:, 1:])) < 1e-13 * u0 and np.max(np.abs(V)) < 1e-13 * u0
+
+
+def test_wind_norm_parseval():
+    """wind_norm^2 equals the area-weighted grid mean of u^2 + v^2."""
+    from oracle.norms import wind_norm
+    M = 21
+    g = sht.Grid(M, 64, 32, A)
+    rng = np.random.default_rng(8)
+    xi, de = rand_spec(M, rng, 1e-5), rand_spec(M, rng, 1e-6)
+    xi[0] = de[0] = 0.0
+    U, V = g.uv_fourier_from_psichi(xi * g.invlap, de * g.invlap)
+    Ug, Vg = g.fourier_to_grid(U), g.fourier_to_grid(V)
+    ms = 0.5 * np.sum(g.w[:, None] * (Ug ** 2 + Vg ** 2) / g.coslat2[:, None]) / g.nlon
+    assert abs(wind_norm(xi, de, M, A) ** 2 - ms) < 1e-12 * ms

@@ -234,3 +234,22 @@ def test_second_order_in_time():
         errs.append(np.max(rel_err(U, ref, 21)))
     ratio = errs[0] / errs[1]
     assert 3.3 < ratio < 4.7, (errs, ratio)
+
+
+def test_float64_rounding_floor_of_divergence_tendency():
+    """The float64 oracle against itself in extended precision: the plain
+    spectral L2 of N_delta carries a rounding floor far above the other fields
+    (the Laplacian of the kinetic energy amplifies rounding by n(n+1)), while
+    the wind norm and Phi' stay near machine precision.  This is why parity
+    of vorticity/divergence is stated in the wind norm."""
+    from oracle.norms import state_rel_err
+    M = 63
+    md, U = jet_state(M, 192, 96)
+    U = workloads.white_noise(M, U, 1e-4, 2)
+    mx = Model(M, 192, 96, phibar=md.phibar, extended=True)
+    N0 = md.tendencies(U)
+    Nx = mx.tendencies(U.astype(np.clongdouble)).astype(np.complex128)
+    plain = rel_err(N0, Nx, M)
+    energy = state_rel_err(N0, Nx, M)
+    assert plain[2] > 5 * energy[1]          # delta is the ill-conditioned field
+    assert np.all(energy < 1e-12) and plain[0] < 1e-13
