@@ -23,19 +23,21 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // latency-bound single-state launches of the serial coarse sweep), k-slabs of
 // TK = 16 double-buffered in LDS: the next slab is fetched into registers
 // while the matrix cores work on the current one, one barrier per slab.
-template <bool kSynth, int TC>
+template <bool kSynth, int TR, int TC>
 __global__ __launch_bounds__(256) void k_legendre(const double* __restrict__ T,
                                                   const int* __restrict__ rowoff,
                                                   const int* __restrict__ tiles,
                                                   const double* __restrict__ Bsrc,
                                                   double* __restrict__ C, int nlat, int nlat2,
                                                   int ncol) {
-  constexpr int TR = kGemmTR, TK = kGemmTK;
+  constexpr int TK = kGemmTK;
   constexpr int LDA = TR + 2, LDB = TC + 2;
+  constexpr int NA = TK * TR / 256;                  // A elements per thread per slab
   constexpr int NB = TK * TC / 256;                  // B elements per thread per slab
   constexpr int WC = TC == 64 ? 2 : 1;               // waves across columns
   constexpr int WR = 4 / WC;                         // waves across rows
   constexpr int BI = TR / WR / 16, BJ = TC / WC / 16;  // MFMA blocks per wave
+  static_assert(BI >= 1 && BJ >= 1 && NA >= 1 && NB >= 1, "tile shape");
   __shared__ double As[2][TK * LDA];
   __shared__ double Bs[2][TK * LDB];
 
@@ -66,18 +68,18 @@ __global__ __launch_bounds__(256) void k_legendre(const double* __restrict__ T,
 #pragma unroll
     for (int j = 0; j < BJ; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
 
-  double ra[4], rb[NB];
+  double ra[NA], rb[NB];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NA; ++q) {
       const int e = tid + q * 256;
       double v = 0.0;
       if (kSynth) {
-        const int kk = e >> 6, rr = e & 63;
+        const int kk = e / TR, rr = e % TR;
         const int k = k0 + kk, r = row0 + rr;
         if (k < K && r < R) v = T[(size_t)(roff + k) * nlat2 + r];
       } else {
-        const int rr = e >> 4, kk = e & 15;
+        const int rr = e / TK, kk = e % TK;
         const int k = k0 + kk, r = row0 + rr;
         if (k < K && r < R) v = T[(size_t)(roff + r) * nlat2 + k];
       }
@@ -100,12 +102,12 @@ __global__ __launch_bounds__(256) void k_legendre(const double* __restrict__ T,
   };
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NA; ++q) {
       const int e = tid + q * 256;
       if (kSynth)
-        As[buf][(e >> 6) * LDA + (e & 63)] = ra[q];
+        As[buf][(e / TR) * LDA + (e % TR)] = ra[q];
       else
-        As[buf][(e & 15) * LDA + (e >> 4)] = ra[q];
+        As[buf][(e % TK) * LDA + (e / TK)] = ra[q];
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
@@ -158,17 +160,22 @@ __global__ __launch_bounds__(256) void k_legendre(const double* __restrict__ T,
   }
 }
 
+// Synthesis rows are the nlat/2 latitudes (64-row tiles); analysis rows are
+// the ragged n-range of one (m, parity) (32-row tiles waste less of it).
+// Single-state launches use 64 x 16 tiles; batched ones 64 x 64 (synthesis)
+// or 32 x 64 (analysis).  Every shape reduces over k in the same order.
 template <bool kSynth>
-static pint_status launch_legendre(Plan& p, const GemmTiles& tl, const double* Bsrc, double* C,
-                                   int ncol, hipStream_t s) {
+static pint_status launch_legendre(Plan& p, const GemmTiles& narrow, const GemmTiles& wide,
+                                   const double* Bsrc, double* C, int ncol, hipStream_t s) {
+  constexpr int TRW = kSynth ? kGemmTR : kGemmTRAnal;
   if (ncol <= 32) {
-    dim3 grid(((ncol + 15) / 16) * tl.count);
-    hipLaunchKernelGGL((k_legendre<kSynth, 16>), grid, dim3(256), 0, s, p.ptab, p.rowoff, tl.dev,
-                       Bsrc, C, p.nlat, p.nlat2, ncol);
+    dim3 grid(((ncol + 15) / 16) * narrow.count);
+    hipLaunchKernelGGL((k_legendre<kSynth, kGemmTR, 16>), grid, dim3(256), 0, s, p.ptab,
+                       p.rowoff, narrow.dev, Bsrc, C, p.nlat, p.nlat2, ncol);
   } else {
-    dim3 grid(((ncol + 63) / 64) * tl.count);
-    hipLaunchKernelGGL((k_legendre<kSynth, 64>), grid, dim3(256), 0, s, p.ptab, p.rowoff, tl.dev,
-                       Bsrc, C, p.nlat, p.nlat2, ncol);
+    dim3 grid(((ncol + 63) / 64) * wide.count);
+    hipLaunchKernelGGL((k_legendre<kSynth, TRW, 64>), grid, dim3(256), 0, s, p.ptab, p.rowoff,
+                       wide.dev, Bsrc, C, p.nlat, p.nlat2, ncol);
   }
   PINT_HIP(hipGetLastError());
   return PINT_OK;
@@ -176,12 +183,12 @@ static pint_status launch_legendre(Plan& p, const GemmTiles& tl, const double* B
 
 pint_status legendre_synth(Plan& p, int B, int nf, hipStream_t s) {
   ProfScope ps(p, PK_SYNTH, nf == kSynFields ? B : -B, s);
-  return launch_legendre<true>(p, p.syn_tiles, p.S, p.F, 2 * nf * B, s);
+  return launch_legendre<true>(p, p.syn_tiles, p.syn_tiles, p.S, p.F, 2 * nf * B, s);
 }
 
 pint_status legendre_anal(Plan& p, int B, int nf, hipStream_t s) {
   ProfScope ps(p, PK_ANAL, nf == kAnaFields ? B : -B, s);
-  return launch_legendre<false>(p, p.ana_tiles, p.G, p.Q, 2 * nf * B, s);
+  return launch_legendre<false>(p, p.ana_tiles64, p.ana_tiles, p.G, p.Q, 2 * nf * B, s);
 }
 
 }  // namespace pint

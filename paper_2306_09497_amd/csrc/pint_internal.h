@@ -29,11 +29,11 @@ namespace pint {
 constexpr int kSynFields = 6;
 constexpr int kAnaFields = 4;
 constexpr int kMaxNlon = 1024;
-constexpr int kGemmTR = 64;      // Legendre GEMM tile rows
+constexpr int kGemmTR = 64;      // Legendre GEMM tile rows (synthesis)
+constexpr int kGemmTRAnal = 64;  // Legendre GEMM tile rows (analysis)
 constexpr int kGemmTC = 64;      // Legendre GEMM tile columns
 constexpr int kGemmTK = 16;      // Legendre GEMM k-slab staged in LDS
 constexpr int kRingThreads = 512;
-constexpr int kFftMaxBf = 2;     // FFT butterflies per thread per pass
 
 void set_error(const char* fmt, ...);
 
@@ -82,9 +82,7 @@ struct Plan {
   double2* twid = nullptr;     // [nlon] exp(-2 pi i t / nlon)
   double4* cnco = nullptr;     // [ncoef] linear-operator coefficients (A/W, B/W, C/W, n(n+1)/a^2)
   std::vector<int> h_rowoff;   // host copy
-  int nradix = 0;
-  int radix[16];
-  GemmTiles syn_tiles, ana_tiles;
+  GemmTiles syn_tiles, ana_tiles, ana_tiles64;
   // workspace (sized for max_batch)
   double* S = nullptr;         // [nrows][12 B]   synthesis GEMM input
   double* F = nullptr;         // [2(M+1) nlat2][12 B] synthesis output (E/O)
@@ -153,6 +151,9 @@ pint_status imex_steps(Plan& p, const pint_stepper& st, double* uw, int B, int n
 pint_status legendre_synth(Plan& p, int B, int nf, hipStream_t s);
 pint_status legendre_anal(Plan& p, int B, int nf, hipStream_t s);
 pint_status ring_tendency(Plan& p, int B, hipStream_t s);
+bool ring_supported(int nlon);
+size_t ring_lds_bytes(int nlon);
+pint_status ring_prepare(int nlon);
 
 // scalar transforms (public layout)
 pint_status scalar_synthesis(Plan& p, const double* spec, double* grid, int B, hipStream_t s);

@@ -124,16 +124,6 @@ __global__ void k_cn_coef(int M, int ncoef, double a, const int* coefmn, double4
   co[i] = make_double4(c.A, c.B, c.C, c.lap);
 }
 
-static bool radix_plan(int N, int* r, int* nr) {
-  int n = N, k = 0;
-  while (n % 4 == 0) { r[k++] = 4; n /= 4; }
-  while (n % 2 == 0) { r[k++] = 2; n /= 2; }
-  while (n % 3 == 0) { r[k++] = 3; n /= 3; }
-  while (n % 5 == 0) { r[k++] = 5; n /= 5; }
-  *nr = k;
-  return n == 1 && k <= 16;
-}
-
 template <typename T>
 static pint_status dalloc(T** ptr, size_t count, size_t* total) {
   void* v = nullptr;
@@ -156,7 +146,7 @@ static pint_status dalloc(T** ptr, size_t count, size_t* total) {
 
 static void free_plan(Plan& p) {
   void* ptrs[] = {p.mu, p.w, p.c2, p.ptab, p.rowoff, p.rowinfo, p.coefmn, p.twid, p.cnco,
-                  p.syn_tiles.dev, p.ana_tiles.dev, p.S, p.F, p.G, p.Q, p.Uw, p.Ua, p.Ub,
+                  p.syn_tiles.dev, p.ana_tiles.dev, p.ana_tiles64.dev, p.S, p.F, p.G, p.Q, p.Uw, p.Ua, p.Ub,
                   p.N1, p.T0, p.red};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -213,23 +203,31 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
     set_error("pint_plan_create: M too large");
     return PINT_E_INVAL;
   }
-  int rad[16], nr = 0;
-  if (!radix_plan(nlon, rad, &nr)) {
-    set_error("pint_plan_create: nlon=%d must be 2^a 3^b 5^c", nlon);
+  if (!ring_supported(nlon)) {
+    set_error("pint_plan_create: nlon=%d has no compiled ring FFT (supported: 64 96 128 192 "
+              "256 384 512 640 768 1024)", nlon);
     return PINT_E_INVAL;
-  }
-  for (int i = 0; i < nr; ++i) {
-    // ring kernel: 4 signals, 256 threads, at most kFftMaxBf butterflies per thread
-    if (4 * (nlon / rad[i]) > kRingThreads * kFftMaxBf) {
-      set_error("pint_plan_create: nlon=%d needs a radix-%d pass too wide for the ring kernel",
-                nlon, rad[i]);
-      return PINT_E_INVAL;
-    }
   }
   if (!(cfg->a > 0) || !(cfg->phibar >= 0) || cfg->max_batch < 1 || cfg->max_batch > 65535 ||
       !isfinite(cfg->omega) || !isfinite(cfg->g)) {
     set_error("pint_plan_create: need a > 0, phibar >= 0, finite omega/g, 1 <= max_batch <= 65535");
     return PINT_E_INVAL;
+  }
+  {
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+            hipSuccess) {
+      set_error("pint_plan_create: cannot query the device");
+      return PINT_E_HIP;
+    }
+    if (ring_lds_bytes(nlon) > (size_t)lds_max) {
+      set_error("pint_plan_create: nlon=%d needs %zu bytes of LDS per workgroup, device allows %d",
+                nlon, ring_lds_bytes(nlon), lds_max);
+      return PINT_E_INVAL;
+    }
+    pint_status rs = ring_prepare(nlon);
+    if (rs != PINT_OK) return rs;
   }
   pint_plan* pp = new pint_plan();
   Plan& p = pp->p;
@@ -243,8 +241,6 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
   p.g = cfg->g;
   p.phibar = cfg->phibar;
   p.max_batch = cfg->max_batch;
-  p.nradix = nr;
-  memcpy(p.radix, rad, sizeof rad);
 
   // row space
   p.h_rowoff.assign(2 * (M + 1) + 1, 0);
@@ -282,7 +278,8 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
   PLAN_TRY(dalloc(&p.twid, nlon, &tot));
   PLAN_TRY(dalloc(&p.cnco, p.ncoef, &tot));
   PLAN_TRY(build_tiles(p.h_rowoff, M, p.nlat2, true, kGemmTR, &p.syn_tiles, &tot));
-  PLAN_TRY(build_tiles(p.h_rowoff, M, p.nlat2, false, kGemmTR, &p.ana_tiles, &tot));
+  PLAN_TRY(build_tiles(p.h_rowoff, M, p.nlat2, false, kGemmTRAnal, &p.ana_tiles, &tot));
+  PLAN_TRY(build_tiles(p.h_rowoff, M, p.nlat2, false, kGemmTR, &p.ana_tiles64, &tot));
   const size_t B = p.max_batch;
   PLAN_TRY(dalloc(&p.S, (size_t)p.nrows * 12 * B, &tot));
   PLAN_TRY(dalloc(&p.F, (size_t)2 * (M + 1) * p.nlat2 * 12 * B, &tot));

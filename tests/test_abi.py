@@ -1,0 +1,52 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/pint.h declares, and rejects invalid arguments before touching a
+device (no compute calls are made here)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "pint.h")).read()
+    return sorted(set(re.findall(r"\b(pint_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_binding_exports():
+    from paper_2306_09497_amd import pint
+    assert header_functions() == sorted(pint.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2306_09497_amd import pint
+    lib = pint.load()
+    for name in header_functions():
+        assert getattr(lib, name) is not None
+
+
+@pytest.mark.parametrize("cfg,msg", [
+    ((0, 64, 32), "need M >= 1"),
+    ((21, 64, 31), "even nlat"),
+    ((21, 40, 32), "2M+2 <= nlon"),
+    ((21, 66, 34), "no compiled ring FFT"),
+])
+def test_plan_create_rejects(cfg, msg):
+    from paper_2306_09497_amd import pint
+    lib = pint.load()
+    c = pint.Config(cfg[0], cfg[1], cfg[2], 6.37122e6, 7.292e-5, 9.80616, 3e4, 4)
+    h = ctypes.c_void_p()
+    st = lib.pint_plan_create(ctypes.byref(c), None, ctypes.byref(h))
+    assert st == -1 and h.value is None
+    assert msg in lib.pint_last_error().decode()
+
+
+def test_null_arguments():
+    from paper_2306_09497_amd import pint
+    lib = pint.load()
+    assert lib.pint_plan_destroy(None) == -1
+    assert b"null plan" in lib.pint_last_error()
+    assert lib.pint_plan_create(None, None, None) == -1
