@@ -47,9 +47,13 @@ void set_error(const char* fmt, ...);
     }                                                                         \
   } while (0)
 
-struct CnFactors {       // Thomas factors of (I - dt/4 L) for one (dt, terms)
-  double2* lower = nullptr;    // [2 chains][nrows_cn]
-  double2* cprime = nullptr;
+// LU factors of the two tridiagonal chains of (I - dt/4 L) per m, for one
+// (dt, terms), as the coefficients of the two first-order recurrences
+//   y_i = alph_i y_{i-1} + invpiv_i r_i,   x_i = gam_i x_{i+1} + y_i
+// (alph_i = -l_i / piv_i, gam_i = -u_i / piv_i); [2 chains][ncoef] each.
+struct CnFactors {
+  double2* alph = nullptr;
+  double2* gam = nullptr;
   double2* invpiv = nullptr;
 };
 

@@ -154,8 +154,8 @@ static void free_plan(Plan& p) {
   for (hipEvent_t e : p.ev_pool) (void)hipEventDestroy(e);
   p.ev_pool.clear();
   for (auto& kv : p.cn_cache) {
-    (void)hipFree(kv.second.lower);
-    (void)hipFree(kv.second.cprime);
+    (void)hipFree(kv.second.alph);
+    (void)hipFree(kv.second.gam);
     (void)hipFree(kv.second.invpiv);
   }
   p.cn_cache.clear();
@@ -404,7 +404,7 @@ void destroy(pint_plan* pp) {
 // Hermitian part of I - alpha L is the identity in energy variables).
 // ---------------------------------------------------------------------------
 __global__ void k_cn_factor(int M, int ncoef, double a, double W, double phibar, double alpha,
-                            int lg, double2* lower, double2* cprime, double2* invpiv) {
+                            int lg, double2* alph, double2* gam, double2* invpiv) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 2 * (M + 1)) return;
   const int m = t >> 1, chain = t & 1;
@@ -429,9 +429,10 @@ __global__ void k_cn_factor(int M, int ncoef, double a, double W, double phibar,
     const double2 piv = make_double2(d.x - lc.x, d.y - lc.y);
     const double2 ip = cinv(piv);
     const double2 cp = cmul(u, ip);
-    lower[base + i] = l;
+    const double2 al = cmul(l, ip);
+    alph[base + i] = make_double2(-al.x, -al.y);
     invpiv[base + i] = ip;
-    cprime[base + i] = cp;
+    gam[base + i] = make_double2(-cp.x, -cp.y);
     cpp = cp;
   }
 }
@@ -446,14 +447,14 @@ pint_status cn_factors(Plan& p, double dt, unsigned terms, hipStream_t s, const 
   }
   CnFactors f;
   const size_t n = (size_t)2 * p.ncoef;
-  PINT_TRY(dalloc(&f.lower, n, &p.ws_bytes));
-  PINT_TRY(dalloc(&f.cprime, n, &p.ws_bytes));
+  PINT_TRY(dalloc(&f.alph, n, &p.ws_bytes));
+  PINT_TRY(dalloc(&f.gam, n, &p.ws_bytes));
   PINT_TRY(dalloc(&f.invpiv, n, &p.ws_bytes));
   const double W = (key_terms & PINT_T_LC) ? 2.0 * p.omega : 0.0;
   const bool lg = (key_terms & PINT_T_LG) != 0;
   const int nt = 2 * (p.M + 1);
   hipLaunchKernelGGL(k_cn_factor, dim3((nt + 63) / 64), dim3(64), 0, s, p.M, p.ncoef, p.a, W,
-                     lg ? p.phibar : 0.0, dt / 4.0, lg ? 1 : 0, f.lower, f.cprime, f.invpiv);
+                     lg ? p.phibar : 0.0, dt / 4.0, lg ? 1 : 0, f.alph, f.gam, f.invpiv);
   PINT_HIP(hipGetLastError());
   auto ins = p.cn_cache.emplace(key, f);
   *out = &ins.first->second;

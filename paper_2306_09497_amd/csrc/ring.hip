@@ -6,6 +6,8 @@
 // The FFT is a mixed-radix (4, 2, 3, 5) Stockham transform in a single LDS
 // buffer per signal: each pass loads its butterflies' operands into
 // registers, synchronises, then writes the butterfly outputs.
+#include <type_traits>
+
 #include "pint_internal.h"
 
 namespace pint {
@@ -323,118 +325,296 @@ __device__ inline void get_pair(const double2* z, int sig, int m, double2* X, do
 }
 
 // ---------------------------------------------------------------------------
-// Tendency ring kernel.  In: synthesis E/O rows (6 fields: xi, delta, Phi', G,
-// U, V).  Grid values: xi, delta, Phi', dPhi'/dlambda (= i m Phi'), G, U, V,
-// transformed as the pairs (U, V), (G, dPhi'/dlambda), (xi, delta), (Phi', 0)
-// (fields of like magnitude share an FFT).  Pointwise (c^2 = 1 - mu_j^2):
+// Tendency ring kernel (one workgroup of kHThreads per latitude ring and
+// state).  Every real grid field x of the ring (nlon = N = 2H points) is
+// carried as the half-length complex signal z[n] = x[2n] + i x[2n+1]:
+//   synthesis: Z[k] = (X_k + conj X_{H-k}) + i e^{2 pi i k/N} (X_k - conj X_{H-k}),
+//              z = inverse FFT_H(Z)  (X_m = 0 for m > M, X_0 real);
+//   analysis:  Z = FFT_H(z),  X_k = 1/2 [(Z_k + conj Z_{H-k})
+//                                  - i e^{-2 pi i k/N} (Z_k - conj Z_{H-k})].
+// Each field owns its transform (no pairing of unrelated fields, so no field
+// inherits the rounding of a larger one).  The inverse transforms are in-place
+// decimation in frequency (natural order in, digit-reversed out) and the
+// forward ones decimation in time with the stage order reversed
+// (digit-reversed in, natural out): the pointwise products work on the
+// digit-reversed points directly, and every stage needs one barrier only.
+//
+// Fields (Sec. 2.1, advective form of N_A plus N_R), c^2 = 1 - mu_j^2:
 //   N_Phi = -(U dPhi'/dlambda + V G) / (a c^2) - Phi' delta
-//   A = xi U / c^2,  B = xi V / c^2,  K = (U^2 + V^2) / (2 c^2)
-// each scaled by w_j / nlon, then forward FFT of (N_Phi, K), (A, B), m = 0..M,
-// to G[m][j][(b*4+f)*2].
+//   K = (U^2 + V^2) / (2 c^2),  A = xi U / c^2,  B = xi V / c^2,
+// each scaled by w_j / nlon, whose transforms m = 0..M go to
+// G[m][j][(b*4 + f)*2] with f = (N_Phi, K, A, B).  The seven synthesised
+// fields are transformed in two groups through a four-signal LDS buffer:
+// (xi, delta, Phi'), whose xi and Phi' delta stay in registers, then
+// (U, V, G, dPhi'/dlambda).
 // ---------------------------------------------------------------------------
+constexpr int kHThreads = 128;
+
+template <>
+__device__ inline void dft<6>(double2* v, double sign) {
+  double2 a[3] = {v[0], v[2], v[4]};
+  double2 b[3] = {v[1], v[3], v[5]};
+  dft<3>(a, sign);
+  dft<3>(b, sign);
+  const double h = 0.86602540378443864676 * sign;   // sign * sin(pi/3)
+  // b_k *= exp(sign 2 pi i k / 6)
+  const double2 b1 = make_double2(0.5 * b[1].x - h * b[1].y, h * b[1].x + 0.5 * b[1].y);
+  const double2 b2 = make_double2(-0.5 * b[2].x - h * b[2].y, h * b[2].x - 0.5 * b[2].y);
+  v[0] = c_add(a[0], b[0]);
+  v[3] = c_sub(a[0], b[0]);
+  v[1] = c_add(a[1], b1);
+  v[4] = c_sub(a[1], b1);
+  v[2] = c_add(a[2], b2);
+  v[5] = c_sub(a[2], b2);
+}
+
+constexpr int ilog2c(int n) {
+  int c = 0;
+  while (n > 1) { n >>= 1; ++c; }
+  return c;
+}
+// Radix plan of a half-length transform of H points: stage 0 (span H) has
+// radix 6, 5, 8 or 4; the rest is radix 4 with one radix 8 when needed.  The
+// forward transform ends with stage 0 at stride H / R_0, which is even for
+// every supported ring, so its butterflies j and S - j pair up as Z_k, Z_{H-k}.
+constexpr int hplan_first(int H) {
+  return H % 3 == 0 ? 6 : (H % 5 == 0 ? 5 : (ilog2c(H) % 2 ? 8 : 4));
+}
+constexpr int hplan_npass(int H) {
+  int rest = H / hplan_first(H);
+  int c = 1;
+  if (ilog2c(rest) % 2) { rest /= 8; ++c; }
+  while (rest > 1) { rest /= 4; ++c; }
+  return c;
+}
+constexpr int hplan_radix(int H, int i) {
+  if (i == 0) return hplan_first(H);
+  return (i == 1 && ilog2c(H / hplan_first(H)) % 2) ? 8 : 4;
+}
+constexpr int hplan_span(int H, int i) {
+  int L = H;
+  for (int k = 0; k < i; ++k) L /= hplan_radix(H, k);
+  return L;
+}
+constexpr bool hplan_ok(int H) {
+  return hplan_span(H, hplan_npass(H)) == 1 && (H / hplan_first(H)) % 2 == 0;
+}
+
+// LDS layout of the half-length signals: signal s, point i at s*SP + i + i/16.
+template <int H>
+struct HRing {
+  static constexpr int SP = H + H / 16;
+  __device__ static inline int at(int s, int i) { return s * SP + i + (i >> 4); }
+};
+
+// exp(SGN 2 pi i t / N) from the table tw[t] = exp(-2 pi i t / N).
+template <int SGN>
+__device__ inline double2 twid(const double2* __restrict__ tw, int t) {
+  double2 w = tw[t];
+  if constexpr (SGN > 0) w.y = -w.y;
+  return w;
+}
+
+// One in-place stage (span L, radix R, stride S = L/R) over NSIG signals.
+// DIF: butterfly, then twiddles W_L^{j r}; DIT: twiddles, then butterfly.
+// Butterflies touch disjoint points, so loads and stores need no barrier
+// between them; the barrier at the end orders the stage before the next.
+template <int H, int NSIG, int R, int L, bool kDif, int SGN>
+__device__ inline void ip_stage(double2* buf, const double2* __restrict__ tw, int tid) {
+  constexpr int S = L / R;
+  constexpr int NBS = H / R;
+  constexpr int TOTAL = NSIG * NBS;
+  constexpr int NIT = (TOTAL + kHThreads - 1) / kHThreads;
+  constexpr int TWS = 2 * H / L;        // table step per unit of j r
+  using Lay = HRing<H>;
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int id = tid + it * kHThreads;
+    if (TOTAL % kHThreads == 0 || id < TOTAL) {
+      const int sig = id / NBS, rem = id - sig * NBS;
+      const int blk = rem / S, j = rem - blk * S;
+      const int base = blk * L + j;
+      double2 v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = buf[Lay::at(sig, base + r * S)];
+      if constexpr (!kDif && S > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twid<SGN>(tw, j * r * TWS));
+      }
+      dft<R>(v, (double)SGN);
+      if constexpr (kDif && S > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twid<SGN>(tw, j * r * TWS));
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[Lay::at(sig, base + r * S)] = v[r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int H, int NSIG, int SGN, int I>
+__device__ inline void dif_stages(double2* buf, const double2* __restrict__ tw, int tid) {
+  if constexpr (I < hplan_npass(H)) {
+    ip_stage<H, NSIG, hplan_radix(H, I), hplan_span(H, I), true, SGN>(buf, tw, tid);
+    dif_stages<H, NSIG, SGN, I + 1>(buf, tw, tid);
+  }
+}
+
+// DIT stages I, I-1, ..., 1 (stage 0 is done by the caller).
+template <int H, int NSIG, int SGN, int I>
+__device__ inline void dit_stages(double2* buf, const double2* __restrict__ tw, int tid) {
+  if constexpr (I >= 1) {
+    ip_stage<H, NSIG, hplan_radix(H, I), hplan_span(H, I), false, SGN>(buf, tw, tid);
+    dit_stages<H, NSIG, SGN, I - 1>(buf, tw, tid);
+  }
+}
+
+// Z = (X1 + conj X2) + i w (X1 - conj X2)
+__device__ inline double2 hpre(double2 X1, double2 X2, double2 w) {
+  const double2 d = make_double2(X1.x - X2.x, X1.y + X2.y);
+  const double2 wd = cmul(w, d);
+  return make_double2(X1.x + X2.x - wd.y, X1.y - X2.y + wd.x);
+}
+
+// X = 1/2 [(Za + conj Zb) - i w (Za - conj Zb)]
+__device__ inline double2 hpost(double2 Za, double2 Zb, double2 w) {
+  const double2 d = make_double2(Za.x - Zb.x, Za.y + Zb.y);
+  const double2 wd = cmul(w, d);
+  return make_double2(0.5 * (Za.x + Zb.x + wd.y), 0.5 * (Za.y - Zb.y - wd.x));
+}
+
 template <int N>
-__global__ __launch_bounds__(kRingThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_ring_tendency(
+__global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_ring_tendency(
     const double* __restrict__ F, double* __restrict__ Gout, const double* __restrict__ c2,
     const double* __restrict__ w, const double2* __restrict__ tw, int M, int nlat, int nlat2,
     int B, double a) {
-  constexpr int nlon = N;
-  using L = RingLds<N>;
+  constexpr int H = N / 2;
+  static_assert(hplan_ok(H), "no half-length plan for this ring");
+  constexpr int NPW = (H + kHThreads - 1) / kHThreads;   // pointwise points per thread
+  using Lay = HRing<H>;
   extern __shared__ double2 zb[];
-  __shared__ double red[kRingWaves * 8];
-  // logical block = j * B + b (states of one latitude adjacent: their
-  // Fourier rows are contiguous), XCD-remapped
+  // logical block = ((jn * B) + b) * 2 + hemisphere: the northern and southern
+  // rings of one state share the E/O rows and run back to back on one XCD
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int j = lb / B, b = lb - j * B;
-  const int jn = j < nlat2 ? j : nlat - 1 - j;
-  const double sg = j < nlat2 ? 1.0 : -1.0;
+  const int hemi = lb & 1, rb = lb >> 1;
+  const int jn = rb / B, b = rb - jn * B;
+  const int j = hemi ? nlat - 1 - jn : jn;
+  const double sg = hemi ? -1.0 : 1.0;
   const int ncs = 12 * B;
   const int tid = threadIdx.x;
-  auto fourier = [&](int m, double2* v) {
-    const double2* e = reinterpret_cast<const double2*>(F + ((size_t)(2 * m) * nlat2 + jn) * ncs + b * 12);
-    const double2* o = reinterpret_cast<const double2*>(F + ((size_t)(2 * m + 1) * nlat2 + jn) * ncs + b * 12);
-#pragma unroll
-    for (int f = 0; f < 6; ++f) v[f] = c_add(e[f], c_scl(o[f], sg));
-    v[6] = make_double2(-m * v[2].y, m * v[2].x);     // dPhi'/dlambda = i m Phi'
+  auto xhat = [&](int m, int f) -> double2 {
+    const double2 e = *reinterpret_cast<const double2*>(
+        F + ((size_t)(2 * m) * nlat2 + jn) * ncs + b * 12 + 2 * f);
+    const double2 o = *reinterpret_cast<const double2*>(
+        F + ((size_t)(2 * m + 1) * nlat2 + jn) * ncs + b * 12 + 2 * f);
+    return c_add(e, c_scl(o, sg));
   };
-  // field norms over the ring (Parseval, up to a common factor)
-  double nrm[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int m = tid; m <= M; m += kRingThreads) {
-    double2 v[7];
-    fourier(m, v);
+  // Spectra of NS fields -> Z of the half-length signals in slots 0..NS-1.
+  // fld(m, s) returns field s's Fourier coefficient at m <= M.
+  auto put = [&](auto fld, auto nsig) {
+    constexpr int NS = decltype(nsig)::value;
+    for (int q = tid; q <= H / 2; q += kHThreads) {
+      const int k1 = q, k2 = H - q;
+      const bool h1 = k1 <= M, h2 = q > 0 && k2 <= M;
+      double2 X1[NS], X2[NS];
 #pragma unroll
-    for (int f = 0; f < 7; ++f) nrm[f] += v[f].x * v[f].x + v[f].y * v[f].y;
-  }
-  block_sum<7>(nrm, red, tid, (tid & ~63) <= M);
-  // fields: 0 xi, 1 delta, 2 Phi', 3 G, 4 U, 5 V, 6 dPhi'/dlambda
-  const double sUV = pair_scale(nrm[4], nrm[5]);
-  const double sGL = pair_scale(nrm[3], nrm[6]);
-  const double sXD = pair_scale(nrm[0], nrm[1]);
-  for (int i = tid; i < 4 * L::SP; i += kRingThreads) zb[i] = make_double2(0.0, 0.0);
-  __syncthreads();
-  for (int m = tid; m <= M; m += kRingThreads) {
-    double2 v[7];
-    fourier(m, v);                                             // L2 hits
-    put_pair<N>(zb, 0, m, v[4], c_scl(v[5], sUV));              // U + i s V
-    put_pair<N>(zb, 1, m, v[3], c_scl(v[6], sGL));              // G + i s dPhi'/dlambda
-    put_pair<N>(zb, 2, m, v[0], c_scl(v[1], sXD));              // xi + i s delta
-    put_pair<N>(zb, 3, m, v[2], make_double2(0.0, 0.0));        // Phi'
-  }
-  __syncthreads();
-  fft_lds<N, 4>(zb, 1.0, tw, tid);
+      for (int s = 0; s < NS; ++s) {
+        X1[s] = h1 ? fld(k1, s) : make_double2(0.0, 0.0);
+        X2[s] = h2 ? fld(k2, s) : make_double2(0.0, 0.0);
+        if (q == 0) X1[s].y = 0.0;              // a real field's mean
+      }
+      const double2 w1 = twid<1>(tw, k1);      // exp(2 pi i k1 / N)
+      const double2 w2 = make_double2(-w1.x, w1.y);   // exp(2 pi i (H - k1) / N)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        zb[Lay::at(s, k1)] = hpre(X1[s], X2[s], w1);
+        if (q > 0 && k2 != k1) zb[Lay::at(s, k2)] = hpre(X2[s], X1[s], w2);
+      }
+    }
+    __syncthreads();
+  };
+
   const double ic2 = 1.0 / c2[j];
-  const double sc = w[j] / nlon;
-  const double ia = 1.0 / a;
-  // the pair scales are exact powers of two: their inverses by exponent flip
-  const double iUV = ldexp(1.0, -ilogb(sUV)), iGL = ldexp(1.0, -ilogb(sGL)),
-               iXD = ldexp(1.0, -ilogb(sXD));
-  constexpr int NPT = (N + kRingThreads - 1) / kRingThreads;   // grid points per thread
-  double pv[NPT][4];
-  double fn[4] = {0, 0, 0, 0};
+  const double ica = ic2 / a;
+  const double sc = w[j] / N;
+  // ---- group 1: xi, delta, Phi' -> keep xi and Phi' delta per point ----
+  put([&](int m, int s) -> double2 { return xhat(m, s); }, std::integral_constant<int, 3>());
+  dif_stages<H, 3, 1, 0>(zb, tw, tid);
+  double2 Xr[NPW], Dr[NPW];
 #pragma unroll
-  for (int t = 0; t < NPT; ++t) {
-    const int k = tid + t * kRingThreads;
-    if (k < nlon) {
-      const double2 z1 = zb[L::at(0, k)], z2 = zb[L::at(1, k)], z3 = zb[L::at(2, k)],
-                    z4 = zb[L::at(3, k)];
-      const double U = z1.x, V = z1.y * iUV, G = z2.x, phl = z2.y * iGL;
-      const double xi = z3.x, de = z3.y * iXD, ph = z4.x;
-      const double nphi = (-(U * phl + V * G) * ic2 * ia - ph * de) * sc;
-      const double A = xi * U * ic2 * sc, Bv = xi * V * ic2 * sc;
-      const double K = 0.5 * (U * U + V * V) * ic2 * sc;
-      pv[t][0] = nphi;
-      pv[t][1] = K;
-      pv[t][2] = A;
-      pv[t][3] = Bv;
-      fn[0] += nphi * nphi;
-      fn[1] += K * K;
-      fn[2] += A * A;
-      fn[3] += Bv * Bv;
-    }
-  }
-  block_sum<4>(fn, red, tid);      // also orders the reads above before the writes below
-  const double sNK = pair_scale(fn[0], fn[1]);
-  const double sAB = pair_scale(fn[2], fn[3]);
-#pragma unroll
-  for (int t = 0; t < NPT; ++t) {
-    const int k = tid + t * kRingThreads;
-    if (k < nlon) {
-      zb[L::at(0, k)] = make_double2(pv[t][0], pv[t][1] * sNK);
-      zb[L::at(1, k)] = make_double2(pv[t][2], pv[t][3] * sAB);
+  for (int t = 0; t < NPW; ++t) {
+    const int p = tid + t * kHThreads;
+    if (H % kHThreads == 0 || p < H) {
+      const double2 xi = zb[Lay::at(0, p)], de = zb[Lay::at(1, p)], ph = zb[Lay::at(2, p)];
+      Xr[t] = xi;
+      Dr[t] = make_double2(ph.x * de.x, ph.y * de.y);
     }
   }
   __syncthreads();
-  fft_lds<N, 2>(zb, -1.0, tw, tid);
+
+  // ---- group 2: U, V, G, dPhi'/dlambda -> all four products ----
+  put([&](int m, int s) -> double2 {
+        if (s == 0) return xhat(m, 4);
+        if (s == 1) return xhat(m, 5);
+        if (s == 2) return xhat(m, 3);
+        const double2 p = xhat(m, 2);
+        return make_double2(-m * p.y, m * p.x);          // i m Phi'
+      },
+      std::integral_constant<int, 4>());
+  dif_stages<H, 4, 1, 0>(zb, tw, tid);
+#pragma unroll
+  for (int t = 0; t < NPW; ++t) {
+    const int p = tid + t * kHThreads;
+    if (H % kHThreads == 0 || p < H) {
+      const double2 U = zb[Lay::at(0, p)], V = zb[Lay::at(1, p)];
+      const double2 G = zb[Lay::at(2, p)], L = zb[Lay::at(3, p)];
+      const double2 xi = Xr[t], pd = Dr[t];
+      zb[Lay::at(0, p)] = make_double2((-(U.x * L.x + V.x * G.x) * ica - pd.x) * sc,
+                                       (-(U.y * L.y + V.y * G.y) * ica - pd.y) * sc);   // N_Phi
+      zb[Lay::at(1, p)] = make_double2(xi.x * U.x * ic2 * sc, xi.y * U.y * ic2 * sc);   // A
+      zb[Lay::at(2, p)] = make_double2(xi.x * V.x * ic2 * sc, xi.y * V.y * ic2 * sc);   // B
+      zb[Lay::at(3, p)] = make_double2(0.5 * (U.x * U.x + V.x * V.x) * ic2 * sc,
+                                       0.5 * (U.y * U.y + V.y * V.y) * ic2 * sc);   // K
+    }
+  }
+  __syncthreads();
+
+  // ---- forward transforms of (N_Phi, A, B, K) in slots 0..3 ----
+  dit_stages<H, 4, -1, hplan_npass(H) - 1>(zb, tw, tid);
+  // last stage (span H) with the pairing k <-> H - k and the unpacking
+  constexpr int R1 = hplan_first(H), S1 = H / R1, UPS = S1 / 2;
+  constexpr int TOTU = 4 * UPS;
   const int ncg = 8 * B;
-  const double iNK = ldexp(1.0, -ilogb(sNK)), iAB = ldexp(1.0, -ilogb(sAB));
-  for (int m = tid; m <= M; m += kRingThreads) {
-    double2 X0, Y0, X1, Y1;
-    get_pair<N>(zb, 0, m, &X0, &Y0);
-    get_pair<N>(zb, 1, m, &X1, &Y1);
-    double2* g = reinterpret_cast<double2*>(Gout + ((size_t)m * nlat + j) * ncg + b * 8);
-    g[0] = X0;
-    g[1] = c_scl(Y0, iNK);
-    g[2] = X1;
-    g[3] = c_scl(Y1, iAB);
+  for (int u = tid; u < TOTU; u += kHThreads) {
+    const int sig = u / UPS, uu = u - sig * UPS;
+    const int ja = uu, jb = uu == 0 ? S1 / 2 : S1 - uu;
+    double2 za[R1], zc[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      za[r] = zb[Lay::at(sig, ja + r * S1)];
+      zc[r] = zb[Lay::at(sig, jb + r * S1)];
+    }
+#pragma unroll
+    for (int r = 1; r < R1; ++r) {
+      za[r] = cmul(za[r], twid<-1>(tw, ja * r * 2));
+      zc[r] = cmul(zc[r], twid<-1>(tw, jb * r * 2));
+    }
+    dft<R1>(za, -1.0);
+    dft<R1>(zc, -1.0);
+    const int f = sig == 0 ? 0 : (sig == 3 ? 1 : sig + 1);   // slot -> (N_Phi, K, A, B)
+    double* gcol = Gout + (size_t)j * ncg + b * 8 + 2 * f;
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const int ka = ja + r * S1, kc = jb + r * S1;
+      // partners Z_{H-k}
+      const double2 pa = uu == 0 ? za[(R1 - r) % R1] : zc[R1 - 1 - r];
+      const double2 pc = uu == 0 ? zc[R1 - 1 - r] : za[R1 - 1 - r];
+      if (ka <= M)
+        *reinterpret_cast<double2*>(gcol + (size_t)ka * nlat * ncg) = hpost(za[r], pa, tw[ka]);
+      if (kc <= M)
+        *reinterpret_cast<double2*>(gcol + (size_t)kc * nlat * ncg) = hpost(zc[r], pc, tw[kc]);
+    }
   }
 }
 
@@ -540,12 +720,12 @@ bool ring_supported(int nlon) {
   return false;
 }
 
-// Dynamic LDS of the tendency ring kernel: 4 signals.
+// Dynamic LDS of the tendency ring kernel: 4 half-length signals.
 size_t ring_lds_bytes(int nlon) {
   switch (nlon) {
 #define PINT_CASE(n) \
   case n:            \
-    return (size_t)4 * RingLds<n>::SP * sizeof(double2);
+    return (size_t)4 * HRing<n / 2>::SP * sizeof(double2);
     PINT_FOR_EACH_NLON(PINT_CASE)
 #undef PINT_CASE
     default:
@@ -575,7 +755,7 @@ pint_status ring_tendency(Plan& p, int B, hipStream_t s) {
   switch (p.nlon) {
 #define PINT_CASE(n)                                                                         \
   case n:                                                                                    \
-    hipLaunchKernelGGL(k_ring_tendency<n>, dim3(p.nlat * B), dim3(kRingThreads),             \
+    hipLaunchKernelGGL(k_ring_tendency<n>, dim3(p.nlat * B), dim3(kHThreads),                \
                        ring_lds_bytes(n), s, p.F, p.G, p.c2, p.w, p.twid, p.M, p.nlat,       \
                        p.nlat2, B, p.a);                                                     \
     break;

@@ -206,50 +206,19 @@ pint_status nl_eval(Plan& p, const double* u, double* out, const double* ua, dou
 // ---------------------------------------------------------------------------
 // Crank-Nicolson half step (I - alpha L) x = (I + alpha L) y, alpha = dt/4,
 // with the viscosity factor 1/(1 + dt nu (n(n+1)/a^2)^(q/2)) applied to the
-// result (see cn_factors for the chain form).
-//
-// Phase 1 (k_cn_rhs, one thread per (idx, b), fully parallel): the right-hand
-// side r = (I + alpha L) y, with Phi eliminated from the delta rows:
-//   x <- (r_Phi, r_xi, r_delta + alpha n(n+1)/a^2 r_Phi).
-// Phase 2: the two tridiagonal chains per m (forward elimination with the
-// precomputed factors, back substitution), then x_Phi = r_Phi - alpha Phibar
-// x_delta and the viscosity factor.  Small batches run each m in LDS
-// (k_cn_chain_lds, latency-bound serial sweeps); large batches run one
-// thread per (m, chain, b) on the work layout (k_cn_chain).
-// y and x must not overlap.
+// result (see cn_factors for the chain form).  One 64-lane wave per (m, b):
+//  1. right-hand side r = (I + alpha L) y with Phi eliminated from the delta
+//     rows: (r_Phi, r_xi, r_delta + alpha n(n+1)/a^2 r_Phi);
+//  2. per chain, forward elimination y_i = alph_i y_{i-1} + invpiv_i r_i and
+//     back substitution x_i = gam_i x_{i+1} + y_i.  Each is a first-order
+//     linear recurrence, i.e. a composition of affine maps: lane l composes
+//     the maps of its SEG consecutive positions, an inclusive scan over the
+//     64 lanes (log steps) gives every lane its incoming value, and each lane
+//     then runs its own positions;
+//  3. x_Phi = r_Phi - alpha Phibar x_delta, viscosity, store.
+// The order of operations depends on M only (never on B), so results are
+// batch-invariant.  y and x must not overlap.
 // ---------------------------------------------------------------------------
-__global__ void k_cn_rhs(const double* __restrict__ y, double* __restrict__ x,
-                         const double4* __restrict__ co, const int* __restrict__ coefmn,
-                         int ncoef, int M, int B, double W, double pb, double lgf, double alpha) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (size_t)ncoef * B) return;
-  const int b = (int)(t % B);
-  const int i = (int)(t / B);
-  const int mn = coefmn[i];
-  const int m = mn >> 16, n = mn & 0xffff;
-  const double4 c = co[i];
-  const double A = W * c.x, Bc = W * c.y, C = W * c.z, lap = lgf * c.w;
-  const size_t base = ((size_t)i * B + b) * 3;
-  const double2 yphi = ld2(y, base), yxi = ld2(y, base + 1), yde = ld2(y, base + 2);
-  double2 axi = cimul(yxi, Bc), ade = cadd(cscale(yphi, lap), cimul(yde, Bc));
-  if (n > m) {
-    const size_t bm = ((size_t)(i - 1) * B + b) * 3;
-    axi = cadd(axi, cscale(ld2(y, bm + 2), A));
-    ade = csub(ade, cscale(ld2(y, bm + 1), A));
-  }
-  if (n < M) {
-    const size_t bp = ((size_t)(i + 1) * B + b) * 3;
-    axi = cadd(axi, cscale(ld2(y, bp + 2), C));
-    ade = csub(ade, cscale(ld2(y, bp + 1), C));
-  }
-  const double2 rxi = cadd(yxi, cscale(axi, alpha));
-  const double2 rde = cadd(yde, cscale(ade, alpha));
-  const double2 rphi = csub(yphi, cscale(yde, alpha * pb));
-  st2(x, base, rphi);
-  st2(x, base + 1, rxi);
-  st2(x, base + 2, cadd(rde, cscale(rphi, alpha * lap)));
-}
-
 __device__ inline double visc_factor(int n, double a, double vdt, double nu, int q) {
   if (!(nu > 0.0)) return 1.0;
   const double l = (double)n * (n + 1) / (a * a);
@@ -261,121 +230,135 @@ __device__ inline double visc_factor(int n, double a, double vdt, double nu, int
 // chain position i of chain c at wavenumber m holds xi if (i even) == (c == 0)
 __device__ inline int chain_slot(int i, int chain) { return (((i & 1) == 0) == (chain == 0)) ? 1 : 2; }
 
-__global__ void k_cn_chain(double* __restrict__ x, const double2* __restrict__ lower,
-                           const double2* __restrict__ cprime, const double2* __restrict__ invpiv,
-                           int M, int ncoef, int B, double a, double alpha, double pb, double vdt,
-                           double nu, int q) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (size_t)2 * (M + 1) * B) return;
-  const int b = (int)(t % B);
-  const int mc = (int)(t / B);
-  const int m = mc >> 1, chain = mc & 1;
-  const int K = M - m + 1;
-  const int i0 = coef_idx(M, m, m);
-  const size_t fb = (size_t)chain * ncoef + i0;
-  auto addr = [&](int i, int slot) -> size_t { return ((size_t)(i0 + i) * B + b) * 3 + slot; };
-  // forward elimination, operands of step i+1 fetched before step i completes
-  double2 dprev = make_double2(0.0, 0.0);
-  double2 r = ld2(x, addr(0, chain_slot(0, chain)));
-  double2 l = lower[fb], ip = invpiv[fb];
-  for (int i = 0; i < K; ++i) {
-    double2 rn = r, ln = l, ipn = ip;
-    if (i + 1 < K) {
-      rn = ld2(x, addr(i + 1, chain_slot(i + 1, chain)));
-      ln = lower[fb + i + 1];
-      ipn = invpiv[fb + i + 1];
-    }
-    const double2 d = cmul(csub(r, cmul(l, dprev)), ip);
-    st2(x, addr(i, chain_slot(i, chain)), d);
-    dprev = d;
-    r = rn;
-    l = ln;
-    ip = ipn;
-  }
-  // back substitution with viscosity; delta positions also finish Phi
-  double2 xnext = dprev;
-  {
-    const int i = K - 1, n = m + i, sl = chain_slot(i, chain);
-    const double vf = visc_factor(n, a, vdt, nu, q);
-    st2(x, addr(i, sl), cscale(xnext, vf));
-    if (sl == 2) {
-      const double2 rphi = ld2(x, addr(i, 0));
-      st2(x, addr(i, 0), cscale(csub(rphi, cscale(xnext, alpha * pb)), vf));
-    }
-  }
-  for (int i = K - 2; i >= 0; --i) {
-    const int n = m + i, sl = chain_slot(i, chain);
-    const double2 xv = csub(ld2(x, addr(i, sl)), cmul(cprime[fb + i], xnext));
-    xnext = xv;
-    const double vf = visc_factor(n, a, vdt, nu, q);
-    st2(x, addr(i, sl), cscale(xv, vf));
-    if (sl == 2) {
-      const double2 rphi = ld2(x, addr(i, 0));
-      st2(x, addr(i, 0), cscale(csub(rphi, cscale(xv, alpha * pb)), vf));
+__device__ inline double2 cfma(double2 a, double2 x, double2 b) {   // a x + b
+  return cadd(cmul(a, x), b);
+}
+
+__device__ inline double2 shfl_up2(double2 v, int d) {
+  return make_double2(__shfl_up(v.x, d, 64), __shfl_up(v.y, d, 64));
+}
+__device__ inline double2 shfl_down2(double2 v, int d) {
+  return make_double2(__shfl_down(v.x, d, 64), __shfl_down(v.y, d, 64));
+}
+
+// Inclusive scan of affine maps f_l(v) = A_l v + B_l over the 64 lanes:
+// kUp: lane l gets f_l o f_{l-1} o ... o f_0; otherwise f_l o ... o f_63.
+template <bool kUp>
+__device__ inline void affine_scan(double2& A, double2& Bv, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const double2 Ap = kUp ? shfl_up2(A, d) : shfl_down2(A, d);
+    const double2 Bp = kUp ? shfl_up2(Bv, d) : shfl_down2(Bv, d);
+    if (kUp ? lane >= d : lane + d < 64) {
+      Bv = cfma(A, Bp, Bv);
+      A = cmul(A, Ap);
     }
   }
 }
 
-// Small batches: one 64-thread workgroup per (m, b); the m-block of x and the
-// chain factors are staged in LDS, lanes 0 and 1 run the two chains, then all
-// lanes finish Phi, apply viscosity and store.
-constexpr int kCnLdsMaxK = 512;
-__global__ __launch_bounds__(64) void k_cn_chain_lds(double* __restrict__ x,
-                                                     const double2* __restrict__ lower,
-                                                     const double2* __restrict__ cprime,
-                                                     const double2* __restrict__ invpiv, int M,
-                                                     int ncoef, int B, double a, double alpha,
-                                                     double pb, double vdt, double nu, int q) {
-  extern __shared__ double2 sm[];
-  const int m = blockIdx.x, b = blockIdx.y;
+template <int SEG>
+__global__ __launch_bounds__(64) void k_cn_solve(
+    const double* __restrict__ y, double* __restrict__ x, const double4* __restrict__ co,
+    const double2* __restrict__ alph, const double2* __restrict__ gam,
+    const double2* __restrict__ invpiv, int M, int ncoef, int B, double a, double W, double lgf,
+    double pb, double alpha, double vdt, double nu, int q) {
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);    // logical block m * B + b
+  const int m = lb / B, b = lb - m * B;
   const int K = M - m + 1;
   const int i0 = coef_idx(M, m, m);
-  double2* sx = sm;               // [K][3]
-  double2* sl = sm + 3 * K;       // [2][K] lower
-  double2* sc = sl + 2 * K;       // [2][K] cprime
-  double2* si = sc + 2 * K;       // [2][K] invpiv
-  for (int e = threadIdx.x; e < 3 * K; e += 64) {
-    const int i = e / 3, f = e - 3 * i;
-    sx[e] = ld2(x, ((size_t)(i0 + i) * B + b) * 3 + f);
-  }
-  for (int e = threadIdx.x; e < 2 * K; e += 64) {
-    const int c = e / K, i = e - c * K;
-    const size_t g = (size_t)c * ncoef + i0 + i;
-    sl[e] = lower[g];
-    sc[e] = cprime[g];
-    si[e] = invpiv[g];
-  }
-  __syncthreads();
-  if (threadIdx.x < 2) {
-    const int chain = threadIdx.x;
-    const double2* L = sl + chain * K;
-    const double2* Cp = sc + chain * K;
-    const double2* Ip = si + chain * K;
-    double2 dprev = make_double2(0.0, 0.0);
-    for (int i = 0; i < K; ++i) {
-      double2& r = sx[3 * i + chain_slot(i, chain)];
-      const double2 d = cmul(csub(r, cmul(L[i], dprev)), Ip[i]);
-      r = d;
-      dprev = d;
-    }
-    double2 xnext = dprev;
-    for (int i = K - 2; i >= 0; --i) {
-      double2& r = sx[3 * i + chain_slot(i, chain)];
-      const double2 xv = csub(r, cmul(Cp[i], xnext));
-      r = xv;
-      xnext = xv;
+  const int lane = threadIdx.x;
+  const int p0 = lane * SEG;
+  auto Y = [&](int i, int f) { return ld2(y, ((size_t)(i0 + i) * B + b) * 3 + f); };
+  const double2 zero = make_double2(0.0, 0.0), one = make_double2(1.0, 0.0);
+  // 1. right-hand side of the lane's positions
+  double2 rphi[SEG], rv[2][SEG];
+#pragma unroll
+  for (int k = 0; k < SEG; ++k) {
+    const int i = p0 + k;
+    rphi[k] = zero;
+    rv[0][k] = zero;
+    rv[1][k] = zero;
+    if (i < K) {
+      const double4 c = co[i0 + i];
+      const double A = W * c.x, Bc = W * c.y, C = W * c.z, lap = lgf * c.w;
+      const double2 yphi = Y(i, 0), yxi = Y(i, 1), yde = Y(i, 2);
+      double2 axi = cimul(yxi, Bc), ade = cadd(cscale(yphi, lap), cimul(yde, Bc));
+      if (i > 0) {
+        axi = cadd(axi, cscale(Y(i - 1, 2), A));
+        ade = csub(ade, cscale(Y(i - 1, 1), A));
+      }
+      if (i + 1 < K) {
+        axi = cadd(axi, cscale(Y(i + 1, 2), C));
+        ade = csub(ade, cscale(Y(i + 1, 1), C));
+      }
+      const double2 rxi = cadd(yxi, cscale(axi, alpha));
+      const double2 rde = cadd(yde, cscale(ade, alpha));
+      rphi[k] = csub(yphi, cscale(yde, alpha * pb));
+      const double2 rdp = cadd(rde, cscale(rphi[k], alpha * lap));
+      const bool xi0 = chain_slot(i, 0) == 1;
+      rv[0][k] = xi0 ? rxi : rdp;
+      rv[1][k] = xi0 ? rdp : rxi;
     }
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < K; i += 64) {
-    const int n = m + i;
-    const double vf = visc_factor(n, a, vdt, nu, q);
-    const double2 xde = sx[3 * i + 2];
-    const double2 xphi = csub(sx[3 * i], cscale(xde, alpha * pb));
-    const size_t g = ((size_t)(i0 + i) * B + b) * 3;
-    st2(x, g, cscale(xphi, vf));
-    st2(x, g + 1, cscale(sx[3 * i + 1], vf));
-    st2(x, g + 2, cscale(xde, vf));
+  // 2. the two chains
+#pragma unroll
+  for (int ch = 0; ch < 2; ++ch) {
+    const size_t fb = (size_t)ch * ncoef + i0;
+    double2 al[SEG], be[SEG], ga[SEG];
+#pragma unroll
+    for (int k = 0; k < SEG; ++k) {
+      const int i = p0 + k;
+      al[k] = i < K ? alph[fb + i] : one;
+      ga[k] = i < K ? gam[fb + i] : one;
+      be[k] = i < K ? cmul(invpiv[fb + i], rv[ch][k]) : zero;
+    }
+    // forward: the lane's composite map, scan, then its own positions
+    double2 A = one, Bv = zero;
+#pragma unroll
+    for (int k = 0; k < SEG; ++k) {
+      Bv = cfma(al[k], Bv, be[k]);
+      A = cmul(al[k], A);
+    }
+    affine_scan<true>(A, Bv, lane);
+    double2 v = shfl_up2(Bv, 1);
+    if (lane == 0) v = zero;
+#pragma unroll
+    for (int k = 0; k < SEG; ++k) {
+      v = cfma(al[k], v, be[k]);
+      rv[ch][k] = p0 + k < K ? v : zero;               // y_i
+    }
+    // backward (positions beyond K keep the identity map and y = 0)
+    A = one;
+    Bv = zero;
+#pragma unroll
+    for (int k = SEG - 1; k >= 0; --k) {
+      Bv = cfma(ga[k], Bv, rv[ch][k]);
+      A = cmul(ga[k], A);
+    }
+    affine_scan<false>(A, Bv, lane);
+    v = shfl_down2(Bv, 1);
+    if (lane == 63) v = zero;
+#pragma unroll
+    for (int k = SEG - 1; k >= 0; --k) {
+      v = cfma(ga[k], v, rv[ch][k]);
+      rv[ch][k] = v;                                   // x_i
+    }
+  }
+  // 3. Phi, viscosity, store
+#pragma unroll
+  for (int k = 0; k < SEG; ++k) {
+    const int i = p0 + k;
+    if (i < K) {
+      const bool xi0 = chain_slot(i, 0) == 1;
+      const double2 xxi = xi0 ? rv[0][k] : rv[1][k];
+      const double2 xde = xi0 ? rv[1][k] : rv[0][k];
+      const double vf = visc_factor(m + i, a, vdt, nu, q);
+      const double2 xphi = csub(rphi[k], cscale(xde, alpha * pb));
+      const size_t g = ((size_t)(i0 + i) * B + b) * 3;
+      st2(x, g, cscale(xphi, vf));
+      st2(x, g + 1, cscale(xxi, vf));
+      st2(x, g + 2, cscale(xde, vf));
+    }
   }
 }
 
@@ -387,21 +370,24 @@ pint_status cn_apply(Plan& p, const CnFactors& f, double dt, unsigned terms, int
   const double pb = lg ? p.phibar : 0.0;
   const double nuv = (terms & PINT_T_VISC) ? nu : 0.0;
   const double alpha = dt / 4.0;
-  {
-    const size_t total = (size_t)p.ncoef * B;
-    hipLaunchKernelGGL(k_cn_rhs, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, y, x,
-                       p.cnco, p.coefmn, p.ncoef, p.M, B, W, pb, lg ? 1.0 : 0.0, alpha);
-    PINT_HIP(hipGetLastError());
-  }
-  if (B <= 4 && p.M + 1 <= kCnLdsMaxK) {
-    const size_t lds = (size_t)9 * (p.M + 1) * sizeof(double2);
-    hipLaunchKernelGGL(k_cn_chain_lds, dim3(p.M + 1, B), dim3(64), lds, s, x, f.lower, f.cprime,
-                       f.invpiv, p.M, p.ncoef, B, p.a, alpha, pb, dt, nuv, q);
+  const int K = p.M + 1;
+  const dim3 grid((unsigned)(K * B));
+#define PINT_CN(SEG)                                                                            \
+  hipLaunchKernelGGL(k_cn_solve<SEG>, grid, dim3(64), 0, s, y, x, p.cnco, f.alph, f.gam,       \
+                     f.invpiv, p.M, p.ncoef, B, p.a, W, lg ? 1.0 : 0.0, pb, alpha, dt, nuv, q)
+  if (K <= 64) {
+    PINT_CN(1);
+  } else if (K <= 128) {
+    PINT_CN(2);
+  } else if (K <= 256) {
+    PINT_CN(4);
+  } else if (K <= 512) {
+    PINT_CN(8);
   } else {
-    const size_t total = (size_t)2 * (p.M + 1) * B;
-    hipLaunchKernelGGL(k_cn_chain, dim3((unsigned)((total + 127) / 128)), dim3(128), 0, s, x,
-                       f.lower, f.cprime, f.invpiv, p.M, p.ncoef, B, p.a, alpha, pb, dt, nuv, q);
+    set_error("Crank-Nicolson chains longer than 512 are not supported (M=%d)", p.M);
+    return PINT_E_INVAL;
   }
+#undef PINT_CN
   PINT_HIP(hipGetLastError());
   return PINT_OK;
 }
