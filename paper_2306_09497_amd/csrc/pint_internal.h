@@ -89,7 +89,7 @@ struct Plan {
   GemmTiles syn_tiles, ana_tiles, ana_tiles64;
   // workspace (sized for max_batch)
   double* S = nullptr;         // [nrows][12 B]   synthesis GEMM input
-  double* F = nullptr;         // [2(M+1) nlat2][12 B] synthesis output (E/O)
+  double* F = nullptr;         // [(M+1) nlat][12 B] synthesis output (Fourier coefficients)
   double* G = nullptr;         // [(M+1) nlat][8 B] ring output
   double* Q = nullptr;         // [nrows][8 B]    analysis output
   double* Uw = nullptr;        // work-layout states, 5 buffers of [ncoef][B][3] complex

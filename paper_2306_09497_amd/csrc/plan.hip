@@ -169,7 +169,8 @@ static pint_status build_tiles(const std::vector<int>& rowoff, int M, int nlat2,
   std::vector<int> h;
   for (int cls = 0; cls < kNumXcd; ++cls) {
     for (int m = cls; m <= M; m += kNumXcd) {
-      for (int par = 0; par < 2; ++par) {
+      // a synthesis tile covers both parities of m (listed as p = 2m)
+      for (int par = 0; par < (synth ? 1 : 2); ++par) {
         const int p = 2 * m + par;
         const int cnt = rowoff[p + 1] - rowoff[p];
         const int R = synth ? nlat2 : cnt;

@@ -432,7 +432,17 @@ __device__ inline void ip_stage(double2* buf, const double2* __restrict__ tw, in
     const int id = tid + it * kHThreads;
     if (TOTAL % kHThreads == 0 || id < TOTAL) {
       const int sig = id / NBS, rem = id - sig * NBS;
-      const int blk = rem / S, j = rem - blk * S;
+      // lanes run along j for wide strides and along the blocks for strides
+      // <= 4, so that the lanes of one LDS access hit distinct banks
+      int blk, j;
+      if constexpr (S <= 4) {
+        constexpr int NBLK = H / L;
+        j = rem / NBLK;
+        blk = rem - j * NBLK;
+      } else {
+        blk = rem / S;
+        j = rem - blk * S;
+      }
       const int base = blk * L + j;
       double2 v[R];
 #pragma unroll
@@ -494,42 +504,48 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
   constexpr int NPW = (H + kHThreads - 1) / kHThreads;   // pointwise points per thread
   using Lay = HRing<H>;
   extern __shared__ double2 zb[];
-  // logical block = ((jn * B) + b) * 2 + hemisphere: the northern and southern
-  // rings of one state share the E/O rows and run back to back on one XCD
+  // logical block = ((jn * B) + b) * 2 + hemisphere: the rings of one state
+  // run back to back on one XCD
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int hemi = lb & 1, rb = lb >> 1;
   const int jn = rb / B, b = rb - jn * B;
   const int j = hemi ? nlat - 1 - jn : jn;
-  const double sg = hemi ? -1.0 : 1.0;
   const int ncs = 12 * B;
   const int tid = threadIdx.x;
+  // Fourier coefficient of field f at wavenumber m on this ring
   auto xhat = [&](int m, int f) -> double2 {
-    const double2 e = *reinterpret_cast<const double2*>(
-        F + ((size_t)(2 * m) * nlat2 + jn) * ncs + b * 12 + 2 * f);
-    const double2 o = *reinterpret_cast<const double2*>(
-        F + ((size_t)(2 * m + 1) * nlat2 + jn) * ncs + b * 12 + 2 * f);
-    return c_add(e, c_scl(o, sg));
+    return *reinterpret_cast<const double2*>(F + ((size_t)m * nlat + j) * ncs + b * 12 + 2 * f);
   };
   // Spectra of NS fields -> Z of the half-length signals in slots 0..NS-1.
-  // fld(m, s) returns field s's Fourier coefficient at m <= M.
+  // fld(m, s) returns field s's Fourier coefficient at m <= M.  Every load
+  // of the phase is issued before the first use.
   auto put = [&](auto fld, auto nsig) {
     constexpr int NS = decltype(nsig)::value;
-    for (int q = tid; q <= H / 2; q += kHThreads) {
-      const int k1 = q, k2 = H - q;
-      const bool h1 = k1 <= M, h2 = q > 0 && k2 <= M;
-      double2 X1[NS], X2[NS];
+    constexpr int NQ = (H / 2 + kHThreads) / kHThreads;   // pairs (k, H-k) per thread
+    double2 X1[NQ][NS], X2[NQ][NS];
+#pragma unroll
+    for (int it = 0; it < NQ; ++it) {
+      const int q = tid + it * kHThreads;
+      const bool h1 = q <= H / 2 && q <= M, h2 = q > 0 && q <= H / 2 && H - q <= M;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        X1[s] = h1 ? fld(k1, s) : make_double2(0.0, 0.0);
-        X2[s] = h2 ? fld(k2, s) : make_double2(0.0, 0.0);
-        if (q == 0) X1[s].y = 0.0;              // a real field's mean
+        X1[it][s] = h1 ? fld(q, s) : make_double2(0.0, 0.0);
+        X2[it][s] = h2 ? fld(H - q, s) : make_double2(0.0, 0.0);
+        if (q == 0) X1[it][s].y = 0.0;              // a real field's mean
       }
-      const double2 w1 = twid<1>(tw, k1);      // exp(2 pi i k1 / N)
-      const double2 w2 = make_double2(-w1.x, w1.y);   // exp(2 pi i (H - k1) / N)
+    }
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        zb[Lay::at(s, k1)] = hpre(X1[s], X2[s], w1);
-        if (q > 0 && k2 != k1) zb[Lay::at(s, k2)] = hpre(X2[s], X1[s], w2);
+    for (int it = 0; it < NQ; ++it) {
+      const int q = tid + it * kHThreads;
+      if (q <= H / 2) {
+        const int k1 = q, k2 = H - q;
+        const double2 w1 = twid<1>(tw, k1);        // exp(2 pi i k1 / N)
+        const double2 w2 = make_double2(-w1.x, w1.y);   // exp(2 pi i (H - k1) / N)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          zb[Lay::at(s, k1)] = hpre(X1[it][s], X2[it][s], w1);
+          if (q > 0 && k2 != k1) zb[Lay::at(s, k2)] = hpre(X2[it][s], X1[it][s], w2);
+        }
       }
     }
     __syncthreads();
@@ -620,7 +636,7 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
 
 // ---------------------------------------------------------------------------
 // Scalar rings for the public transforms (two states per workgroup).
-// synthesis: E/O rows (nf = 1) -> grid[b][j][k]
+// synthesis: Fourier rows F[m][j][b] (nf = 1) -> grid[b][j][k]
 // analysis:  grid[b][j][k] -> G[m][j][b*2] scaled by w_j / nlon
 // ---------------------------------------------------------------------------
 template <int N>
@@ -634,14 +650,11 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_synth(const double* __res
   __shared__ double red[kRingWaves * 2];
   const int j = blockIdx.x, b0 = 2 * blockIdx.y;
   const bool two = b0 + 1 < B;
-  const int jn = j < nlat2 ? j : nlat - 1 - j;
-  const double sg = j < nlat2 ? 1.0 : -1.0;
   const int ncs = 2 * B;
   auto fourier = [&](int m, double2* x, double2* y) {
-    const double2* e = reinterpret_cast<const double2*>(F + ((size_t)(2 * m) * nlat2 + jn) * ncs);
-    const double2* o = reinterpret_cast<const double2*>(F + ((size_t)(2 * m + 1) * nlat2 + jn) * ncs);
-    *x = c_add(e[b0], c_scl(o[b0], sg));
-    *y = two ? c_add(e[b0 + 1], c_scl(o[b0 + 1], sg)) : make_double2(0.0, 0.0);
+    const double2* f = reinterpret_cast<const double2*>(F + ((size_t)m * nlat + j) * ncs);
+    *x = f[b0];
+    *y = two ? f[b0 + 1] : make_double2(0.0, 0.0);
   };
   double nrm[2] = {0, 0};
   for (int m = threadIdx.x; m <= M; m += kRingThreads) {
