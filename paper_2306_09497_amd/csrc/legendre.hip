@@ -21,8 +21,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 // Tile: TR = 64 rows x TC columns (TC = 64 for batched launches, 16 for the
 // latency-bound single-state launches of the serial coarse sweep), k-slabs of
-// TK (16 batched, 32 single-state: fewer round trips on the serial path)
-// double-buffered in LDS: the next slab is fetched into registers while the
+// TK = 16 double-buffered in LDS: the next slab is fetched into registers while the
 // matrix cores work on the current one, one barrier per slab.  The matrix
 // cores consume k in steps of 4 in increasing order whatever TK and TC are,
 // so every launch shape gives bitwise the same sums.
