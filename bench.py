@@ -121,6 +121,105 @@ def cpu_baseline(seconds):
                       f"{len(os.sched_getaffinity(0))} cores available"}
 
 
+def e_phi_r(phi, ref, mmax, R=32):
+    """max_{m <= n <= R} |Phi_mn - ref_mn| / max_{m <= n <= R} |ref_mn| (spectral
+    error of the geopotential up to total wavenumber R, Sec. 5)."""
+    import numpy as np
+    sel = []
+    for m in range(R + 1):
+        base = m * (2 * mmax + 3 - m) // 2
+        sel.extend(base + (n - m) for n in range(m, R + 1))
+    sel = np.array(sel)
+    d = np.abs(phi[sel] - ref[sel]).max()
+    return float(d / np.abs(ref[sel]).max())
+
+
+def time_to_tol():
+    """Parareal to a relative increment of 1e-8 (cap N iterations) at T127
+    (384x192, 64 slices of 5400 s, fine IMEX 30 s x 180, coarse IMEX 900 s x 6
+    with q=4 nu=1e17, jet + bump), timed against (i) serial fine propagation
+    (batch 1, 11 520 steps) and (ii) the same Parareal with every slice
+    propagated by its own launches (a plan of max_batch 1: batch invariance
+    makes its iterates bitwise those of the batched run).  nu = 1e15 as first
+    specified makes the 900 s coarse step unstable at n = 127 for this jet;
+    1e17 is the paper's unviscous-fine / IMEX-coarse value for large coarse
+    steps.  Also reported, untimed: the error of every iterate against serial
+    fine (E_Phi,32 and relative L2)."""
+    import numpy as np
+    import torch
+    from paper_2306_09497_amd import pint, workloads
+
+    Mc, nlon, nlat, N = 127, 384, 192, 64
+    fine = pint.stepper(30.0, 2, 0.0, pint.T_ALL)
+    coarse = pint.stepper(900.0, 4, 1.0e17, pint.T_ALL)
+    prm = pint.params(pint.PARAREAL, N, fine, 180, coarse, 6, max_iter=N, tol=1e-8)
+    torch.cuda.init()
+    plans = {b: pint.Plan(Mc, nlon, nlat, phibar=PHIBAR, max_batch=b) for b in (N, 1)}
+    pl = plans[N]
+    mu, _ = pl.grid_coords()
+    G = workloads.jet_bump_grid(mu, nlon, phibar=PHIBAR, **workloads.jet_bump_params(0))
+    grid = torch.from_numpy(np.ascontiguousarray(G)).cuda()
+    u0 = torch.zeros((1, 3, pl.ncoef, 2), dtype=torch.float64, device="cuda")
+    pl.analysis(grid, u0, 3)
+    # (i) serial fine, every slice boundary kept
+    ref = torch.zeros((N + 1, 3, pl.ncoef, 2), dtype=torch.float64, device="cuda")
+    ref[0] = u0[0]
+    u = u0.clone()
+    plans[1].step(fine, u, u, 1, 180)                    # warm-up (factors, code)
+    u.copy_(u0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(N):
+        plans[1].step(fine, u, u, 1, 180)
+        ref[n + 1] = u[0]
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter() - t0
+    rf = ref[N].cpu().numpy()
+    phr = rf[0, :, 0] + 1j * rf[0, :, 1]
+
+    def errors(slices):
+        d = pl.rel_diff(slices[1:], ref[1:], N)          # [N][4] vs serial fine
+        fin = slices[N].cpu().numpy()
+        return {"E_phi_32_final": e_phi_r(fin[0, :, 0] + 1j * fin[0, :, 1], phr, Mc),
+                "max_rel_l2_phi_prime": float(d[:, 0].max()),
+                "max_rel_l2_wind": float(d[:, 3].max())}
+
+    out = {"config": "T127 384x192, 64 slices x 5400 s (4 days), fine IMEX 30 s x 180, coarse "
+                     "IMEX 900 s x 6 with q=4 nu=1e17, jet + bump, Parareal to increment 1e-8 "
+                     "(cap 64 = N)",
+           "serial_fine_s": t_ref, "serial_fine_steps": N * 180}
+    runs = {}
+    for name, b in (("parareal_batched", N), ("parareal_per_slice", 1)):
+        slices = torch.zeros((N + 1, 3, pl.ncoef, 2), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, rep, msg = plans[b].solve_status(prm, u0, slices)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        runs[name] = slices
+        out[name] = {"status": st, "iters": rep.iters, "seconds": el,
+                     "speedup_vs_serial_fine": t_ref / el,
+                     "fine_slice_steps": rep.fine_slice_steps,
+                     "increments": [rep.incr[i] for i in range(rep.iters)], **errors(slices)}
+    out["per_slice_iterates_bitwise_equal"] = bool(
+        torch.equal(runs["parareal_batched"], runs["parareal_per_slice"]))
+    out["batched_vs_per_slice_speedup"] = (out["parareal_per_slice"]["seconds"]
+                                           / out["parareal_batched"]["seconds"])
+    # error of every iterate against serial fine (untimed; one iteration per call)
+    curve = []
+    slices = torch.zeros((N + 1, 3, pl.ncoef, 2), dtype=torch.float64, device="cuda")
+    pl.solve(pint.params(pint.PARAREAL, N, fine, 180, coarse, 6, max_iter=0), u0, slices)
+    one = pint.params(pint.PARAREAL, N, fine, 180, coarse, 6, max_iter=1, resume=True)
+    for k in range(out["parareal_batched"]["iters"]):
+        pl.solve(one, u0, slices)
+        e = errors(slices)
+        curve.append([round(e["E_phi_32_final"], 12), round(e["max_rel_l2_phi_prime"], 12)])
+    out["error_per_iteration_E_phi_32_and_rel_l2"] = curve
+    for p_ in plans.values():
+        p_.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,12 +227,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--time-to-tol", action="store_true",
+                    help="print the T127 Parareal time-to-tolerance measurement instead")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the whole PinT problem on a "
               "single MI355X (time slices are the batch dimension); --gpus must be 1.",
               file=sys.stderr)
         return 2
+    if args.time_to_tol:
+        print(json.dumps({"metric": "PinT time-to-tol vs serial fine", **time_to_tol()}),
+              flush=True)
+        return 0
 
     import numpy as np
     import torch
