@@ -39,22 +39,36 @@ static pint_status check_stepper(const Plan& p, const pint_stepper* st) {
   return PINT_OK;
 }
 
-// nsteps IMEX steps (Sec. 2.3.1, eq. IMEX) on a work-layout batch uw (in/out):
-//   Ua = CN(U); Ub = Ua + dt N(Ua); Ub = Ua + dt/2 (N(Ua) + N(Ub)); U = D_nu CN(Ub)
-pint_status imex_steps(Plan& p, const pint_stepper& st, double* uw, int B, int nsteps,
-                       hipStream_t s) {
+// nsteps IMEX steps (Sec. 2.3.1, eq. IMEX) of B <= max_batch states:
+//   Ua = CN(U); Ub = Ua + dt N(Ua); U' = D_nu CN(Ua + dt/2 (N(Ua) + N(Ub)))
+// as  sp_cn_prep, [synthesis, ring, analysis, sp_stage1, synthesis, ring,
+// analysis, sp_stage2] per step, where each sp_stage2 but the last also runs
+// the next step's first half step.  Without the nonlinear term a step is the
+// two half steps alone.  out may alias in.
+pint_status imex_steps(Plan& p, const pint_stepper& st, const double* in, double* out, int B,
+                       int nsteps, hipStream_t s) {
+  if (nsteps == 0) {
+    if (in != out)
+      PINT_HIP(hipMemcpyAsync(out, in, (size_t)B * 3 * p.ncoef * 2 * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+    return PINT_OK;
+  }
   const CnFactors* f = nullptr;
   PINT_TRY(cn_factors(p, st.dt, st.terms, s, &f));
-  const bool nl = (st.terms & PINT_T_NL) != 0;
+  if (!(st.terms & PINT_T_NL)) {
+    for (int k = 0; k < nsteps; ++k) PINT_TRY(sp_cn(p, *f, st, &st, k ? out : in, out, B, s));
+    return PINT_OK;
+  }
+  PINT_TRY(sp_cn_prep(p, *f, st, in, B, s));
   for (int k = 0; k < nsteps; ++k) {
-    PINT_TRY(cn_apply(p, *f, st.dt, st.terms & ~PINT_T_VISC, st.visc_order, 0.0, uw, p.Ua, B, s));
-    const double* uc = p.Ua;
-    if (nl) {
-      PINT_TRY(nl_eval(p, p.Ua, p.Ub, p.Ua, p.N1, st.dt, 1, B, s));
-      PINT_TRY(nl_eval(p, p.Ub, p.Ub, p.Ua, p.N1, st.dt, 2, B, s));
-      uc = p.Ub;
-    }
-    PINT_TRY(cn_apply(p, *f, st.dt, st.terms, st.visc_order, st.visc_nu, uc, uw, B, s));
+    PINT_TRY(legendre_synth(p, B, kSynFields, s));
+    PINT_TRY(ring_tendency(p, B, s));
+    PINT_TRY(legendre_anal(p, B, kAnaFields, s));
+    PINT_TRY(sp_stage1(p, st.dt, B, s));
+    PINT_TRY(legendre_synth(p, B, kSynFields, s));
+    PINT_TRY(ring_tendency(p, B, s));
+    PINT_TRY(legendre_anal(p, B, kAnaFields, s));
+    PINT_TRY(sp_stage2(p, *f, st, out, k + 1 < nsteps, B, s));
   }
   return PINT_OK;
 }
@@ -65,9 +79,7 @@ static pint_status propagate(Plan& p, const pint_stepper& st, const double* in, 
   const size_t sd = (size_t)3 * p.ncoef * 2;
   for (int b0 = 0; b0 < B; b0 += p.max_batch) {
     const int nb = (B - b0) < p.max_batch ? (B - b0) : p.max_batch;
-    PINT_TRY(to_work(p, in + b0 * sd, p.Uw, nb, s));
-    PINT_TRY(imex_steps(p, st, p.Uw, nb, nsteps, s));
-    PINT_TRY(from_work(p, p.Uw, out + b0 * sd, nb, s));
+    PINT_TRY(imex_steps(p, st, in + b0 * sd, out + b0 * sd, nb, nsteps, s));
   }
   return PINT_OK;
 }
@@ -304,9 +316,11 @@ pint_status pint_tendency(pint_plan* plan, const double* u, double* n_out, int B
   const size_t sd = (size_t)3 * p.ncoef * 2;
   for (int b0 = 0; b0 < B; b0 += p.max_batch) {
     const int nb = (B - b0) < p.max_batch ? (B - b0) : p.max_batch;
-    PINT_TRY(to_work(p, u + b0 * sd, p.Uw, nb, s));
-    PINT_TRY(nl_eval(p, p.Uw, p.Ua, nullptr, nullptr, 0.0, 0, nb, s));
-    PINT_TRY(from_work(p, p.Ua, n_out + b0 * sd, nb, s));
+    PINT_TRY(sp_prep(p, u + b0 * sd, nb, s));
+    PINT_TRY(legendre_synth(p, nb, kSynFields, s));
+    PINT_TRY(ring_tendency(p, nb, s));
+    PINT_TRY(legendre_anal(p, nb, kAnaFields, s));
+    PINT_TRY(sp_tend(p, n_out + b0 * sd, nb, s));
   }
   return PINT_OK;
 }
@@ -323,9 +337,7 @@ pint_status pint_implicit(pint_plan* plan, const pint_stepper* st, const double*
   const size_t sd = (size_t)3 * p.ncoef * 2;
   for (int b0 = 0; b0 < B; b0 += p.max_batch) {
     const int nb = (B - b0) < p.max_batch ? (B - b0) : p.max_batch;
-    PINT_TRY(to_work(p, u + b0 * sd, p.Uw, nb, s));
-    PINT_TRY(cn_apply(p, *f, st->dt, st->terms, st->visc_order, st->visc_nu, p.Uw, p.Ua, nb, s));
-    PINT_TRY(from_work(p, p.Ua, x + b0 * sd, nb, s));
+    PINT_TRY(sp_cn(p, *f, *st, nullptr, u + b0 * sd, x + b0 * sd, nb, s));
   }
   return PINT_OK;
 }

@@ -10,39 +10,35 @@
 //   analysis:  Q[row(p,r)][c] = sum_jn T[row(p,r)][jn] *
 //                               (G[m][jn][c] + (-1)^par G[m][nlat-1-jn][c])
 //
-// T is the row-space table [nrows][nlat2].  Reduction order over k is fixed
-// and independent of the column tiling and tile width, so results are
-// batch-invariant.
+// A tile always covers both parities of its m, so the E/O combination costs
+// no extra loads.  T is the row-space table [nrows][nlat2] (synthesis) or its
+// transpose [nlat2][nrows] (analysis: rows contiguous).  Reduction order over
+// k is fixed and independent of the tiling, so results are batch-invariant.
 #include "pint_internal.h"
 
 namespace pint {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// Tile: TR = 64 rows x TC columns (TC = 64 for batched launches, 16 for the
-// latency-bound single-state launches of the serial coarse sweep), k-slabs of
-// TK = 16 double-buffered in LDS: the next slab is fetched into registers while the
-// matrix cores work on the current one, one barrier per slab.  The matrix
-// cores consume k in steps of 4 in increasing order whatever TK and TC are,
-// so every launch shape gives bitwise the same sums.
-// A synthesis tile covers both parities of its m (two accumulators) and its
-// epilogue writes the latitude pairs: F[m][j] = E + O (north, j < nlat/2),
-// F[m][nlat-1-j] = E - O (south).
-template <bool kSynth, int TR, int TC, int TK>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_legendre(
-                                                  const double* __restrict__ T,
-                                                  const int* __restrict__ rowoff,
-                                                  const int* __restrict__ tiles,
-                                                  const double* __restrict__ Bsrc,
-                                                  double* __restrict__ C, int nlat, int nlat2,
-                                                  int ncol) {
+// Synthesis tile: TR = 64 latitudes x TC columns (TC = 64 for batched
+// launches, 16 for the latency-bound single-state launches of the serial
+// coarse sweep), k-slabs of TK = 16 double-buffered in LDS: the next slab is
+// fetched into registers while the matrix cores work on the current one, one
+// barrier per slab.  A tile runs both parities of its m through one slab
+// pipeline into two accumulators, and its epilogue writes the latitude pairs
+// F[m][j] = E + O (north, j < nlat/2) and F[m][nlat-1-j] = E - O (south).
+// The matrix cores consume k in steps of 4 in increasing order whatever TC
+// is, so every launch shape gives bitwise the same sums.
+template <int TR, int TC, int TK>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_legendre_synth(
+    const double* __restrict__ T, const int* __restrict__ rowoff, const int* __restrict__ tiles,
+    const double* __restrict__ S, double* __restrict__ F, int nlat, int nlat2, int ncol) {
   constexpr int LDA = TR + 2, LDB = TC + 2;
   constexpr int NA = TK * TR / 256;                  // A elements per thread per slab
   constexpr int NB = TK * TC / 256;                  // B elements per thread per slab
   constexpr int WC = TC == 64 ? 2 : 1;               // waves across columns
   constexpr int WR = 4 / WC;                         // waves across rows
   constexpr int BI = TR / WR / 16, BJ = TC / WC / 16;  // MFMA blocks per wave
-  constexpr int NPAR = kSynth ? 2 : 1;               // parities per tile
   static_assert(BI >= 1 && BJ >= 1 && NA >= 1 && NB >= 1, "tile shape");
   __shared__ double As[2][TK * LDA];
   __shared__ double Bs[2][TK * LDB];
@@ -53,9 +49,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int nct = (ncol + TC - 1) / TC;
   const int rt = lb / nct;
-  const int p0 = tiles[2 * rt];
+  const int m = tiles[2 * rt] >> 1;
   const int row0 = tiles[2 * rt + 1];
-  const int m = p0 >> 1;
   const int col0 = (lb - rt * nct) * TC;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -63,71 +58,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int li = lane & 15, lk = lane >> 4;
   const size_t gbase = (size_t)m * nlat;
 
-  v4d acc[NPAR][BI][BJ];
+  v4d acc[2][BI][BJ];
 #pragma unroll
-  for (int q = 0; q < NPAR; ++q)
+  for (int q = 0; q < 2; ++q)
 #pragma unroll
     for (int i = 0; i < BI; ++i)
 #pragma unroll
       for (int j = 0; j < BJ; ++j) acc[q][i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
 
-  // slabs of the tile: parity 0 then (synthesis) parity 1, one pipeline
-  const int roff0 = rowoff[kSynth ? 2 * m : p0];
-  const int cnt0 = rowoff[(kSynth ? 2 * m : p0) + 1] - roff0;
-  const int K0 = kSynth ? cnt0 : nlat2;
-  const int ns0 = (K0 + TK - 1) / TK;
-  int roff1 = 0, K1 = 0, ns1 = 0;
-  if constexpr (kSynth) {
-    roff1 = rowoff[2 * m + 1];
-    K1 = rowoff[2 * m + 2] - roff1;
-    ns1 = (K1 + TK - 1) / TK;
-  }
-  const int R = kSynth ? nlat2 : cnt0;
-  const double sgn = (p0 & 1) ? -1.0 : 1.0;          // analysis: parity of the problem
+  // k-slabs: the even rows' slabs, then the odd rows'
+  const int roff0 = rowoff[2 * m], K0 = rowoff[2 * m + 1] - roff0;
+  const int roff1 = rowoff[2 * m + 1], K1 = rowoff[2 * m + 2] - roff1;
+  const int ns0 = (K0 + TK - 1) / TK, ns1 = (K1 + TK - 1) / TK;
+  const int nslab = ns0 + ns1;
   double ra[NA], rb[NB];
   auto fetch = [&](int sl) {
-    const bool second = kSynth && sl >= ns0;
+    const bool second = sl >= ns0;
     const int roff = second ? roff1 : roff0;
     const int K = second ? K1 : K0;
     const int k0 = (second ? sl - ns0 : sl) * TK;
 #pragma unroll
     for (int e4 = 0; e4 < NA; ++e4) {
       const int e = tid + e4 * 256;
-      double v = 0.0;
-      if (kSynth) {
-        const int kk = e / TR, rr = e % TR;
-        const int k = k0 + kk, r = row0 + rr;
-        if (k < K && r < R) v = T[(size_t)(roff + k) * nlat2 + r];
-      } else {
-        const int rr = e / TK, kk = e % TK;
-        const int k = k0 + kk, r = row0 + rr;
-        if (k < K && r < R) v = T[(size_t)(roff + r) * nlat2 + k];
-      }
-      ra[e4] = v;
+      const int kk = e / TR, rr = e % TR;              // lanes along the latitudes
+      const int k = k0 + kk, r = row0 + rr;
+      ra[e4] = (k < K && r < nlat2) ? T[(size_t)(roff + k) * nlat2 + r] : 0.0;
     }
 #pragma unroll
     for (int e4 = 0; e4 < NB; ++e4) {
       const int e = tid + e4 * 256;
       const int kk = e / TC, cc = e % TC;
       const int k = k0 + kk, c = col0 + cc;
-      double v = 0.0;
-      if (k < K && c < ncol) {
-        if (kSynth)
-          v = Bsrc[(size_t)(roff + k) * ncol + c];
-        else
-          v = Bsrc[(gbase + k) * ncol + c] + sgn * Bsrc[(gbase + (nlat - 1 - k)) * ncol + c];
-      }
-      rb[e4] = v;
+      rb[e4] = (k < K && c < ncol) ? S[(size_t)(roff + k) * ncol + c] : 0.0;
     }
   };
   auto stash = [&](int buf) {
 #pragma unroll
     for (int e4 = 0; e4 < NA; ++e4) {
       const int e = tid + e4 * 256;
-      if (kSynth)
-        As[buf][(e / TR) * LDA + (e % TR)] = ra[e4];
-      else
-        As[buf][(e % TK) * LDA + (e / TK)] = ra[e4];
+      As[buf][(e / TR) * LDA + (e % TR)] = ra[e4];
     }
 #pragma unroll
     for (int e4 = 0; e4 < NB; ++e4) {
@@ -151,7 +120,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
   };
 
-  const int nslab = ns0 + ns1;
   if (nslab > 0) {
     fetch(0);
     stash(0);
@@ -159,7 +127,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   __syncthreads();
   // parity 0 slabs (the last one prefetches parity 1's first), then parity 1
 #pragma unroll
-  for (int q = 0; q < NPAR; ++q) {
+  for (int q = 0; q < 2; ++q) {
     for (int sl = q ? ns0 : 0; sl < (q ? nslab : ns0); ++sl) {
       const int cur = sl & 1;
       if (sl + 1 < nslab) fetch(sl + 1);
@@ -178,49 +146,172 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = row0 + wr + bi * 16 + lk + 4 * i;
-        if constexpr (kSynth) {
-          if (r < nlat2 && c < ncol) {
-            const double e = acc[0][bi][bj][i], o = acc[NPAR - 1][bi][bj][i];
-            C[(gbase + r) * ncol + c] = e + o;
-            C[(gbase + (nlat - 1 - r)) * ncol + c] = e - o;
-          }
-        } else {
-          const int cnt = rowoff[p0 + 1] - rowoff[p0];
-          if (r < cnt && c < ncol) C[(size_t)(rowoff[p0] + r) * ncol + c] = acc[0][bi][bj][i];
+        if (r < nlat2 && c < ncol) {
+          const double e = acc[0][bi][bj][i], o = acc[1][bi][bj][i];
+          F[(gbase + r) * ncol + c] = e + o;
+          F[(gbase + (nlat - 1 - r)) * ncol + c] = e - o;
         }
       }
     }
   }
 }
 
-// Synthesis rows are the nlat/2 latitudes; analysis rows are the ragged
-// n-range of one (m, parity).  Single-state launches use 64 x 16 tiles,
-// batched ones 64 x 64 tiles.  Every shape reduces over k in the same order.
-template <bool kSynth>
-static pint_status launch_legendre(Plan& p, const GemmTiles& narrow, const GemmTiles& wide,
-                                   const double* Bsrc, double* C, int ncol, hipStream_t s) {
-  constexpr int TRW = kSynth ? kGemmTR : kGemmTRAnal;
+// Analysis tile: TR2 = 32 rows of each parity of one m (64 rows in all) x TC
+// columns.  Both parities contract over the same northern latitudes k with
+// B_E = G(k) + G(nlat-1-k) and B_O = G(k) - G(nlat-1-k), formed from one load
+// of each pair.  The row-wave groups of the first half of the tile take the
+// even rows, the others the odd rows.  Per output element the matrix cores
+// consume k in steps of 4 in increasing order, as in every other shape.
+template <int TC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_legendre_anal(
+    const double* __restrict__ Tt, const int* __restrict__ rowoff, const int* __restrict__ tiles,
+    const double* __restrict__ G, double* __restrict__ Q, int nlat, int nlat2, int ncol,
+    int nrows) {
+  constexpr int TK = kGemmTK, TR2 = 32, TR = 2 * TR2;
+  constexpr int LDA = TR + 2, LDB = TC + 2;
+  constexpr int NA = TK * TR / 256;                  // A elements per thread per slab
+  constexpr int NB = TK * TC / 256;                  // G pairs per thread per slab
+  constexpr int WC = TC >= 32 ? TC / 32 : 1;         // waves across columns
+  constexpr int WR = 4 / WC;                         // waves across rows
+  constexpr int BI = TR / WR / 16, BJ = TC / WC / 16;
+  static_assert(BI >= 1 && BJ >= 1 && NA >= 1 && NB >= 1 && (TR / WR) <= TR2, "tile shape");
+  __shared__ double As[2][TK * LDA];
+  __shared__ double Bs[2][2][TK * LDB];              // [buffer][parity]
+
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int nct = (ncol + TC - 1) / TC;
+  const int rt = lb / nct;
+  const int m = tiles[2 * rt] >> 1;
+  const int row0 = tiles[2 * rt + 1];
+  const int col0 = (lb - rt * nct) * TC;
+  const int roffE = rowoff[2 * m], cntE = rowoff[2 * m + 1] - roffE;
+  const int roffO = rowoff[2 * m + 1], cntO = rowoff[2 * m + 2] - roffO;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave / WC) * (TR / WR), wc = (wave % WC) * (TC / WC);
+  const int par = wr >= TR2;                         // uniform per wave
+  const int li = lane & 15, lk = lane >> 4;
+  const size_t gbase = (size_t)m * nlat;
+
+  v4d acc[BI][BJ];
+#pragma unroll
+  for (int i = 0; i < BI; ++i)
+#pragma unroll
+    for (int j = 0; j < BJ; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+
+  double ra[NA], rbe[NB], rbo[NB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int e4 = 0; e4 < NA; ++e4) {
+      const int e = tid + e4 * 256;
+      const int kk = e / TR, ri = e % TR;
+      const int k = k0 + kk;
+      const bool odd = ri >= TR2;
+      const int r = row0 + (odd ? ri - TR2 : ri);
+      double v = 0.0;
+      if (k < nlat2 && r < (odd ? cntO : cntE))
+        v = Tt[(size_t)k * nrows + (odd ? roffO : roffE) + r];
+      ra[e4] = v;
+    }
+#pragma unroll
+    for (int e4 = 0; e4 < NB; ++e4) {
+      const int e = tid + e4 * 256;
+      const int kk = e / TC, cc = e % TC;
+      const int k = k0 + kk, c = col0 + cc;
+      double ve = 0.0, vo = 0.0;
+      if (k < nlat2 && c < ncol) {
+        const double gn = G[(gbase + k) * ncol + c];
+        const double gs = G[(gbase + (nlat - 1 - k)) * ncol + c];
+        ve = gn + gs;
+        vo = gn + (-1.0) * gs;
+      }
+      rbe[e4] = ve;
+      rbo[e4] = vo;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int e4 = 0; e4 < NA; ++e4) {
+      const int e = tid + e4 * 256;
+      As[buf][(e / TR) * LDA + (e % TR)] = ra[e4];
+    }
+#pragma unroll
+    for (int e4 = 0; e4 < NB; ++e4) {
+      const int e = tid + e4 * 256;
+      Bs[buf][0][(e / TC) * LDB + (e % TC)] = rbe[e4];
+      Bs[buf][1][(e / TC) * LDB + (e % TC)] = rbo[e4];
+    }
+  };
+  const int nslab = (nlat2 + TK - 1) / TK;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int sl = 0; sl < nslab; ++sl) {
+    const int cur = sl & 1;
+    if (sl + 1 < nslab) fetch((sl + 1) * TK);
+    const double* bs = Bs[cur][par];
+#pragma unroll
+    for (int ks = 0; ks < TK; ks += 4) {
+      double a[BI], b[BJ];
+#pragma unroll
+      for (int i = 0; i < BI; ++i) a[i] = As[cur][(ks + lk) * LDA + wr + 16 * i + li];
+#pragma unroll
+      for (int j = 0; j < BJ; ++j) b[j] = bs[(ks + lk) * LDB + wc + 16 * j + li];
+#pragma unroll
+      for (int i = 0; i < BI; ++i)
+#pragma unroll
+        for (int j = 0; j < BJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (sl + 1 < nslab) stash(cur ^ 1);
+    __syncthreads();
+  }
+  const int roff = par ? roffO : roffE, cnt = par ? cntO : cntE;
+  const int wrp = wr - par * TR2;                    // row offset within the parity
+#pragma unroll
+  for (int bi = 0; bi < BI; ++bi) {
+#pragma unroll
+    for (int bj = 0; bj < BJ; ++bj) {
+      const int c = col0 + wc + bj * 16 + li;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = row0 + wrp + bi * 16 + lk + 4 * i;
+        if (r < cnt && c < ncol) Q[(size_t)(roff + r) * ncol + c] = acc[bi][bj][i];
+      }
+    }
+  }
+}
+
+pint_status legendre_synth(Plan& p, int B, int nf, hipStream_t s) {
+  ProfScope ps(p, PK_SYNTH, nf == kSynFields ? B : -B, s);
+  const int ncol = 2 * nf * B;
   if (ncol <= 32) {
-    dim3 grid(((ncol + 15) / 16) * narrow.count);
-    hipLaunchKernelGGL((k_legendre<kSynth, kGemmTR, 16, kGemmTK>), grid, dim3(256), 0, s,
-                       p.ptab, p.rowoff, narrow.dev, Bsrc, C, p.nlat, p.nlat2, ncol);
+    dim3 grid(((ncol + 15) / 16) * p.syn_tiles.count);
+    hipLaunchKernelGGL((k_legendre_synth<kGemmTR, 16, kGemmTK>), grid, dim3(256), 0, s, p.ptab,
+                       p.rowoff, p.syn_tiles.dev, p.S, p.F, p.nlat, p.nlat2, ncol);
   } else {
-    dim3 grid(((ncol + 63) / 64) * wide.count);
-    hipLaunchKernelGGL((k_legendre<kSynth, TRW, 64, kGemmTK>), grid, dim3(256), 0, s, p.ptab,
-                       p.rowoff, wide.dev, Bsrc, C, p.nlat, p.nlat2, ncol);
+    dim3 grid(((ncol + 63) / 64) * p.syn_tiles.count);
+    hipLaunchKernelGGL((k_legendre_synth<kGemmTR, 64, kGemmTK>), grid, dim3(256), 0, s, p.ptab,
+                       p.rowoff, p.syn_tiles.dev, p.S, p.F, p.nlat, p.nlat2, ncol);
   }
   PINT_HIP(hipGetLastError());
   return PINT_OK;
 }
 
-pint_status legendre_synth(Plan& p, int B, int nf, hipStream_t s) {
-  ProfScope ps(p, PK_SYNTH, nf == kSynFields ? B : -B, s);
-  return launch_legendre<true>(p, p.syn_tiles, p.syn_tiles, p.S, p.F, 2 * nf * B, s);
-}
-
 pint_status legendre_anal(Plan& p, int B, int nf, hipStream_t s) {
   ProfScope ps(p, PK_ANAL, nf == kAnaFields ? B : -B, s);
-  return launch_legendre<false>(p, p.ana_tiles64, p.ana_tiles, p.G, p.Q, 2 * nf * B, s);
+  const int ncol = 2 * nf * B;
+  if (ncol <= 32) {
+    dim3 grid(((ncol + 15) / 16) * p.ana_tiles.count);
+    hipLaunchKernelGGL(k_legendre_anal<16>, grid, dim3(256), 0, s, p.ptabT, p.rowoff,
+                       p.ana_tiles.dev, p.G, p.Q, p.nlat, p.nlat2, ncol, p.nrows);
+  } else {
+    dim3 grid(((ncol + 63) / 64) * p.ana_tiles.count);
+    hipLaunchKernelGGL(k_legendre_anal<64>, grid, dim3(256), 0, s, p.ptabT, p.rowoff,
+                       p.ana_tiles.dev, p.G, p.Q, p.nlat, p.nlat2, ncol, p.nrows);
+  }
+  PINT_HIP(hipGetLastError());
+  return PINT_OK;
 }
 
 }  // namespace pint

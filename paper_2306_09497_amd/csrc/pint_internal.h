@@ -30,7 +30,7 @@ constexpr int kSynFields = 6;
 constexpr int kAnaFields = 4;
 constexpr int kMaxNlon = 1024;
 constexpr int kGemmTR = 64;      // Legendre GEMM tile rows (synthesis)
-constexpr int kGemmTRAnal = 64;  // Legendre GEMM tile rows (analysis)
+constexpr int kGemmTRAnal = 32;  // Legendre GEMM tile rows per parity (analysis)
 constexpr int kGemmTC = 64;      // Legendre GEMM tile columns
 constexpr int kGemmTK = 16;      // Legendre GEMM k-slab staged in LDS
 constexpr int kRingThreads = 512;
@@ -80,23 +80,21 @@ struct Plan {
   double* w = nullptr;         // [nlat]
   double* c2 = nullptr;        // [nlat] 1 - mu^2 (= sin^2 colatitude)
   double* ptab = nullptr;      // [nrows][nlat2] Pbar_n^m(mu_j), north half
+  double* ptabT = nullptr;     // [nlat2][nrows] the same table transposed (analysis GEMM)
   int* rowoff = nullptr;       // [2(M+1)+1] device copy
   int* rowinfo = nullptr;      // [nrows] packed (m << 16 | n)
   int* coefmn = nullptr;       // [ncoef] packed (m << 16 | n)
   double2* twid = nullptr;     // [nlon] exp(-2 pi i t / nlon)
   double4* cnco = nullptr;     // [ncoef] linear-operator coefficients (A/W, B/W, C/W, n(n+1)/a^2)
   std::vector<int> h_rowoff;   // host copy
-  GemmTiles syn_tiles, ana_tiles, ana_tiles64;
+  GemmTiles syn_tiles, ana_tiles;
   // workspace (sized for max_batch)
   double* S = nullptr;         // [nrows][12 B]   synthesis GEMM input
   double* F = nullptr;         // [(M+1) nlat][12 B] synthesis output (Fourier coefficients)
   double* G = nullptr;         // [(M+1) nlat][8 B] ring output
   double* Q = nullptr;         // [nrows][8 B]    analysis output
-  double* Uw = nullptr;        // work-layout states, 5 buffers of [ncoef][B][3] complex
-  double* Ua = nullptr;
-  double* Ub = nullptr;
-  double* N1 = nullptr;
-  double* T0 = nullptr;
+  double* Ua = nullptr;        // states [B][3][ncoef] complex: first half-step result
+  double* N1 = nullptr;        //   and first-stage tendencies of the IMEX step
   double* red = nullptr;       // reduction scratch
   double* h_red = nullptr;     // pinned host mirror
   size_t ws_bytes = 0;
@@ -138,18 +136,26 @@ void destroy(pint_plan* pp);
 pint_status build_tables(Plan& p, hipStream_t s);
 pint_status cn_factors(Plan& p, double dt, unsigned terms, hipStream_t s, const CnFactors** out);
 
-// layout conversion: public [B][3][ncoef] <-> work [ncoef][B][3] (complex)
-pint_status to_work(Plan& p, const double* pub, double* work, int B, hipStream_t s);
-pint_status from_work(Plan& p, const double* work, double* pub, int B, hipStream_t s);
-
-// nonlinear evaluation on work-layout states; stage: 0 = write N to out,
-// 1 = N1 := N, out := ua + dt N, 2 = out := ua + dt/2 (N1 + N)
-pint_status nl_eval(Plan& p, const double* u, double* out, const double* ua, double* n1,
-                    double dt, int stage, int B, hipStream_t s);
-pint_status cn_apply(Plan& p, const CnFactors& f, double dt, unsigned terms, int q, double nu,
-                     const double* y, double* x, int B, hipStream_t s);
-pint_status imex_steps(Plan& p, const pint_stepper& st, double* uw, int B, int nsteps,
-                       hipStream_t s);
+// Spectral kernels on public-layout states (one wave per (m, state)):
+//  sp_cn_prep  Ua = CN(in) (no viscosity); S = synthesis input of Ua
+//  sp_stage1   N1 = N(Q); S = synthesis input of Ua + dt N1
+//  sp_stage2   U = D_nu CN(Ua + dt/2 (N1 + N(Q))); chain: Ua = CN(U), S from
+//              Ua (the next step begins); else out = U
+//  sp_prep     S = synthesis input of in;  sp_tend  out = N(Q)
+//  sp_cn       out = CN(in) with st0 (and its viscosity); with st1, st0's
+//              half step without viscosity then st1's with it
+pint_status sp_cn_prep(Plan& p, const CnFactors& f, const pint_stepper& st, const double* in,
+                       int B, hipStream_t s);
+pint_status sp_stage1(Plan& p, double dt, int B, hipStream_t s);
+pint_status sp_stage2(Plan& p, const CnFactors& f, const pint_stepper& st, double* out,
+                      bool chain, int B, hipStream_t s);
+pint_status sp_prep(Plan& p, const double* in, int B, hipStream_t s);
+pint_status sp_tend(Plan& p, double* out, int B, hipStream_t s);
+pint_status sp_cn(Plan& p, const CnFactors& f, const pint_stepper& st0, const pint_stepper* st1,
+                  const double* in, double* out, int B, hipStream_t s);
+// nsteps IMEX steps of B <= max_batch public-layout states (out may alias in)
+pint_status imex_steps(Plan& p, const pint_stepper& st, const double* in, double* out, int B,
+                       int nsteps, hipStream_t s);
 
 // transforms on the GEMM workspace
 pint_status legendre_synth(Plan& p, int B, int nf, hipStream_t s);

@@ -2,6 +2,7 @@
 // (Gauss nodes/weights, normalised associated Legendre functions, FFT
 // twiddles), Crank-Nicolson tridiagonal factors, and the workspace.
 #include <math.h>
+#include <algorithm>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -79,8 +80,8 @@ __global__ void k_gauss(int nlat, double* mu, double* w, double* c2) {
 //   Pbar_{m+1}^m = sqrt(2m+3) mu Pbar_m^m,
 //   Pbar_n^m = (mu Pbar_{n-1}^m - eps_{n-1}^m Pbar_{n-2}^m) / eps_n^m,
 //   eps_n^m = sqrt((n^2 - m^2) / (4 n^2 - 1)).
-__global__ void k_ptab(int M, int nlat2, const double* mu, const double* c2, const int* rowoff,
-                       double* ptab) {
+__global__ void k_ptab(int M, int nlat2, int nrows, const double* mu, const double* c2,
+                       const int* rowoff, double* ptab, double* ptabT) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int m = blockIdx.y;
   if (j >= nlat2) return;
@@ -92,7 +93,11 @@ __global__ void k_ptab(int M, int nlat2, const double* mu, const double* c2, con
   double pprev = pmm;                  // n - 2
   double pcur = sqrt(2.0 * m + 3.0) * x * pmm;  // n - 1 (= m + 1)
   ptab[(size_t)o0 * nlat2 + j] = pmm;
-  if (m + 1 <= M + 1) ptab[(size_t)o1 * nlat2 + j] = pcur;
+  ptabT[(size_t)j * nrows + o0] = pmm;
+  if (m + 1 <= M + 1) {
+    ptab[(size_t)o1 * nlat2 + j] = pcur;
+    ptabT[(size_t)j * nrows + o1] = pcur;
+  }
   for (int n = m + 2; n <= M + 1; ++n) {
     const double e1 = sqrt(((double)(n - 1) * (n - 1) - (double)m * m) /
                            (4.0 * (n - 1) * (n - 1) - 1.0));
@@ -101,6 +106,7 @@ __global__ void k_ptab(int M, int nlat2, const double* mu, const double* c2, con
     const int par = (n - m) & 1;
     const int row = (par ? o1 : o0) + ((n - m - par) >> 1);
     ptab[(size_t)row * nlat2 + j] = pn;
+    ptabT[(size_t)j * nrows + row] = pn;
     pprev = pcur;
     pcur = pn;
   }
@@ -145,9 +151,9 @@ static pint_status dalloc(T** ptr, size_t count, size_t* total) {
   } while (0)
 
 static void free_plan(Plan& p) {
-  void* ptrs[] = {p.mu, p.w, p.c2, p.ptab, p.rowoff, p.rowinfo, p.coefmn, p.twid, p.cnco,
-                  p.syn_tiles.dev, p.ana_tiles.dev, p.ana_tiles64.dev, p.S, p.F, p.G, p.Q, p.Uw, p.Ua, p.Ub,
-                  p.N1, p.T0, p.red};
+  void* ptrs[] = {p.mu, p.w, p.c2, p.ptab, p.ptabT, p.rowoff, p.rowinfo, p.coefmn, p.twid, p.cnco,
+                  p.syn_tiles.dev, p.ana_tiles.dev, p.S, p.F, p.G, p.Q, p.Ua, p.N1,
+                  p.red};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (p.h_red) (void)hipHostFree(p.h_red);
@@ -169,10 +175,11 @@ static pint_status build_tiles(const std::vector<int>& rowoff, int M, int nlat2,
   std::vector<int> h;
   for (int cls = 0; cls < kNumXcd; ++cls) {
     for (int m = cls; m <= M; m += kNumXcd) {
-      // a synthesis tile covers both parities of m (listed as p = 2m)
-      for (int par = 0; par < (synth ? 1 : 2); ++par) {
+      // a tile covers both parities of m (listed as p = 2m): synthesis tiles
+      // run over the latitudes, analysis tiles over the longer parity's rows
+      for (int par = 0; par < 1; ++par) {
         const int p = 2 * m + par;
-        const int cnt = rowoff[p + 1] - rowoff[p];
+        const int cnt = std::max(rowoff[p + 1] - rowoff[p], rowoff[p + 2] - rowoff[p + 1]);
         const int R = synth ? nlat2 : cnt;
         if (cnt == 0) continue;
         for (int r0 = 0; r0 < R; r0 += TR) {
@@ -273,6 +280,7 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
   PLAN_TRY(dalloc(&p.w, nlat, &tot));
   PLAN_TRY(dalloc(&p.c2, nlat, &tot));
   PLAN_TRY(dalloc(&p.ptab, (size_t)p.nrows * p.nlat2, &tot));
+  PLAN_TRY(dalloc(&p.ptabT, (size_t)p.nrows * p.nlat2, &tot));
   PLAN_TRY(dalloc(&p.rowoff, p.h_rowoff.size(), &tot));
   PLAN_TRY(dalloc(&p.rowinfo, rowinfo.size(), &tot));
   PLAN_TRY(dalloc(&p.coefmn, coefmn.size(), &tot));
@@ -280,18 +288,14 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
   PLAN_TRY(dalloc(&p.cnco, p.ncoef, &tot));
   PLAN_TRY(build_tiles(p.h_rowoff, M, p.nlat2, true, kGemmTR, &p.syn_tiles, &tot));
   PLAN_TRY(build_tiles(p.h_rowoff, M, p.nlat2, false, kGemmTRAnal, &p.ana_tiles, &tot));
-  PLAN_TRY(build_tiles(p.h_rowoff, M, p.nlat2, false, kGemmTR, &p.ana_tiles64, &tot));
   const size_t B = p.max_batch;
   PLAN_TRY(dalloc(&p.S, (size_t)p.nrows * 12 * B, &tot));
   PLAN_TRY(dalloc(&p.F, (size_t)2 * (M + 1) * p.nlat2 * 12 * B, &tot));
   PLAN_TRY(dalloc(&p.G, (size_t)(M + 1) * nlat * 8 * B, &tot));
   PLAN_TRY(dalloc(&p.Q, (size_t)p.nrows * 8 * B, &tot));
   const size_t sw = (size_t)p.ncoef * B * 3 * 2;
-  PLAN_TRY(dalloc(&p.Uw, sw, &tot));
   PLAN_TRY(dalloc(&p.Ua, sw, &tot));
-  PLAN_TRY(dalloc(&p.Ub, sw, &tot));
   PLAN_TRY(dalloc(&p.N1, sw, &tot));
-  PLAN_TRY(dalloc(&p.T0, sw, &tot));
   PLAN_TRY(dalloc(&p.red, (size_t)8 * B + 64, &tot));
   if (hipHostMalloc((void**)&p.h_red, (8 * B + 64) * sizeof(double), 0) != hipSuccess) {
     free_plan(p);
@@ -317,8 +321,8 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
                           hipMemcpyHostToDevice, s)) != hipSuccess)
     return fail_hip(e, "hipMemcpyAsync(coefmn)");
   hipLaunchKernelGGL(k_gauss, dim3((p.nlat2 + 63) / 64), dim3(64), 0, s, nlat, p.mu, p.w, p.c2);
-  hipLaunchKernelGGL(k_ptab, dim3((p.nlat2 + 63) / 64, M + 1), dim3(64), 0, s, M, p.nlat2, p.mu,
-                     p.c2, p.rowoff, p.ptab);
+  hipLaunchKernelGGL(k_ptab, dim3((p.nlat2 + 63) / 64, M + 1), dim3(64), 0, s, M, p.nlat2,
+                     p.nrows, p.mu, p.c2, p.rowoff, p.ptab, p.ptabT);
   hipLaunchKernelGGL(k_twiddle, dim3((nlon + 255) / 256), dim3(256), 0, s, nlon, p.twid);
   hipLaunchKernelGGL(k_cn_coef, dim3((p.ncoef + 255) / 256), dim3(256), 0, s, M, p.ncoef, p.a,
                      p.coefmn, p.cnco);

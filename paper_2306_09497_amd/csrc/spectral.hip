@@ -1,7 +1,7 @@
-// Spectral-space kernels: layout conversion, synthesis-input preparation,
-// tendency assembly with the RK2 stage combine, the Crank-Nicolson solve with
-// fused viscosity, the Parareal/MGRIT correction and the increment norms.
-// All are HBM-bound streaming kernels over the batch-innermost work layout.
+// Spectral-space kernels: the Crank-Nicolson solve with fused viscosity, the
+// synthesis-input preparation and the tendency assembly with the RK2 stage
+// combine, fused per zonal wavenumber; the Parareal/MGRIT correction and the
+// increment norms.  HBM-bound over the public layout [B][3][ncoef].
 #include "pint_internal.h"
 
 namespace pint {
@@ -20,205 +20,25 @@ __device__ inline double2 cimul(double2 x, double s) {   // i * s * x
 }
 
 // ---------------------------------------------------------------------------
-// public [B][3][ncoef] <-> work [ncoef][B][3]; one thread per complex element
+// Spectral kernels.  States are in the public layout [B][3][ncoef] complex.
+// Every kernel runs one 64-lane wave per (zonal wavenumber m, state b); lane l
+// owns the SEG consecutive chain positions i = l*SEG .. l*SEG+SEG-1 of m
+// (i = n - m, K = M - m + 1 positions; positions >= K hold zeros).  The
+// neighbours n-1 and n+1 that the recurrence shifts and the Crank-Nicolson
+// right-hand side need come from the adjacent lanes by shuffles.  The order
+// of every floating-point operation depends on M only, never on B, so results
+// are bitwise batch-invariant.
 // ---------------------------------------------------------------------------
-__global__ void k_to_work(const double* __restrict__ pub, double* __restrict__ work, int ncoef,
-                          int B) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t total = (size_t)ncoef * B * 3;
-  if (t >= total) return;
-  const int f = (int)(t % 3);
-  const size_t r = t / 3;
-  const int b = (int)(r % B);
-  const size_t i = r / B;
-  st2(work, t, ld2(pub, ((size_t)b * 3 + f) * ncoef + i));
+__device__ inline double2 cfma(double2 a, double2 x, double2 b) {   // a x + b
+  return cadd(cmul(a, x), b);
+}
+__device__ inline double2 shfl_up2(double2 v, int d) {
+  return make_double2(__shfl_up(v.x, d, 64), __shfl_up(v.y, d, 64));
+}
+__device__ inline double2 shfl_down2(double2 v, int d) {
+  return make_double2(__shfl_down(v.x, d, 64), __shfl_down(v.y, d, 64));
 }
 
-__global__ void k_from_work(const double* __restrict__ work, double* __restrict__ pub, int ncoef,
-                            int B) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t total = (size_t)ncoef * B * 3;
-  if (t >= total) return;
-  const int i = (int)(t % ncoef);
-  const size_t r = t / ncoef;
-  const int f = (int)(r % 3);
-  const int b = (int)(r / 3);
-  st2(pub, t, ld2(work, ((size_t)i * B + b) * 3 + f));
-}
-
-pint_status to_work(Plan& p, const double* pub, double* work, int B, hipStream_t s) {
-  ProfScope ps(p, PK_LAYOUT, B, s);
-  const size_t total = (size_t)p.ncoef * B * 3;
-  hipLaunchKernelGGL(k_to_work, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, pub, work,
-                     p.ncoef, B);
-  PINT_HIP(hipGetLastError());
-  return PINT_OK;
-}
-
-pint_status from_work(Plan& p, const double* work, double* pub, int B, hipStream_t s) {
-  ProfScope ps(p, PK_LAYOUT, B, s);
-  const size_t total = (size_t)p.ncoef * B * 3;
-  hipLaunchKernelGGL(k_from_work, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, work,
-                     pub, p.ncoef, B);
-  PINT_HIP(hipGetLastError());
-  return PINT_OK;
-}
-
-// ---------------------------------------------------------------------------
-// Synthesis inputs (one thread per (row, b)): the coefficients, on Pbar_n^m
-// for n = m..M+1, of
-//   xi, delta, Phi' (Phi minus the constant Phibar), G = (1-mu^2) dPhi'/dmu,
-//   U = u cos(lat) = (1/a)[d chi/d lambda - (1-mu^2) d psi/d mu],
-//   V = v cos(lat) = (1/a)[d psi/d lambda + (1-mu^2) d chi/d mu],
-// with psi = lap^-1 xi, chi = lap^-1 delta, using
-//   (1-mu^2) d/dmu sum_k c_k Pbar_k = sum_n [-(n-1) eps_n c_{n-1} + (n+2) eps_{n+1} c_{n+1}] Pbar_n
-// (from (1-mu^2) dPbar_n/dmu = -n eps_{n+1} Pbar_{n+1} + (n+1) eps_n Pbar_{n-1}).
-// Output S[row][(b*6 + f)*2 + reim].
-// ---------------------------------------------------------------------------
-__global__ void k_prep(const double* __restrict__ uw, double* __restrict__ S,
-                       const int* __restrict__ rowinfo, int nrows, int M, int B, double a,
-                       double phibar) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (size_t)nrows * B) return;
-  const int b = (int)(t % B);
-  const int row = (int)(t / B);
-  const int mn = rowinfo[row];
-  const int m = mn >> 16, n = mn & 0xffff;
-  auto ld = [&](int nn, int f) -> double2 {
-    if (nn < m || nn > M) return make_double2(0.0, 0.0);
-    return ld2(uw, ((size_t)coef_idx(M, m, nn) * B + b) * 3 + f);
-  };
-  const double2 ph = ld(n, 0), xi = ld(n, 1), de = ld(n, 2);
-  const double2 phm = ld(n - 1, 0), xim = ld(n - 1, 1), dem = ld(n - 1, 2);
-  const double2 php = ld(n + 1, 0), xip = ld(n + 1, 1), dep = ld(n + 1, 2);
-  const double e0 = eps_nm(n, m), e1 = eps_nm(n + 1, m);
-  const double lo = (n - 1) * e0, hi = (n + 2) * e1;
-  const double sm = s_of(n - 1, a), s0 = s_of(n, a), sp = s_of(n + 1, a);
-  double2 php_ = ph;
-  if (m == 0 && n == 0) php_.x -= phibar;
-  const double2 G = cadd(cscale(phm, -lo), cscale(php, hi));
-  // psi_k = s_k xi_k, chi_k = s_k delta_k
-  const double2 psi = cscale(xi, s0), chi = cscale(de, s0);
-  const double2 dpsi = cadd(cscale(xim, -lo * sm), cscale(xip, hi * sp));   // (1-mu^2) dpsi/dmu
-  const double2 dchi = cadd(cscale(dem, -lo * sm), cscale(dep, hi * sp));
-  const double ia = 1.0 / a;
-  const double2 U = cscale(csub(cimul(chi, (double)m), dpsi), ia);
-  const double2 V = cscale(cadd(cimul(psi, (double)m), dchi), ia);
-  double2* out = reinterpret_cast<double2*>(S + ((size_t)row * B + b) * 12);
-  out[0] = xi;
-  out[1] = de;
-  out[2] = php_;
-  out[3] = G;
-  out[4] = U;
-  out[5] = V;
-}
-
-// ---------------------------------------------------------------------------
-// Tendency assembly and RK2 combine (one thread per (idx, b)).  Q holds, per
-// row (m, k <= M+1), the weighted projections
-//   Q_f(k) = sum_j w_j Pbar_k^m(mu_j) f_m(mu_j)  for f = N_Phi, K, A/c^2, B/c^2
-// (A = xi U, B = xi V, c^2 = 1 - mu^2).  Then
-//   N_Phi = Q_NPhi / 2,  K = Q_K / 2,
-//   div  = 1/(2a) [ i m Q_A(n) - (-n eps_{n+1} Q_B(n+1) + (n+1) eps_n Q_B(n-1)) ]
-//   curl = 1/(2a) [ i m Q_B(n) + (-n eps_{n+1} Q_A(n+1) + (n+1) eps_n Q_A(n-1)) ]
-//   N_xi = -div,  N_delta = curl + n(n+1)/a^2 K,   (0,0) of N_xi, N_delta = 0.
-// stage 0: out = N; 1: n1 = N, out = ua + dt N; 2: out = ua + dt/2 (n1 + N).
-// ---------------------------------------------------------------------------
-__global__ void k_assemble(const double* __restrict__ Q, const int* __restrict__ coefmn,
-                           const int* __restrict__ rowoff, int ncoef, int M, int B, double a,
-                           double dt, int stage, const double* __restrict__ ua,
-                           double* __restrict__ n1, double* __restrict__ out) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (size_t)ncoef * B) return;
-  const int b = (int)(t % B);
-  const size_t i = t / B;
-  const int mn = coefmn[i];
-  const int m = mn >> 16, n = mn & 0xffff;
-  auto qrow = [&](int k) -> const double2* {
-    const int par = (k - m) & 1;
-    const int row = rowoff[2 * m + par] + ((k - m - par) >> 1);
-    return reinterpret_cast<const double2*>(Q + ((size_t)row * B + b) * 8);
-  };
-  const double2* q0 = qrow(n);
-  const double2* qp = qrow(n + 1);
-  const double2 zero = make_double2(0.0, 0.0);
-  double2 qAm = zero, qBm = zero;
-  if (n > m) {
-    const double2* qm = qrow(n - 1);
-    qAm = qm[2];
-    qBm = qm[3];
-  }
-  const double e0 = eps_nm(n, m), e1 = eps_nm(n + 1, m);
-  const double ha = 0.5 / a;
-  const double2 nphi = cscale(q0[0], 0.5);
-  const double2 K = cscale(q0[1], 0.5);
-  const double2 hB = cadd(cscale(qp[3], -n * e1), cscale(qBm, (n + 1) * e0));
-  const double2 hA = cadd(cscale(qp[2], -n * e1), cscale(qAm, (n + 1) * e0));
-  const double2 div = cscale(csub(cimul(q0[2], (double)m), hB), ha);
-  const double2 curl = cscale(cadd(cimul(q0[3], (double)m), hA), ha);
-  double2 nxi = cscale(div, -1.0);
-  double2 nde = cadd(curl, cscale(K, (double)n * (n + 1) / (a * a)));
-  if (m == 0 && n == 0) {
-    nxi = zero;
-    nde = zero;
-  }
-  const size_t base = (i * B + b) * 3;
-  const double2 nv[3] = {nphi, nxi, nde};
-  if (stage == 0) {
-    for (int f = 0; f < 3; ++f) st2(out, base + f, nv[f]);
-  } else if (stage == 1) {
-    for (int f = 0; f < 3; ++f) {
-      st2(n1, base + f, nv[f]);
-      st2(out, base + f, cadd(ld2(ua, base + f), cscale(nv[f], dt)));
-    }
-  } else {
-    const double hdt = 0.5 * dt;
-    for (int f = 0; f < 3; ++f)
-      st2(out, base + f, cadd(ld2(ua, base + f), cscale(cadd(ld2(n1, base + f), nv[f]), hdt)));
-  }
-}
-
-pint_status nl_eval(Plan& p, const double* u, double* out, const double* ua, double* n1,
-                    double dt, int stage, int B, hipStream_t s) {
-  {
-    ProfScope ps(p, PK_PREP, B, s);
-    const size_t total = (size_t)p.nrows * B;
-    hipLaunchKernelGGL(k_prep, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, u, p.S,
-                       p.rowinfo, p.nrows, p.M, B, p.a, p.phibar);
-    PINT_HIP(hipGetLastError());
-  }
-  pint_status st = legendre_synth(p, B, kSynFields, s);
-  if (st != PINT_OK) return st;
-  st = ring_tendency(p, B, s);
-  if (st != PINT_OK) return st;
-  st = legendre_anal(p, B, kAnaFields, s);
-  if (st != PINT_OK) return st;
-  {
-    ProfScope ps(p, PK_ASSEMBLE, B, s);
-    const size_t total = (size_t)p.ncoef * B;
-    hipLaunchKernelGGL(k_assemble, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, p.Q,
-                       p.coefmn, p.rowoff, p.ncoef, p.M, B, p.a, dt, stage, ua, n1, out);
-    PINT_HIP(hipGetLastError());
-  }
-  return PINT_OK;
-}
-
-// ---------------------------------------------------------------------------
-// Crank-Nicolson half step (I - alpha L) x = (I + alpha L) y, alpha = dt/4,
-// with the viscosity factor 1/(1 + dt nu (n(n+1)/a^2)^(q/2)) applied to the
-// result (see cn_factors for the chain form).  One 64-lane wave per (m, b):
-//  1. right-hand side r = (I + alpha L) y with Phi eliminated from the delta
-//     rows: (r_Phi, r_xi, r_delta + alpha n(n+1)/a^2 r_Phi);
-//  2. per chain, forward elimination y_i = alph_i y_{i-1} + invpiv_i r_i and
-//     back substitution x_i = gam_i x_{i+1} + y_i.  Each is a first-order
-//     linear recurrence, i.e. a composition of affine maps: lane l composes
-//     the maps of its SEG consecutive positions, an inclusive scan over the
-//     64 lanes (log steps) gives every lane its incoming value, and each lane
-//     then runs its own positions;
-//  3. x_Phi = r_Phi - alpha Phibar x_delta, viscosity, store.
-// The order of operations depends on M only (never on B), so results are
-// batch-invariant.  y and x must not overlap.
-// ---------------------------------------------------------------------------
 __device__ inline double visc_factor(int n, double a, double vdt, double nu, int q) {
   if (!(nu > 0.0)) return 1.0;
   const double l = (double)n * (n + 1) / (a * a);
@@ -227,19 +47,8 @@ __device__ inline double visc_factor(int n, double a, double vdt, double nu, int
   return 1.0 / (1.0 + vdt * nu * pw);
 }
 
-// chain position i of chain c at wavenumber m holds xi if (i even) == (c == 0)
-__device__ inline int chain_slot(int i, int chain) { return (((i & 1) == 0) == (chain == 0)) ? 1 : 2; }
-
-__device__ inline double2 cfma(double2 a, double2 x, double2 b) {   // a x + b
-  return cadd(cmul(a, x), b);
-}
-
-__device__ inline double2 shfl_up2(double2 v, int d) {
-  return make_double2(__shfl_up(v.x, d, 64), __shfl_up(v.y, d, 64));
-}
-__device__ inline double2 shfl_down2(double2 v, int d) {
-  return make_double2(__shfl_down(v.x, d, 64), __shfl_down(v.y, d, 64));
-}
+// chain position i of chain c holds xi if (i even) == (c == 0), else delta
+__device__ inline bool xi_on_chain0(int i) { return (i & 1) == 0; }
 
 // Inclusive scan of affine maps f_l(v) = A_l v + B_l over the 64 lanes:
 // kUp: lane l gets f_l o f_{l-1} o ... o f_0; otherwise f_l o ... o f_63.
@@ -256,78 +65,148 @@ __device__ inline void affine_scan(double2& A, double2& Bv, int lane) {
   }
 }
 
+// Where one wave sits: wavenumber m, state b, chain length K, first packed
+// index i0 of m, the lane and its first position p0.
+struct WaveAt {
+  int m, b, K, i0, lane, p0;
+};
+
+// A workgroup holds kSpecWaves waves: the states b0 .. b0+kSpecWaves-1 of one
+// m, whose rows of S and Q are adjacent in memory.  Logical block m * nbg + bg,
+// XCD-remapped.  A wave past the last state has nothing to do (w.b >= B).
+constexpr int kSpecWaves = 4;
+
 template <int SEG>
-__global__ __launch_bounds__(64) void k_cn_solve(
-    const double* __restrict__ y, double* __restrict__ x, const double4* __restrict__ co,
-    const double2* __restrict__ alph, const double2* __restrict__ gam,
-    const double2* __restrict__ invpiv, int M, int ncoef, int B, double a, double W, double lgf,
-    double pb, double alpha, double vdt, double nu, int q) {
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);    // logical block m * B + b
-  const int m = lb / B, b = lb - m * B;
-  const int K = M - m + 1;
-  const int i0 = coef_idx(M, m, m);
-  const int lane = threadIdx.x;
-  const int p0 = lane * SEG;
-  auto Y = [&](int i, int f) { return ld2(y, ((size_t)(i0 + i) * B + b) * 3 + f); };
+__device__ inline WaveAt wave_at(int M, int B) {
+  WaveAt w;
+  const int nbg = (B + kSpecWaves - 1) / kSpecWaves;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  w.m = lb / nbg;
+  w.b = (lb - w.m * nbg) * kSpecWaves + (int)(threadIdx.x >> 6);
+  w.K = M - w.m + 1;
+  w.i0 = coef_idx(M, w.m, w.m);
+  w.lane = threadIdx.x & 63;
+  w.p0 = w.lane * SEG;
+  return w;
+}
+
+template <int SEG>
+__device__ inline void load_state(const double* __restrict__ u, const WaveAt& w, int ncoef,
+                                  double2 (&V)[SEG][3]) {
+#pragma unroll
+  for (int k = 0; k < SEG; ++k) {
+    const int i = w.p0 + k;
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+      V[k][f] = i < w.K ? ld2(u, ((size_t)w.b * 3 + f) * ncoef + w.i0 + i) : make_double2(0.0, 0.0);
+  }
+}
+
+template <int SEG>
+__device__ inline void store_state(double* __restrict__ u, const WaveAt& w, int ncoef,
+                                   const double2 (&V)[SEG][3]) {
+#pragma unroll
+  for (int k = 0; k < SEG; ++k) {
+    const int i = w.p0 + k;
+    if (i < w.K) {
+#pragma unroll
+      for (int f = 0; f < 3; ++f) st2(u, ((size_t)w.b * 3 + f) * ncoef + w.i0 + i, V[k][f]);
+    }
+  }
+}
+
+// Values of the positions just before and after the lane's segment.
+template <int SEG>
+__device__ inline void edge_neighbours(const double2 (&V)[SEG][3], int lane, double2 (&prev)[3],
+                                       double2 (&next)[3]) {
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    prev[f] = shfl_up2(V[SEG - 1][f], 1);
+    next[f] = shfl_down2(V[0][f], 1);
+    if (lane == 0) prev[f] = make_double2(0.0, 0.0);
+    if (lane == 63) next[f] = make_double2(0.0, 0.0);
+  }
+}
+
+// Crank-Nicolson half step (eq. IMEX_implicit) on the wave's (m, b):
+// (I - alpha L) x = (I + alpha L) y with the factor chains of cn_factors, then
+// the viscosity factor 1/(1 + vdt nu (n(n+1)/a^2)^(q/2)) (nu = 0: none).
+//  1. r = (I + alpha L) y with Phi eliminated from the delta rows:
+//     (r_Phi, r_xi, r_delta + alpha n(n+1)/a^2 r_Phi);
+//  2. per chain, forward elimination y_i = alph_i y_{i-1} + invpiv_i r_i and
+//     back substitution x_i = gam_i x_{i+1} + y_i: each a composition of
+//     affine maps, composed per lane, scanned over the lanes, then finished
+//     per lane;
+//  3. x_Phi = r_Phi - alpha Phibar x_delta and the viscosity factor.
+struct CnArgs {
+  const double4* co;
+  const double2 *alph, *gam, *invpiv;
+  double a, W, lgf, pb, alpha, vdt, nu;
+  int q;
+};
+
+template <int SEG>
+__device__ inline void cn_lane(double2 (&V)[SEG][3], const WaveAt& w, int ncoef,
+                               const CnArgs& c) {
   const double2 zero = make_double2(0.0, 0.0), one = make_double2(1.0, 0.0);
-  // 1. right-hand side of the lane's positions
+  double2 prev[3], next[3];
+  edge_neighbours<SEG>(V, w.lane, prev, next);
   double2 rphi[SEG], rv[2][SEG];
 #pragma unroll
   for (int k = 0; k < SEG; ++k) {
-    const int i = p0 + k;
+    const int i = w.p0 + k;
     rphi[k] = zero;
     rv[0][k] = zero;
     rv[1][k] = zero;
-    if (i < K) {
-      const double4 c = co[i0 + i];
-      const double A = W * c.x, Bc = W * c.y, C = W * c.z, lap = lgf * c.w;
-      const double2 yphi = Y(i, 0), yxi = Y(i, 1), yde = Y(i, 2);
+    const double2 xim = k > 0 ? V[k - 1][1] : prev[1], dem = k > 0 ? V[k - 1][2] : prev[2];
+    const double2 xip = k + 1 < SEG ? V[k + 1][1] : next[1];
+    const double2 dep = k + 1 < SEG ? V[k + 1][2] : next[2];
+    if (i < w.K) {
+      const double4 cf = c.co[w.i0 + i];
+      const double A = c.W * cf.x, Bc = c.W * cf.y, C = c.W * cf.z, lap = c.lgf * cf.w;
+      const double2 yphi = V[k][0], yxi = V[k][1], yde = V[k][2];
       double2 axi = cimul(yxi, Bc), ade = cadd(cscale(yphi, lap), cimul(yde, Bc));
       if (i > 0) {
-        axi = cadd(axi, cscale(Y(i - 1, 2), A));
-        ade = csub(ade, cscale(Y(i - 1, 1), A));
+        axi = cadd(axi, cscale(dem, A));
+        ade = csub(ade, cscale(xim, A));
       }
-      if (i + 1 < K) {
-        axi = cadd(axi, cscale(Y(i + 1, 2), C));
-        ade = csub(ade, cscale(Y(i + 1, 1), C));
+      if (i + 1 < w.K) {
+        axi = cadd(axi, cscale(dep, C));
+        ade = csub(ade, cscale(xip, C));
       }
-      const double2 rxi = cadd(yxi, cscale(axi, alpha));
-      const double2 rde = cadd(yde, cscale(ade, alpha));
-      rphi[k] = csub(yphi, cscale(yde, alpha * pb));
-      const double2 rdp = cadd(rde, cscale(rphi[k], alpha * lap));
-      const bool xi0 = chain_slot(i, 0) == 1;
-      rv[0][k] = xi0 ? rxi : rdp;
-      rv[1][k] = xi0 ? rdp : rxi;
+      const double2 rxi = cadd(yxi, cscale(axi, c.alpha));
+      const double2 rde = cadd(yde, cscale(ade, c.alpha));
+      rphi[k] = csub(yphi, cscale(yde, c.alpha * c.pb));
+      const double2 rdp = cadd(rde, cscale(rphi[k], c.alpha * lap));
+      rv[0][k] = xi_on_chain0(i) ? rxi : rdp;
+      rv[1][k] = xi_on_chain0(i) ? rdp : rxi;
     }
   }
-  // 2. the two chains
 #pragma unroll
   for (int ch = 0; ch < 2; ++ch) {
-    const size_t fb = (size_t)ch * ncoef + i0;
+    const size_t fb = (size_t)ch * ncoef + w.i0;
     double2 al[SEG], be[SEG], ga[SEG];
 #pragma unroll
     for (int k = 0; k < SEG; ++k) {
-      const int i = p0 + k;
-      al[k] = i < K ? alph[fb + i] : one;
-      ga[k] = i < K ? gam[fb + i] : one;
-      be[k] = i < K ? cmul(invpiv[fb + i], rv[ch][k]) : zero;
+      const int i = w.p0 + k;
+      al[k] = i < w.K ? c.alph[fb + i] : one;
+      ga[k] = i < w.K ? c.gam[fb + i] : one;
+      be[k] = i < w.K ? cmul(c.invpiv[fb + i], rv[ch][k]) : zero;
     }
-    // forward: the lane's composite map, scan, then its own positions
     double2 A = one, Bv = zero;
 #pragma unroll
     for (int k = 0; k < SEG; ++k) {
       Bv = cfma(al[k], Bv, be[k]);
       A = cmul(al[k], A);
     }
-    affine_scan<true>(A, Bv, lane);
+    affine_scan<true>(A, Bv, w.lane);
     double2 v = shfl_up2(Bv, 1);
-    if (lane == 0) v = zero;
+    if (w.lane == 0) v = zero;
 #pragma unroll
     for (int k = 0; k < SEG; ++k) {
       v = cfma(al[k], v, be[k]);
-      rv[ch][k] = p0 + k < K ? v : zero;               // y_i
+      rv[ch][k] = w.p0 + k < w.K ? v : zero;          // y_i
     }
-    // backward (positions beyond K keep the identity map and y = 0)
     A = one;
     Bv = zero;
 #pragma unroll
@@ -335,62 +214,376 @@ __global__ __launch_bounds__(64) void k_cn_solve(
       Bv = cfma(ga[k], Bv, rv[ch][k]);
       A = cmul(ga[k], A);
     }
-    affine_scan<false>(A, Bv, lane);
+    affine_scan<false>(A, Bv, w.lane);
     v = shfl_down2(Bv, 1);
-    if (lane == 63) v = zero;
+    if (w.lane == 63) v = zero;
 #pragma unroll
     for (int k = SEG - 1; k >= 0; --k) {
       v = cfma(ga[k], v, rv[ch][k]);
-      rv[ch][k] = v;                                   // x_i
+      rv[ch][k] = v;                                    // x_i
     }
   }
-  // 3. Phi, viscosity, store
 #pragma unroll
   for (int k = 0; k < SEG; ++k) {
-    const int i = p0 + k;
-    if (i < K) {
-      const bool xi0 = chain_slot(i, 0) == 1;
-      const double2 xxi = xi0 ? rv[0][k] : rv[1][k];
-      const double2 xde = xi0 ? rv[1][k] : rv[0][k];
-      const double vf = visc_factor(m + i, a, vdt, nu, q);
-      const double2 xphi = csub(rphi[k], cscale(xde, alpha * pb));
-      const size_t g = ((size_t)(i0 + i) * B + b) * 3;
-      st2(x, g, cscale(xphi, vf));
-      st2(x, g + 1, cscale(xxi, vf));
-      st2(x, g + 2, cscale(xde, vf));
+    const int i = w.p0 + k;
+    if (i < w.K) {
+      const double2 xxi = xi_on_chain0(i) ? rv[0][k] : rv[1][k];
+      const double2 xde = xi_on_chain0(i) ? rv[1][k] : rv[0][k];
+      const double vf = visc_factor(w.m + i, c.a, c.vdt, c.nu, c.q);
+      V[k][0] = cscale(csub(rphi[k], cscale(xde, c.alpha * c.pb)), vf);
+      V[k][1] = cscale(xxi, vf);
+      V[k][2] = cscale(xde, vf);
+    } else {
+      V[k][0] = V[k][1] = V[k][2] = zero;
     }
   }
 }
 
-pint_status cn_apply(Plan& p, const CnFactors& f, double dt, unsigned terms, int q, double nu,
-                     const double* y, double* x, int B, hipStream_t s) {
-  ProfScope ps(p, PK_CN, B, s);
-  const double W = (terms & PINT_T_LC) ? 2.0 * p.omega : 0.0;
-  const bool lg = (terms & PINT_T_LG) != 0;
-  const double pb = lg ? p.phibar : 0.0;
-  const double nuv = (terms & PINT_T_VISC) ? nu : 0.0;
-  const double alpha = dt / 4.0;
-  const int K = p.M + 1;
-  const dim3 grid((unsigned)(K * B));
-#define PINT_CN(SEG)                                                                            \
-  hipLaunchKernelGGL(k_cn_solve<SEG>, grid, dim3(64), 0, s, y, x, p.cnco, f.alph, f.gam,       \
-                     f.invpiv, p.M, p.ncoef, B, p.a, W, lg ? 1.0 : 0.0, pb, alpha, dt, nuv, q)
-  if (K <= 64) {
-    PINT_CN(1);
-  } else if (K <= 128) {
-    PINT_CN(2);
-  } else if (K <= 256) {
-    PINT_CN(4);
-  } else if (K <= 512) {
-    PINT_CN(8);
-  } else {
-    set_error("Crank-Nicolson chains longer than 512 are not supported (M=%d)", p.M);
-    return PINT_E_INVAL;
+// Synthesis inputs (Sec. 2.1-2.2) of the wave's (m, b): the coefficients, on
+// Pbar_n^m for n = m..M+1, of
+//   xi, delta, Phi' (Phi minus the constant Phibar), G = (1-mu^2) dPhi'/dmu,
+//   U = u cos(lat) = (1/a)[d chi/d lambda - (1-mu^2) d psi/d mu],
+//   V = v cos(lat) = (1/a)[d psi/d lambda + (1-mu^2) d chi/d mu],
+// with psi = lap^-1 xi, chi = lap^-1 delta, using
+//   (1-mu^2) d/dmu sum_k c_k Pbar_k = sum_n [-(n-1) eps_n c_{n-1} + (n+2) eps_{n+1} c_{n+1}] Pbar_n
+// (from (1-mu^2) dPbar_n/dmu = -n eps_{n+1} Pbar_{n+1} + (n+1) eps_n Pbar_{n-1}).
+// Row n = M+1 (state zero there) is written by the lane holding n = M.
+// Output S[row][(b*6 + f)*2 + reim].
+__device__ inline void prep_row(double* __restrict__ S, const int* __restrict__ rowoff, int m,
+                                int n, int b, int B, double a, double phibar, const double2* cur,
+                                const double2* pv, const double2* nx) {
+  const double2 xi = cur[1], de = cur[2];
+  double2 ph = cur[0];
+  if (m == 0 && n == 0) ph.x -= phibar;
+  const double e0 = eps_nm(n, m), e1 = eps_nm(n + 1, m);
+  const double lo = (n - 1) * e0, hi = (n + 2) * e1;
+  const double sm = s_of(n - 1, a), s0 = s_of(n, a), sp = s_of(n + 1, a);
+  const double2 G = cadd(cscale(pv[0], -lo), cscale(nx[0], hi));
+  const double2 psi = cscale(xi, s0), chi = cscale(de, s0);
+  const double2 dpsi = cadd(cscale(pv[1], -lo * sm), cscale(nx[1], hi * sp));
+  const double2 dchi = cadd(cscale(pv[2], -lo * sm), cscale(nx[2], hi * sp));
+  const double ia = 1.0 / a;
+  const double2 U = cscale(csub(cimul(chi, (double)m), dpsi), ia);
+  const double2 V = cscale(cadd(cimul(psi, (double)m), dchi), ia);
+  const int par = (n - m) & 1;
+  const int row = rowoff[2 * m + par] + ((n - m - par) >> 1);
+  double2* out = reinterpret_cast<double2*>(S + ((size_t)row * B + b) * 12);
+  out[0] = xi;
+  out[1] = de;
+  out[2] = ph;
+  out[3] = G;
+  out[4] = U;
+  out[5] = V;
+}
+
+template <int SEG>
+__device__ inline void prep_lane(const double2 (&V)[SEG][3], const WaveAt& w, int B,
+                                 double* __restrict__ S, const int* __restrict__ rowoff,
+                                 double a, double phibar) {
+  double2 prev[3], next[3];
+  edge_neighbours<SEG>(V, w.lane, prev, next);
+  const double2 zero3[3] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0),
+                            make_double2(0.0, 0.0)};
+#pragma unroll
+  for (int k = 0; k < SEG; ++k) {
+    const int i = w.p0 + k;
+    if (i < w.K) {
+      const double2* pv = k > 0 ? V[k - 1] : prev;
+      const double2* nx = k + 1 < SEG ? V[k + 1] : next;
+      prep_row(S, rowoff, w.m, w.m + i, w.b, B, a, phibar, V[k], pv, nx);
+      if (i + 1 == w.K) prep_row(S, rowoff, w.m, w.m + w.K, w.b, B, a, phibar, zero3, V[k], zero3);
+    }
   }
-#undef PINT_CN
+}
+
+// Tendencies from the analysis output Q (Sec. 2.1-2.2).  Q holds, per row
+// (m, k <= M+1), the weighted projections
+//   Q_f(k) = sum_j w_j Pbar_k^m(mu_j) f_m(mu_j)  for f = N_Phi, K, A/c^2, B/c^2
+// (A = xi U, B = xi V, c^2 = 1 - mu^2).  Then
+//   N_Phi = Q_NPhi / 2,  K = Q_K / 2,
+//   div  = 1/(2a) [ i m Q_A(n) - (-n eps_{n+1} Q_B(n+1) + (n+1) eps_n Q_B(n-1)) ]
+//   curl = 1/(2a) [ i m Q_B(n) + (-n eps_{n+1} Q_A(n+1) + (n+1) eps_n Q_A(n-1)) ]
+//   N_xi = -div,  N_delta = curl + n(n+1)/a^2 K,   (0,0) of N_xi, N_delta = 0.
+template <int SEG>
+__device__ inline void asm_lane(const double* __restrict__ Q, const int* __restrict__ rowoff,
+                                const WaveAt& w, int B, double a, double2 (&N)[SEG][3]) {
+  const double2 zero = make_double2(0.0, 0.0);
+  const int m = w.m;
+  auto qrow = [&](int k) -> const double2* {
+    const int par = (k - m) & 1;
+    const int row = rowoff[2 * m + par] + ((k - m - par) >> 1);
+    return reinterpret_cast<const double2*>(Q + ((size_t)row * B + w.b) * 8);
+  };
+  const double ha = 0.5 / a;
+#pragma unroll
+  for (int k = 0; k < SEG; ++k) {
+    const int i = w.p0 + k, n = m + i;
+    N[k][0] = N[k][1] = N[k][2] = zero;
+    if (i < w.K) {
+      const double2* q0 = qrow(n);
+      const double2* qp = qrow(n + 1);
+      double2 qAm = zero, qBm = zero;
+      if (n > m) {
+        const double2* qm = qrow(n - 1);
+        qAm = qm[2];
+        qBm = qm[3];
+      }
+      const double e0 = eps_nm(n, m), e1 = eps_nm(n + 1, m);
+      const double2 Kc = cscale(q0[1], 0.5);
+      const double2 hB = cadd(cscale(qp[3], -n * e1), cscale(qBm, (n + 1) * e0));
+      const double2 hA = cadd(cscale(qp[2], -n * e1), cscale(qAm, (n + 1) * e0));
+      const double2 div = cscale(csub(cimul(q0[2], (double)m), hB), ha);
+      const double2 curl = cscale(cadd(cimul(q0[3], (double)m), hA), ha);
+      N[k][0] = cscale(q0[0], 0.5);
+      if (!(m == 0 && n == 0)) {
+        N[k][1] = cscale(div, -1.0);
+        N[k][2] = cadd(curl, cscale(Kc, (double)n * (n + 1) / (a * a)));
+      }
+    }
+  }
+}
+
+struct SpecArgs {
+  const int* rowoff;
+  int M, ncoef, B;
+  double a, phibar;
+};
+
+// K_A: Ua = CN(in); S = synthesis input of Ua.
+template <int SEG>
+__global__ __launch_bounds__(64 * kSpecWaves) void k_sp_cn_prep(const double* __restrict__ in,
+                                                   double* __restrict__ ua, double* __restrict__ S,
+                                                   SpecArgs sa, CnArgs c) {
+  const WaveAt w = wave_at<SEG>(sa.M, sa.B);
+  if (w.b >= sa.B) return;                            // uniform per wave
+  double2 V[SEG][3];
+  load_state<SEG>(in, w, sa.ncoef, V);
+  cn_lane<SEG>(V, w, sa.ncoef, c);
+  store_state<SEG>(ua, w, sa.ncoef, V);
+  prep_lane<SEG>(V, w, sa.B, S, sa.rowoff, sa.a, sa.phibar);
+}
+
+// K_B (first explicit stage): N1 = N(Q); S = synthesis input of Ua + dt N1.
+template <int SEG>
+__global__ __launch_bounds__(64 * kSpecWaves) void k_sp_stage1(const double* __restrict__ Q,
+                                                  const double* __restrict__ ua,
+                                                  double* __restrict__ n1, double* __restrict__ S,
+                                                  double dt, SpecArgs sa) {
+  const WaveAt w = wave_at<SEG>(sa.M, sa.B);
+  if (w.b >= sa.B) return;                            // uniform per wave
+  double2 N[SEG][3], V[SEG][3];
+  asm_lane<SEG>(Q, sa.rowoff, w, sa.B, sa.a, N);
+  store_state<SEG>(n1, w, sa.ncoef, N);
+  load_state<SEG>(ua, w, sa.ncoef, V);
+#pragma unroll
+  for (int k = 0; k < SEG; ++k)
+#pragma unroll
+    for (int f = 0; f < 3; ++f) V[k][f] = cadd(V[k][f], cscale(N[k][f], dt));
+  prep_lane<SEG>(V, w, sa.B, S, sa.rowoff, sa.a, sa.phibar);
+}
+
+// K_C (second explicit stage and the closing half step):
+// U = D_nu CN(Ua + dt/2 (N1 + N(Q))); chain = 0: out = U; chain = 1: the next
+// step's first half step follows at once: ua = CN(U), S = its synthesis input.
+template <int SEG>
+__global__ __launch_bounds__(64 * kSpecWaves) void k_sp_stage2(const double* __restrict__ Q,
+                                                  double* __restrict__ ua,
+                                                  const double* __restrict__ n1,
+                                                  double* __restrict__ out,
+                                                  double* __restrict__ S, double dt, int chain,
+                                                  SpecArgs sa, CnArgs c) {
+  const WaveAt w = wave_at<SEG>(sa.M, sa.B);
+  if (w.b >= sa.B) return;                            // uniform per wave
+  double2 N[SEG][3], V[SEG][3];
+  asm_lane<SEG>(Q, sa.rowoff, w, sa.B, sa.a, N);
+  load_state<SEG>(n1, w, sa.ncoef, V);
+  const double hdt = 0.5 * dt;
+#pragma unroll
+  for (int k = 0; k < SEG; ++k)
+#pragma unroll
+    for (int f = 0; f < 3; ++f) N[k][f] = cadd(V[k][f], N[k][f]);   // N1 + N
+  load_state<SEG>(ua, w, sa.ncoef, V);
+#pragma unroll
+  for (int k = 0; k < SEG; ++k)
+#pragma unroll
+    for (int f = 0; f < 3; ++f) V[k][f] = cadd(V[k][f], cscale(N[k][f], hdt));
+  cn_lane<SEG>(V, w, sa.ncoef, c);                    // with the stepper's viscosity
+  if (chain) {
+    CnArgs c1 = c;
+    c1.nu = 0.0;
+    cn_lane<SEG>(V, w, sa.ncoef, c1);
+    store_state<SEG>(ua, w, sa.ncoef, V);
+    prep_lane<SEG>(V, w, sa.B, S, sa.rowoff, sa.a, sa.phibar);
+  } else {
+    store_state<SEG>(out, w, sa.ncoef, V);
+  }
+}
+
+// Synthesis input of the states in (pint_tendency).
+template <int SEG>
+__global__ __launch_bounds__(64 * kSpecWaves) void k_sp_prep(const double* __restrict__ in,
+                                                double* __restrict__ S, SpecArgs sa) {
+  const WaveAt w = wave_at<SEG>(sa.M, sa.B);
+  if (w.b >= sa.B) return;                            // uniform per wave
+  double2 V[SEG][3];
+  load_state<SEG>(in, w, sa.ncoef, V);
+  prep_lane<SEG>(V, w, sa.B, S, sa.rowoff, sa.a, sa.phibar);
+}
+
+// N(Q) to out (pint_tendency).
+template <int SEG>
+__global__ __launch_bounds__(64 * kSpecWaves) void k_sp_tend(const double* __restrict__ Q,
+                                                double* __restrict__ out, SpecArgs sa) {
+  const WaveAt w = wave_at<SEG>(sa.M, sa.B);
+  if (w.b >= sa.B) return;                            // uniform per wave
+  double2 N[SEG][3];
+  asm_lane<SEG>(Q, sa.rowoff, w, sa.B, sa.a, N);
+  store_state<SEG>(out, w, sa.ncoef, N);
+}
+
+// out = CN(in) (c0), then, if two, out = CN(out) (c1): pint_implicit and the
+// linear-only IMEX step.
+template <int SEG>
+__global__ __launch_bounds__(64 * kSpecWaves) void k_sp_cn(const double* __restrict__ in,
+                                              double* __restrict__ out, int two, SpecArgs sa,
+                                              CnArgs c0, CnArgs c1) {
+  const WaveAt w = wave_at<SEG>(sa.M, sa.B);
+  if (w.b >= sa.B) return;                            // uniform per wave
+  double2 V[SEG][3];
+  load_state<SEG>(in, w, sa.ncoef, V);
+  cn_lane<SEG>(V, w, sa.ncoef, c0);
+  if (two) cn_lane<SEG>(V, w, sa.ncoef, c1);
+  store_state<SEG>(out, w, sa.ncoef, V);
+}
+
+// ---- launchers ----
+static int seg_of(int M) {
+  const int K = M + 1;
+  return K <= 64 ? 1 : K <= 128 ? 2 : K <= 256 ? 4 : K <= 512 ? 8 : 0;
+}
+
+static SpecArgs spec_args(const Plan& p, int B) {
+  SpecArgs sa;
+  sa.rowoff = p.rowoff;
+  sa.M = p.M;
+  sa.ncoef = p.ncoef;
+  sa.B = B;
+  sa.a = p.a;
+  sa.phibar = p.phibar;
+  return sa;
+}
+
+static CnArgs cn_args(const Plan& p, const CnFactors& f, const pint_stepper& st, bool visc) {
+  CnArgs c;
+  c.co = p.cnco;
+  c.alph = f.alph;
+  c.gam = f.gam;
+  c.invpiv = f.invpiv;
+  c.a = p.a;
+  c.W = (st.terms & PINT_T_LC) ? 2.0 * p.omega : 0.0;
+  const bool lg = (st.terms & PINT_T_LG) != 0;
+  c.lgf = lg ? 1.0 : 0.0;
+  c.pb = lg ? p.phibar : 0.0;
+  c.alpha = st.dt / 4.0;
+  c.vdt = st.dt;
+  c.nu = (visc && (st.terms & PINT_T_VISC)) ? st.visc_nu : 0.0;
+  c.q = st.visc_order;
+  return c;
+}
+
+#define PINT_SEG_DISPATCH(launch)                                                   \
+  switch (seg_of(p.M)) {                                                            \
+    case 1: launch(1); break;                                                       \
+    case 2: launch(2); break;                                                       \
+    case 4: launch(4); break;                                                       \
+    case 8: launch(8); break;                                                       \
+    default:                                                                        \
+      set_error("chains longer than 512 coefficients are not supported (M=%d)", p.M); \
+      return PINT_E_INVAL;                                                          \
+  }
+
+pint_status sp_cn_prep(Plan& p, const CnFactors& f, const pint_stepper& st, const double* in,
+                       int B, hipStream_t s) {
+  ProfScope ps(p, PK_CN, B, s);
+  const SpecArgs sa = spec_args(p, B);
+  const CnArgs c = cn_args(p, f, st, false);
+  const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
+#define L(SEG) \
+  hipLaunchKernelGGL(k_sp_cn_prep<SEG>, grid, dim3(64 * kSpecWaves), 0, s, in, p.Ua, p.S, sa, c)
+  PINT_SEG_DISPATCH(L)
+#undef L
   PINT_HIP(hipGetLastError());
   return PINT_OK;
 }
+
+pint_status sp_stage1(Plan& p, double dt, int B, hipStream_t s) {
+  ProfScope ps(p, PK_ASSEMBLE, B, s);
+  const SpecArgs sa = spec_args(p, B);
+  const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
+#define L(SEG)                                                                              \
+  hipLaunchKernelGGL(k_sp_stage1<SEG>, grid, dim3(64 * kSpecWaves), 0, s, p.Q, p.Ua, p.N1, p.S, \
+                     dt, sa)
+  PINT_SEG_DISPATCH(L)
+#undef L
+  PINT_HIP(hipGetLastError());
+  return PINT_OK;
+}
+
+pint_status sp_stage2(Plan& p, const CnFactors& f, const pint_stepper& st, double* out,
+                      bool chain, int B, hipStream_t s) {
+  ProfScope ps(p, PK_ASSEMBLE, B, s);
+  const SpecArgs sa = spec_args(p, B);
+  const CnArgs c = cn_args(p, f, st, true);
+  const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
+#define L(SEG)                                                                                  \
+  hipLaunchKernelGGL(k_sp_stage2<SEG>, grid, dim3(64 * kSpecWaves), 0, s, p.Q, p.Ua, p.N1, out, \
+                     p.S, st.dt, chain ? 1 : 0, sa, c)
+  PINT_SEG_DISPATCH(L)
+#undef L
+  PINT_HIP(hipGetLastError());
+  return PINT_OK;
+}
+
+pint_status sp_prep(Plan& p, const double* in, int B, hipStream_t s) {
+  ProfScope ps(p, PK_PREP, B, s);
+  const SpecArgs sa = spec_args(p, B);
+  const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
+#define L(SEG) \
+  hipLaunchKernelGGL(k_sp_prep<SEG>, grid, dim3(64 * kSpecWaves), 0, s, in, p.S, sa)
+  PINT_SEG_DISPATCH(L)
+#undef L
+  PINT_HIP(hipGetLastError());
+  return PINT_OK;
+}
+
+pint_status sp_tend(Plan& p, double* out, int B, hipStream_t s) {
+  ProfScope ps(p, PK_ASSEMBLE, B, s);
+  const SpecArgs sa = spec_args(p, B);
+  const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
+#define L(SEG) \
+  hipLaunchKernelGGL(k_sp_tend<SEG>, grid, dim3(64 * kSpecWaves), 0, s, p.Q, out, sa)
+  PINT_SEG_DISPATCH(L)
+#undef L
+  PINT_HIP(hipGetLastError());
+  return PINT_OK;
+}
+
+pint_status sp_cn(Plan& p, const CnFactors& f, const pint_stepper& st0, const pint_stepper* st1,
+                  const double* in, double* out, int B, hipStream_t s) {
+  ProfScope ps(p, PK_CN, B, s);
+  const SpecArgs sa = spec_args(p, B);
+  const CnArgs c0 = cn_args(p, f, st0, st1 == nullptr);
+  const CnArgs c1 = st1 ? cn_args(p, f, *st1, true) : c0;
+  const int two = st1 ? 1 : 0;
+  const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
+#define L(SEG)                                                                               \
+  hipLaunchKernelGGL(k_sp_cn<SEG>, grid, dim3(64 * kSpecWaves), 0, s, in, out, two, sa, c0, c1)
+  PINT_SEG_DISPATCH(L)
+#undef L
+  PINT_HIP(hipGetLastError());
+  return PINT_OK;
+}
+#undef PINT_SEG_DISPATCH
 
 // ---------------------------------------------------------------------------
 // Parareal / MGRIT correction: out = (gnew - gold) + f  (coarse difference
