@@ -35,30 +35,33 @@ DT_FINE, DT_COARSE = 45.0, 180.0
 NU_COARSE, Q_COARSE = 1.0e17, 4
 PHIBAR = 9.80616e4          # g * 10 km mean depth
 PEAK_FP64 = 78.6e12         # MI355X dense FP64 (matrix and vector), FLOP/s
+PEAK_FP32 = 157.3e12        # MI355X dense FP32 matrix, FLOP/s
 PEAK_HBM = 8.0e12           # MI355X HBM3E, B/s
 
 
-def algorithmic_work(kind, B):
+def algorithmic_work(kind, B, prec=0):
     """Algorithmic FLOPs and HBM bytes of one launch over B states (T255).
 
     Legendre GEMMs (N/S folded): rows n = m..M+1 per m, parity-split, against
     the nlat/2 northern latitudes; synthesis has 6 fields x (re, im) columns
-    per state, analysis 4.  Bytes: table once + operands + result once.
+    per state, analysis 4.  Bytes: table once + operands + result once, at 8
+    bytes per value (FP64) or 4 (FP32 Legendre mode, prec = 1).
     """
+    w = 4.0 if prec == 1 else 8.0
     nrows = (M + 1) * (M + 4) // 2          # sum_m (M - m + 2)
     nl2 = NLAT // 2
     if kind == "legendre_synth":
         cols = 12 * B
         flops = 2.0 * nl2 * nrows * cols
-        byts = 8.0 * (nrows * nl2 + nrows * cols + 2 * (M + 1) * nl2 * cols)
+        byts = w * (nrows * nl2 + nrows * cols + 2 * (M + 1) * nl2 * cols)
     elif kind == "legendre_anal":
         cols = 8 * B
         flops = 2.0 * nl2 * nrows * cols
-        byts = 8.0 * (nrows * nl2 + (M + 1) * NLAT * cols + nrows * cols)
+        byts = w * (nrows * nl2 + (M + 1) * NLAT * cols + nrows * cols)
     elif kind == "ring_tendency":
         # read the Fourier rows of the 6 fields once, write the 4 analysis fields once
         flops = 0.0
-        byts = 8.0 * (2 * (M + 1) * nl2 * 12 * B + (M + 1) * NLAT * 8 * B)
+        byts = w * (2 * (M + 1) * nl2 * 12 * B + (M + 1) * NLAT * 8 * B)
     else:
         flops, byts = 0.0, 0.0
     return flops, byts
@@ -220,33 +223,15 @@ def time_to_tol():
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--time-to-tol", action="store_true",
-                    help="print the T127 Parareal time-to-tolerance measurement instead")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the whole PinT problem on a "
-              "single MI355X (time slices are the batch dimension); --gpus must be 1.",
-              file=sys.stderr)
-        return 2
-    if args.time_to_tol:
-        print(json.dumps({"metric": "PinT time-to-tol vs serial fine", **time_to_tol()}),
-              flush=True)
-        return 0
-
+def measure(precision, steps, warmup):
+    """Time `steps` MGRIT iterations at the given Legendre precision; return
+    the throughput, the per-kernel profile of the batched transform kernels
+    and the slice states after warmup + steps iterations."""
     import numpy as np
     import torch
     from paper_2306_09497_amd import pint, workloads
 
-    torch.cuda.init()
-    stream = torch.cuda.current_stream()
-    plan = pint.Plan(M, NLON, NLAT, phibar=PHIBAR, max_batch=GROUP)
+    plan = pint.Plan(M, NLON, NLAT, phibar=PHIBAR, max_batch=GROUP, precision=precision)
     # synthetic jet + bump initial state, analysed on the device
     mu, _ = plan.grid_coords()
     G = workloads.jet_bump_grid(mu, NLON, phibar=PHIBAR, **workloads.jet_bump_params(0))
@@ -260,7 +245,7 @@ def main():
                u0, slices)                                     # initial coarse sweep
     it = pint.params(pint.MGRIT, GROUP, fine, CFACTOR, coarse, 1, nrelax=1, max_iter=1,
                      resume=True)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         plan.solve(it, u0, slices)
     torch.cuda.synchronize()
 
@@ -271,7 +256,7 @@ def main():
     t0 = time.perf_counter()
     fine_steps = 0
     incr = []
-    for _ in range(args.steps):
+    for _ in range(steps):
         rep = plan.solve(it, u0, slices)
         fine_steps += rep.fine_slice_steps
         incr.append(rep.incr[0])
@@ -279,8 +264,60 @@ def main():
     t1 = time.perf_counter()
     prof = plan.profile_read()
     plan.profile([])
+    plan.close()
     elapsed = t1 - t0
-    value = fine_steps / elapsed
+    return {"value": fine_steps / elapsed, "elapsed": elapsed, "fine_steps": fine_steps,
+            "prof": prof, "incr": incr, "slices": slices}
+
+
+def field_errors(a, b):
+    """Per-field relative L2 difference (Phi', xi, delta) of two (N, 3, ncoef, 2)
+    device tensors over all slices."""
+    import torch
+    d = (a - b).double()
+    out = {}
+    for f, name in enumerate(("phi", "xi", "delta")):
+        ref = b[:, f].clone()
+        if f == 0:
+            ref[:, 0, 0] = 0.0                     # Phi without its mean
+        out[name] = float(torch.linalg.vector_norm(d[:, f]) / torch.linalg.vector_norm(ref))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+                    help="Legendre/ring precision of the headline (fp32: FP32 Legendre GEMMs, "
+                         "Fourier rows and tendencies; state and solves FP64)")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the FP32-Legendre side measurement of the default run")
+    ap.add_argument("--time-to-tol", action="store_true",
+                    help="print the T127 Parareal time-to-tolerance measurement instead")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the whole PinT problem on a "
+              "single MI355X (time slices are the batch dimension); --gpus must be 1.",
+              file=sys.stderr)
+        return 2
+    if args.time_to_tol:
+        print(json.dumps({"metric": "PinT time-to-tol vs serial fine", **time_to_tol()}),
+              flush=True)
+        return 0
+
+    import torch
+    from paper_2306_09497_amd import pint
+
+    torch.cuda.init()
+    prec = pint.LEG_FP32 if args.precision == "fp32" else pint.FP64
+    res = measure(prec, args.steps, args.warmup)
+    prof, elapsed, fine_steps, value = res["prof"], res["elapsed"], res["fine_steps"], res["value"]
+    incr = res["incr"]
+    peak_mfma = PEAK_FP32 if prec == pint.LEG_FP32 else PEAK_FP64
 
     # dominant kernel of the timed region and its roofline
     per_kind = {}
@@ -290,21 +327,21 @@ def main():
     dom = max(per_kind, key=lambda k: per_kind[k][1])
     n_launch, tot_ms = per_kind[dom]
     avg_s = tot_ms / n_launch * 1e-3
-    flops, byts = algorithmic_work(dom, GROUP)
+    flops, byts = algorithmic_work(dom, GROUP, prec)
     if flops > 0:
-        roof = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": PEAK_FP64 / 1e12,
+        roof = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": peak_mfma / 1e12,
                 "unit": "TFLOP/s"}
     else:
         roof = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": PEAK_HBM / 1e9,
                 "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(dom)
+    roof["traffic"] = measured_traffic(dom) if prec == pint.FP64 else None
     roof["kernel"] = dom
     roof["avg_launch_ms"] = tot_ms / n_launch
 
     kernels = {}
     for kind, (n, ms) in sorted(per_kind.items()):
-        f, b = algorithmic_work(kind, GROUP)
+        f, b = algorithmic_work(kind, GROUP, prec)
         avg = ms / n * 1e-3
         kernels[kind] = {"launches": n, "avg_ms": ms / n,
                          "share_of_step": ms * 1e-3 / elapsed,
@@ -322,7 +359,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == pint.FP64 else "f32+f64",
         "data": "synthetic",
         "config": {
             "workload": "T255 768x384, two-level MGRIT FCF iteration over one slice group: "
@@ -336,10 +373,21 @@ def main():
         "kernels": kernels,
         "mgrit_increment": incr,
     }
+    if prec == pint.FP64 and not args.no_mixed:
+        # the same iterations with FP32 Legendre GEMMs, Fourier rows and
+        # tendencies: throughput and per-field difference of all slice states
+        # from the FP64 path after warmup + steps iterations
+        r32 = measure(pint.LEG_FP32, args.steps, args.warmup)
+        out["fp32_legendre"] = {
+            "value": r32["value"], "unit": "slice-steps/s",
+            "ms_per_step": r32["elapsed"] / args.steps * 1e3,
+            "speedup_vs_fp64": r32["value"] / value,
+            "rel_l2_vs_fp64_path": field_errors(r32["slices"], res["slices"]),
+            "iterations_compared": args.warmup + args.steps,
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
-    plan.close()
     return 0
 
 

@@ -58,16 +58,28 @@ enum {
   PINT_T_ALL = 15
 };
 
+/* Arithmetic of the transforms (pint_config.precision).
+ * PINT_FP64: every stage in FP64.
+ * PINT_LEG_FP32: the Legendre GEMMs (FP32 operands on the FP32 matrix cores,
+ *   FP32 accumulation), the Fourier intermediates and the ring FFTs with the
+ *   pointwise tendencies run in FP32; the spectral state, the Crank-Nicolson
+ *   solve, viscosity, the RK combine, table generation, the Parareal/MGRIT
+ *   corrections and the norms stay FP64.  The public scalar transforms
+ *   (pint_synthesis, pint_analysis) stay FP64 in both modes.  */
+enum { PINT_FP64 = 0, PINT_LEG_FP32 = 1 };
+
 /* Truncation, grid and planet.  Requires M >= 1, nlat even, nlat >= M+2,
  * nlon >= 2M+2, nlon = 2^a 3^b 5^c <= 1024; the 3/2 rule (nlon >= 3M+3,
  * nlat >= (3M+3)/2) makes the quadratic terms alias-free (Sec. 2.2).
  * phibar is the constant mean geopotential Phibar of L_G (Sec. 2.1).
  * max_batch bounds the number of states one internal launch processes; the
- * plan's workspace is sized for it (larger calls are split into chunks).  */
+ * plan's workspace is sized for it (larger calls are split into chunks).
+ * precision is PINT_FP64 or PINT_LEG_FP32.  */
 typedef struct {
   int M, nlon, nlat;
   double a, omega, g, phibar;
   int max_batch;
+  int precision;
 } pint_config;
 
 /* One time stepper: IMEX step of size dt (Sec. 2.3.1, eq. IMEX), followed by

@@ -61,13 +61,13 @@ pint_status imex_steps(Plan& p, const pint_stepper& st, const double* in, double
   }
   PINT_TRY(sp_cn_prep(p, *f, st, in, B, s));
   for (int k = 0; k < nsteps; ++k) {
-    PINT_TRY(legendre_synth(p, B, kSynFields, s));
+    PINT_TRY(legendre_synth(p, B, kSynFields, p.prec, s));
     PINT_TRY(ring_tendency(p, B, s));
-    PINT_TRY(legendre_anal(p, B, kAnaFields, s));
+    PINT_TRY(legendre_anal(p, B, kAnaFields, p.prec, s));
     PINT_TRY(sp_stage1(p, st.dt, B, s));
-    PINT_TRY(legendre_synth(p, B, kSynFields, s));
+    PINT_TRY(legendre_synth(p, B, kSynFields, p.prec, s));
     PINT_TRY(ring_tendency(p, B, s));
-    PINT_TRY(legendre_anal(p, B, kAnaFields, s));
+    PINT_TRY(legendre_anal(p, B, kAnaFields, p.prec, s));
     PINT_TRY(sp_stage2(p, *f, st, out, k + 1 < nsteps, B, s));
   }
   return PINT_OK;
@@ -317,9 +317,9 @@ pint_status pint_tendency(pint_plan* plan, const double* u, double* n_out, int B
   for (int b0 = 0; b0 < B; b0 += p.max_batch) {
     const int nb = (B - b0) < p.max_batch ? (B - b0) : p.max_batch;
     PINT_TRY(sp_prep(p, u + b0 * sd, nb, s));
-    PINT_TRY(legendre_synth(p, nb, kSynFields, s));
+    PINT_TRY(legendre_synth(p, nb, kSynFields, p.prec, s));
     PINT_TRY(ring_tendency(p, nb, s));
-    PINT_TRY(legendre_anal(p, nb, kAnaFields, s));
+    PINT_TRY(legendre_anal(p, nb, kAnaFields, p.prec, s));
     PINT_TRY(sp_tend(p, n_out + b0 * sd, nb, s));
   }
   return PINT_OK;

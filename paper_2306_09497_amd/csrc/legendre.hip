@@ -19,6 +19,32 @@
 namespace pint {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// One 16x16x4 matrix-core product per element type.  Operand layouts are the
+// same for FP64 and FP32 (lane l holds A[l%16][l/16] and B[l/16][l%16]); the
+// result layouts differ (measured on gfx950 with in-bounds probes): register
+// i of lane l holds D[l/16 + 4i][l%16] for FP64, D[4(l/16) + i][l%16] for FP32.
+template <typename T>
+struct Mma;
+template <>
+struct Mma<double> {
+  typedef v4d acc_t;
+  __device__ static inline acc_t zero() { return (v4d){0.0, 0.0, 0.0, 0.0}; }
+  __device__ static inline acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lk, int i) { return lk + 4 * i; }
+};
+template <>
+struct Mma<float> {
+  typedef v4f acc_t;
+  __device__ static inline acc_t zero() { return (v4f){0.0f, 0.0f, 0.0f, 0.0f}; }
+  __device__ static inline acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lk, int i) { return 4 * lk + i; }
+};
 
 // Synthesis tile: TR = 64 latitudes x TC columns (TC = 64 for batched
 // launches, 16 for the latency-bound single-state launches of the serial
@@ -29,10 +55,11 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // F[m][j] = E + O (north, j < nlat/2) and F[m][nlat-1-j] = E - O (south).
 // The matrix cores consume k in steps of 4 in increasing order whatever TC
 // is, so every launch shape gives bitwise the same sums.
-template <int TR, int TC, int TK>
+template <typename E, int TR, int TC, int TK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_legendre_synth(
-    const double* __restrict__ T, const int* __restrict__ rowoff, const int* __restrict__ tiles,
-    const double* __restrict__ S, double* __restrict__ F, int nlat, int nlat2, int ncol) {
+    const E* __restrict__ T, const int* __restrict__ rowoff, const int* __restrict__ tiles,
+    const E* __restrict__ S, E* __restrict__ F, int nlat, int nlat2, int ncol) {
+  using MM = Mma<E>;
   constexpr int LDA = TR + 2, LDB = TC + 2;
   constexpr int NA = TK * TR / 256;                  // A elements per thread per slab
   constexpr int NB = TK * TC / 256;                  // B elements per thread per slab
@@ -40,8 +67,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   constexpr int WR = 4 / WC;                         // waves across rows
   constexpr int BI = TR / WR / 16, BJ = TC / WC / 16;  // MFMA blocks per wave
   static_assert(BI >= 1 && BJ >= 1 && NA >= 1 && NB >= 1, "tile shape");
-  __shared__ double As[2][TK * LDA];
-  __shared__ double Bs[2][TK * LDB];
+  __shared__ E As[2][TK * LDA];
+  __shared__ E Bs[2][TK * LDB];
 
   // logical block = row tile * ncoltiles + column tile (column tiles of one
   // table tile adjacent), XCD-remapped so that they share an L2; the tile
@@ -58,20 +85,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int li = lane & 15, lk = lane >> 4;
   const size_t gbase = (size_t)m * nlat;
 
-  v4d acc[2][BI][BJ];
+  typename MM::acc_t acc[2][BI][BJ];
 #pragma unroll
   for (int q = 0; q < 2; ++q)
 #pragma unroll
     for (int i = 0; i < BI; ++i)
 #pragma unroll
-      for (int j = 0; j < BJ; ++j) acc[q][i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+      for (int j = 0; j < BJ; ++j) acc[q][i][j] = MM::zero();
 
   // k-slabs: the even rows' slabs, then the odd rows'
   const int roff0 = rowoff[2 * m], K0 = rowoff[2 * m + 1] - roff0;
   const int roff1 = rowoff[2 * m + 1], K1 = rowoff[2 * m + 2] - roff1;
   const int ns0 = (K0 + TK - 1) / TK, ns1 = (K1 + TK - 1) / TK;
   const int nslab = ns0 + ns1;
-  double ra[NA], rb[NB];
+  E ra[NA], rb[NB];
   auto fetch = [&](int sl) {
     const bool second = sl >= ns0;
     const int roff = second ? roff1 : roff0;
@@ -82,14 +109,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       const int e = tid + e4 * 256;
       const int kk = e / TR, rr = e % TR;              // lanes along the latitudes
       const int k = k0 + kk, r = row0 + rr;
-      ra[e4] = (k < K && r < nlat2) ? T[(size_t)(roff + k) * nlat2 + r] : 0.0;
+      ra[e4] = (k < K && r < nlat2) ? T[(size_t)(roff + k) * nlat2 + r] : E(0);
     }
 #pragma unroll
     for (int e4 = 0; e4 < NB; ++e4) {
       const int e = tid + e4 * 256;
       const int kk = e / TC, cc = e % TC;
       const int k = k0 + kk, c = col0 + cc;
-      rb[e4] = (k < K && c < ncol) ? S[(size_t)(roff + k) * ncol + c] : 0.0;
+      rb[e4] = (k < K && c < ncol) ? S[(size_t)(roff + k) * ncol + c] : E(0);
     }
   };
   auto stash = [&](int buf) {
@@ -104,10 +131,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       Bs[buf][(e / TC) * LDB + (e % TC)] = rb[e4];
     }
   };
-  auto mma = [&](int cur, v4d (&ac)[BI][BJ]) {
+  auto mma = [&](int cur, typename MM::acc_t (&ac)[BI][BJ]) {
 #pragma unroll
     for (int ks = 0; ks < TK; ks += 4) {
-      double a[BI], b[BJ];
+      E a[BI], b[BJ];
 #pragma unroll
       for (int i = 0; i < BI; ++i) a[i] = As[cur][(ks + lk) * LDA + wr + 16 * i + li];
 #pragma unroll
@@ -115,8 +142,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
       for (int i = 0; i < BI; ++i)
 #pragma unroll
-        for (int j = 0; j < BJ; ++j)
-          ac[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], ac[i][j], 0, 0, 0);
+        for (int j = 0; j < BJ; ++j) ac[i][j] = MM::mma(a[i], b[j], ac[i][j]);
     }
   };
 
@@ -136,8 +162,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       __syncthreads();
     }
   }
-  // ---- store: on gfx950 lane l, register i of a 16x16 f64 block holds
-  //      D[l/16 + 4 i][l % 16] ----
+  // ---- store (result layout of Mma<E>) ----
 #pragma unroll
   for (int bi = 0; bi < BI; ++bi) {
 #pragma unroll
@@ -145,9 +170,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       const int c = col0 + wc + bj * 16 + li;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int r = row0 + wr + bi * 16 + lk + 4 * i;
+        const int r = row0 + wr + bi * 16 + MM::row(lk, i);
         if (r < nlat2 && c < ncol) {
-          const double e = acc[0][bi][bj][i], o = acc[1][bi][bj][i];
+          const E e = acc[0][bi][bj][i], o = acc[1][bi][bj][i];
           F[(gbase + r) * ncol + c] = e + o;
           F[(gbase + (nlat - 1 - r)) * ncol + c] = e - o;
         }
@@ -162,11 +187,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // of each pair.  The row-wave groups of the first half of the tile take the
 // even rows, the others the odd rows.  Per output element the matrix cores
 // consume k in steps of 4 in increasing order, as in every other shape.
-template <int TC>
+template <typename E, int TC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_legendre_anal(
-    const double* __restrict__ Tt, const int* __restrict__ rowoff, const int* __restrict__ tiles,
-    const double* __restrict__ G, double* __restrict__ Q, int nlat, int nlat2, int ncol,
-    int nrows) {
+    const E* __restrict__ Tt, const int* __restrict__ rowoff, const int* __restrict__ tiles,
+    const E* __restrict__ G, E* __restrict__ Q, int nlat, int nlat2, int ncol, int nrows) {
+  using MM = Mma<E>;
   constexpr int TK = kGemmTK, TR2 = 32, TR = 2 * TR2;
   constexpr int LDA = TR + 2, LDB = TC + 2;
   constexpr int NA = TK * TR / 256;                  // A elements per thread per slab
@@ -175,8 +200,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   constexpr int WR = 4 / WC;                         // waves across rows
   constexpr int BI = TR / WR / 16, BJ = TC / WC / 16;
   static_assert(BI >= 1 && BJ >= 1 && NA >= 1 && NB >= 1 && (TR / WR) <= TR2, "tile shape");
-  __shared__ double As[2][TK * LDA];
-  __shared__ double Bs[2][2][TK * LDB];              // [buffer][parity]
+  __shared__ E As[2][TK * LDA];
+  __shared__ E Bs[2][2][TK * LDB];                   // [buffer][parity]
 
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int nct = (ncol + TC - 1) / TC;
@@ -193,13 +218,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const int li = lane & 15, lk = lane >> 4;
   const size_t gbase = (size_t)m * nlat;
 
-  v4d acc[BI][BJ];
+  typename MM::acc_t acc[BI][BJ];
 #pragma unroll
   for (int i = 0; i < BI; ++i)
 #pragma unroll
-    for (int j = 0; j < BJ; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < BJ; ++j) acc[i][j] = MM::zero();
 
-  double ra[NA], rbe[NB], rbo[NB];
+  E ra[NA], rbe[NB], rbo[NB];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int e4 = 0; e4 < NA; ++e4) {
@@ -208,7 +233,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       const int k = k0 + kk;
       const bool odd = ri >= TR2;
       const int r = row0 + (odd ? ri - TR2 : ri);
-      double v = 0.0;
+      E v = E(0);
       if (k < nlat2 && r < (odd ? cntO : cntE))
         v = Tt[(size_t)k * nrows + (odd ? roffO : roffE) + r];
       ra[e4] = v;
@@ -218,12 +243,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       const int e = tid + e4 * 256;
       const int kk = e / TC, cc = e % TC;
       const int k = k0 + kk, c = col0 + cc;
-      double ve = 0.0, vo = 0.0;
+      E ve = E(0), vo = E(0);
       if (k < nlat2 && c < ncol) {
-        const double gn = G[(gbase + k) * ncol + c];
-        const double gs = G[(gbase + (nlat - 1 - k)) * ncol + c];
+        const E gn = G[(gbase + k) * ncol + c];
+        const E gs = G[(gbase + (nlat - 1 - k)) * ncol + c];
         ve = gn + gs;
-        vo = gn + (-1.0) * gs;
+        vo = gn + E(-1) * gs;
       }
       rbe[e4] = ve;
       rbo[e4] = vo;
@@ -249,10 +274,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   for (int sl = 0; sl < nslab; ++sl) {
     const int cur = sl & 1;
     if (sl + 1 < nslab) fetch((sl + 1) * TK);
-    const double* bs = Bs[cur][par];
+    const E* bs = Bs[cur][par];
 #pragma unroll
     for (int ks = 0; ks < TK; ks += 4) {
-      double a[BI], b[BJ];
+      E a[BI], b[BJ];
 #pragma unroll
       for (int i = 0; i < BI; ++i) a[i] = As[cur][(ks + lk) * LDA + wr + 16 * i + li];
 #pragma unroll
@@ -260,8 +285,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
       for (int i = 0; i < BI; ++i)
 #pragma unroll
-        for (int j = 0; j < BJ; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < BJ; ++j) acc[i][j] = MM::mma(a[i], b[j], acc[i][j]);
     }
     if (sl + 1 < nslab) stash(cur ^ 1);
     __syncthreads();
@@ -275,41 +299,59 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       const int c = col0 + wc + bj * 16 + li;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int r = row0 + wrp + bi * 16 + lk + 4 * i;
+        const int r = row0 + wrp + bi * 16 + MM::row(lk, i);
         if (r < cnt && c < ncol) Q[(size_t)(roff + r) * ncol + c] = acc[bi][bj][i];
       }
     }
   }
 }
 
-pint_status legendre_synth(Plan& p, int B, int nf, hipStream_t s) {
-  ProfScope ps(p, PK_SYNTH, nf == kSynFields ? B : -B, s);
-  const int ncol = 2 * nf * B;
+template <typename E>
+static void launch_synth(Plan& p, const E* T, const E* S, E* F, int ncol, hipStream_t s) {
   if (ncol <= 32) {
     dim3 grid(((ncol + 15) / 16) * p.syn_tiles.count);
-    hipLaunchKernelGGL((k_legendre_synth<kGemmTR, 16, kGemmTK>), grid, dim3(256), 0, s, p.ptab,
-                       p.rowoff, p.syn_tiles.dev, p.S, p.F, p.nlat, p.nlat2, ncol);
+    hipLaunchKernelGGL((k_legendre_synth<E, kGemmTR, 16, kGemmTK>), grid, dim3(256), 0, s, T,
+                       p.rowoff, p.syn_tiles.dev, S, F, p.nlat, p.nlat2, ncol);
   } else {
     dim3 grid(((ncol + 63) / 64) * p.syn_tiles.count);
-    hipLaunchKernelGGL((k_legendre_synth<kGemmTR, 64, kGemmTK>), grid, dim3(256), 0, s, p.ptab,
-                       p.rowoff, p.syn_tiles.dev, p.S, p.F, p.nlat, p.nlat2, ncol);
+    hipLaunchKernelGGL((k_legendre_synth<E, kGemmTR, 64, kGemmTK>), grid, dim3(256), 0, s, T,
+                       p.rowoff, p.syn_tiles.dev, S, F, p.nlat, p.nlat2, ncol);
   }
+}
+
+template <typename E>
+static void launch_anal(Plan& p, const E* Tt, const E* G, E* Q, int ncol, hipStream_t s) {
+  if (ncol <= 32) {
+    dim3 grid(((ncol + 15) / 16) * p.ana_tiles.count);
+    hipLaunchKernelGGL((k_legendre_anal<E, 16>), grid, dim3(256), 0, s, Tt, p.rowoff,
+                       p.ana_tiles.dev, G, Q, p.nlat, p.nlat2, ncol, p.nrows);
+  } else {
+    dim3 grid(((ncol + 63) / 64) * p.ana_tiles.count);
+    hipLaunchKernelGGL((k_legendre_anal<E, 64>), grid, dim3(256), 0, s, Tt, p.rowoff,
+                       p.ana_tiles.dev, G, Q, p.nlat, p.nlat2, ncol, p.nrows);
+  }
+}
+
+pint_status legendre_synth(Plan& p, int B, int nf, int prec, hipStream_t s) {
+  ProfScope ps(p, PK_SYNTH, nf == kSynFields ? B : -B, s);
+  const int ncol = 2 * nf * B;
+  if (prec == PINT_LEG_FP32)
+    launch_synth<float>(p, p.ptab32, reinterpret_cast<const float*>(p.S),
+                        reinterpret_cast<float*>(p.F), ncol, s);
+  else
+    launch_synth<double>(p, p.ptab, p.S, p.F, ncol, s);
   PINT_HIP(hipGetLastError());
   return PINT_OK;
 }
 
-pint_status legendre_anal(Plan& p, int B, int nf, hipStream_t s) {
+pint_status legendre_anal(Plan& p, int B, int nf, int prec, hipStream_t s) {
   ProfScope ps(p, PK_ANAL, nf == kAnaFields ? B : -B, s);
   const int ncol = 2 * nf * B;
-  if (ncol <= 32) {
-    dim3 grid(((ncol + 15) / 16) * p.ana_tiles.count);
-    hipLaunchKernelGGL(k_legendre_anal<16>, grid, dim3(256), 0, s, p.ptabT, p.rowoff,
-                       p.ana_tiles.dev, p.G, p.Q, p.nlat, p.nlat2, ncol, p.nrows);
-  } else {
-    dim3 grid(((ncol + 63) / 64) * p.ana_tiles.count);
-    hipLaunchKernelGGL(k_legendre_anal<64>, grid, dim3(256), 0, s, p.ptabT, p.rowoff,
-                       p.ana_tiles.dev, p.G, p.Q, p.nlat, p.nlat2, ncol, p.nrows);
-  }
+  if (prec == PINT_LEG_FP32)
+    launch_anal<float>(p, p.ptabT32, reinterpret_cast<const float*>(p.G),
+                       reinterpret_cast<float*>(p.Q), ncol, s);
+  else
+    launch_anal<double>(p, p.ptabT, p.G, p.Q, ncol, s);
   PINT_HIP(hipGetLastError());
   return PINT_OK;
 }

@@ -74,6 +74,7 @@ struct ProfRec {
 
 struct Plan {
   int M, nlon, nlat, nlat2, ncoef, nrows, max_batch;
+  int prec = PINT_FP64;        // PINT_FP64 or PINT_LEG_FP32 (transforms in FP32)
   double a, omega, g, phibar;
   // device tables
   double* mu = nullptr;        // [nlat] north to south
@@ -81,14 +82,18 @@ struct Plan {
   double* c2 = nullptr;        // [nlat] 1 - mu^2 (= sin^2 colatitude)
   double* ptab = nullptr;      // [nrows][nlat2] Pbar_n^m(mu_j), north half
   double* ptabT = nullptr;     // [nlat2][nrows] the same table transposed (analysis GEMM)
+  float* ptab32 = nullptr;     // FP32 copies of both (PINT_LEG_FP32 only)
+  float* ptabT32 = nullptr;
   int* rowoff = nullptr;       // [2(M+1)+1] device copy
   int* rowinfo = nullptr;      // [nrows] packed (m << 16 | n)
   int* coefmn = nullptr;       // [ncoef] packed (m << 16 | n)
   double2* twid = nullptr;     // [nlon] exp(-2 pi i t / nlon)
+  float2* twid32 = nullptr;    // the same in FP32
   double4* cnco = nullptr;     // [ncoef] linear-operator coefficients (A/W, B/W, C/W, n(n+1)/a^2)
   std::vector<int> h_rowoff;   // host copy
   GemmTiles syn_tiles, ana_tiles;
   // workspace (sized for max_batch)
+  // GEMM and ring workspace, sized for FP64; FP32 in PINT_LEG_FP32 mode
   double* S = nullptr;         // [nrows][12 B]   synthesis GEMM input
   double* F = nullptr;         // [(M+1) nlat][12 B] synthesis output (Fourier coefficients)
   double* G = nullptr;         // [(M+1) nlat][8 B] ring output
@@ -158,11 +163,12 @@ pint_status imex_steps(Plan& p, const pint_stepper& st, const double* in, double
                        int nsteps, hipStream_t s);
 
 // transforms on the GEMM workspace
-pint_status legendre_synth(Plan& p, int B, int nf, hipStream_t s);
-pint_status legendre_anal(Plan& p, int B, int nf, hipStream_t s);
+// prec: PINT_FP64 (also used by the public scalar transforms) or PINT_LEG_FP32
+pint_status legendre_synth(Plan& p, int B, int nf, int prec, hipStream_t s);
+pint_status legendre_anal(Plan& p, int B, int nf, int prec, hipStream_t s);
 pint_status ring_tendency(Plan& p, int B, hipStream_t s);
 bool ring_supported(int nlon);
-size_t ring_lds_bytes(int nlon);
+size_t ring_lds_bytes(int nlon, int prec);
 pint_status ring_prepare(int nlon);
 
 // scalar transforms (public layout)
@@ -193,6 +199,9 @@ __device__ inline int xcd_remap(int L, int T) {
 
 __device__ inline double2 cmul(double2 x, double2 y) {
   return make_double2(x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x);
+}
+__device__ inline float2 cmul(float2 x, float2 y) {
+  return make_float2(x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x);
 }
 __device__ inline double2 cinv(double2 x) {
   const double d = x.x * x.x + x.y * x.y;

@@ -112,6 +112,12 @@ __global__ void k_ptab(int M, int nlat2, int nrows, const double* mu, const doub
   }
 }
 
+// FP32 copies (round to nearest) of the FP64 tables for PINT_LEG_FP32.
+__global__ void k_to_float(const double* __restrict__ x, float* __restrict__ y, size_t n) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) y[t] = (float)x[t];
+}
+
 __global__ void k_twiddle(int nlon, double2* tw) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nlon) return;
@@ -151,9 +157,9 @@ static pint_status dalloc(T** ptr, size_t count, size_t* total) {
   } while (0)
 
 static void free_plan(Plan& p) {
-  void* ptrs[] = {p.mu, p.w, p.c2, p.ptab, p.ptabT, p.rowoff, p.rowinfo, p.coefmn, p.twid, p.cnco,
-                  p.syn_tiles.dev, p.ana_tiles.dev, p.S, p.F, p.G, p.Q, p.Ua, p.N1,
-                  p.red};
+  void* ptrs[] = {p.mu, p.w, p.c2, p.ptab, p.ptabT, p.ptab32, p.ptabT32, p.twid32,
+                  p.rowoff, p.rowinfo, p.coefmn, p.twid, p.cnco, p.syn_tiles.dev,
+                  p.ana_tiles.dev, p.S, p.F, p.G, p.Q, p.Ua, p.N1, p.red};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (p.h_red) (void)hipHostFree(p.h_red);
@@ -216,6 +222,11 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
               "256 384 512 640 768 1024)", nlon);
     return PINT_E_INVAL;
   }
+  if (cfg->precision != PINT_FP64 && cfg->precision != PINT_LEG_FP32) {
+    set_error("pint_plan_create: precision must be PINT_FP64 or PINT_LEG_FP32 (got %d)",
+              cfg->precision);
+    return PINT_E_INVAL;
+  }
   if (!(cfg->a > 0) || !(cfg->phibar >= 0) || cfg->max_batch < 1 || cfg->max_batch > 65535 ||
       !isfinite(cfg->omega) || !isfinite(cfg->g)) {
     set_error("pint_plan_create: need a > 0, phibar >= 0, finite omega/g, 1 <= max_batch <= 65535");
@@ -229,9 +240,9 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
       set_error("pint_plan_create: cannot query the device");
       return PINT_E_HIP;
     }
-    if (ring_lds_bytes(nlon) > (size_t)lds_max) {
+    if (ring_lds_bytes(nlon, cfg->precision) > (size_t)lds_max) {
       set_error("pint_plan_create: nlon=%d needs %zu bytes of LDS per workgroup, device allows %d",
-                nlon, ring_lds_bytes(nlon), lds_max);
+                nlon, ring_lds_bytes(nlon, cfg->precision), lds_max);
       return PINT_E_INVAL;
     }
     pint_status rs = ring_prepare(nlon);
@@ -249,6 +260,7 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
   p.g = cfg->g;
   p.phibar = cfg->phibar;
   p.max_batch = cfg->max_batch;
+  p.prec = cfg->precision;
 
   // row space
   p.h_rowoff.assign(2 * (M + 1) + 1, 0);
@@ -285,6 +297,11 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
   PLAN_TRY(dalloc(&p.rowinfo, rowinfo.size(), &tot));
   PLAN_TRY(dalloc(&p.coefmn, coefmn.size(), &tot));
   PLAN_TRY(dalloc(&p.twid, nlon, &tot));
+  if (p.prec == PINT_LEG_FP32) {
+    PLAN_TRY(dalloc(&p.ptab32, (size_t)p.nrows * p.nlat2, &tot));
+    PLAN_TRY(dalloc(&p.ptabT32, (size_t)p.nrows * p.nlat2, &tot));
+    PLAN_TRY(dalloc(&p.twid32, nlon, &tot));
+  }
   PLAN_TRY(dalloc(&p.cnco, p.ncoef, &tot));
   PLAN_TRY(build_tiles(p.h_rowoff, M, p.nlat2, true, kGemmTR, &p.syn_tiles, &tot));
   PLAN_TRY(build_tiles(p.h_rowoff, M, p.nlat2, false, kGemmTRAnal, &p.ana_tiles, &tot));
@@ -324,6 +341,16 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
   hipLaunchKernelGGL(k_ptab, dim3((p.nlat2 + 63) / 64, M + 1), dim3(64), 0, s, M, p.nlat2,
                      p.nrows, p.mu, p.c2, p.rowoff, p.ptab, p.ptabT);
   hipLaunchKernelGGL(k_twiddle, dim3((nlon + 255) / 256), dim3(256), 0, s, nlon, p.twid);
+  if (p.prec == PINT_LEG_FP32) {
+    const size_t nt = (size_t)p.nrows * p.nlat2;
+    hipLaunchKernelGGL(k_to_float, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, p.ptab,
+                       p.ptab32, nt);
+    hipLaunchKernelGGL(k_to_float, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, p.ptabT,
+                       p.ptabT32, nt);
+    hipLaunchKernelGGL(k_to_float, dim3((unsigned)((2 * nlon + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<const double*>(p.twid), reinterpret_cast<float*>(p.twid32),
+                       (size_t)2 * nlon);
+  }
   hipLaunchKernelGGL(k_cn_coef, dim3((p.ncoef + 255) / 256), dim3(256), 0, s, M, p.ncoef, p.a,
                      p.coefmn, p.cnco);
   if ((e = hipGetLastError()) != hipSuccess) return fail_hip(e, "table kernels");

@@ -12,61 +12,114 @@
 
 namespace pint {
 
-__device__ inline double2 c_add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ inline double2 c_sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ inline double2 c_scl(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// Complex arithmetic on double2 (FP64 path) and float2 (FP32 Legendre mode).
+template <typename C>
+struct CxTraits;
+template <>
+struct CxTraits<double2> {
+  typedef double R;
+};
+template <>
+struct CxTraits<float2> {
+  typedef float R;
+};
+template <typename C>
+using RealOf = typename CxTraits<C>::R;
+template <typename T>
+struct CxOf;
+template <>
+struct CxOf<double> {
+  typedef double2 C;
+};
+template <>
+struct CxOf<float> {
+  typedef float2 C;
+};
+
+template <typename C>
+__device__ inline C mkc(RealOf<C> x, RealOf<C> y) {
+  C r;
+  r.x = x;
+  r.y = y;
+  return r;
+}
+template <typename C>
+__device__ inline C c_add(C a, C b) { return mkc<C>(a.x + b.x, a.y + b.y); }
+template <typename C>
+__device__ inline C c_sub(C a, C b) { return mkc<C>(a.x - b.x, a.y - b.y); }
+template <typename C>
+__device__ inline C c_scl(C a, RealOf<C> s) { return mkc<C>(a.x * s, a.y * s); }
 // multiply by sign * i
-__device__ inline double2 c_si(double2 a, double sign) { return make_double2(-sign * a.y, sign * a.x); }
+template <typename C>
+__device__ inline C c_si(C a, RealOf<C> sign) { return mkc<C>(-sign * a.y, sign * a.x); }
+template <typename C>
+__device__ inline C c_mul(C x, C y) {
+  return mkc<C>(x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x);
+}
+
+template <int R1, int R2, typename C>
+__device__ inline void dft_split(C* v, RealOf<C> sign);
 
 // In-register DFT of size R: y_k = sum_r v_r exp(sign 2 pi i r k / R).
-template <int R>
-__device__ inline void dft(double2* v, double sign);
-
-template <>
-__device__ inline void dft<2>(double2* v, double) {
-  const double2 a = v[0], b = v[1];
-  v[0] = c_add(a, b);
-  v[1] = c_sub(a, b);
-}
-
-template <>
-__device__ inline void dft<3>(double2* v, double sign) {
-  const double h = 0.86602540378443864676;   // sin(2 pi / 3)
-  const double2 t = c_add(v[1], v[2]);
-  const double2 d = c_sub(v[1], v[2]);
-  const double2 base = c_sub(v[0], c_scl(t, 0.5));
-  const double2 rot = c_si(c_scl(d, h), sign);
-  v[0] = c_add(v[0], t);
-  v[1] = c_add(base, rot);
-  v[2] = c_sub(base, rot);
-}
-
-template <>
-__device__ inline void dft<4>(double2* v, double sign) {
-  const double2 s02 = c_add(v[0], v[2]), d02 = c_sub(v[0], v[2]);
-  const double2 s13 = c_add(v[1], v[3]), d13 = c_si(c_sub(v[1], v[3]), sign);
-  v[0] = c_add(s02, s13);
-  v[2] = c_sub(s02, s13);
-  v[1] = c_add(d02, d13);
-  v[3] = c_sub(d02, d13);
-}
-
-template <>
-__device__ inline void dft<5>(double2* v, double sign) {
-  const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;   // cos(2pi/5), cos(4pi/5)
-  const double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;    // sin(2pi/5), sin(4pi/5)
-  const double2 a1 = c_add(v[1], v[4]), a2 = c_add(v[2], v[3]);
-  const double2 b1 = c_sub(v[1], v[4]), b2 = c_sub(v[2], v[3]);
-  const double2 y0 = c_add(v[0], c_add(a1, a2));
-  const double2 r1 = c_add(v[0], c_add(c_scl(a1, c1), c_scl(a2, c2)));
-  const double2 r2 = c_add(v[0], c_add(c_scl(a1, c2), c_scl(a2, c1)));
-  const double2 i1 = c_si(c_add(c_scl(b1, s1), c_scl(b2, s2)), sign);
-  const double2 i2 = c_si(c_sub(c_scl(b1, s2), c_scl(b2, s1)), sign);
-  v[0] = y0;
-  v[1] = c_add(r1, i1);
-  v[4] = c_sub(r1, i1);
-  v[2] = c_add(r2, i2);
-  v[3] = c_sub(r2, i2);
+template <int R, typename C>
+__device__ inline void dft(C* v, RealOf<C> sign) {
+  using T = RealOf<C>;
+  if constexpr (R == 2) {
+    const C a = v[0], b = v[1];
+    v[0] = c_add(a, b);
+    v[1] = c_sub(a, b);
+  } else if constexpr (R == 3) {
+    const T h = T(0.86602540378443864676);   // sin(2 pi / 3)
+    const C t = c_add(v[1], v[2]);
+    const C d = c_sub(v[1], v[2]);
+    const C base = c_sub(v[0], c_scl(t, T(0.5)));
+    const C rot = c_si(c_scl(d, h), sign);
+    v[0] = c_add(v[0], t);
+    v[1] = c_add(base, rot);
+    v[2] = c_sub(base, rot);
+  } else if constexpr (R == 4) {
+    const C s02 = c_add(v[0], v[2]), d02 = c_sub(v[0], v[2]);
+    const C s13 = c_add(v[1], v[3]), d13 = c_si(c_sub(v[1], v[3]), sign);
+    v[0] = c_add(s02, s13);
+    v[2] = c_sub(s02, s13);
+    v[1] = c_add(d02, d13);
+    v[3] = c_sub(d02, d13);
+  } else if constexpr (R == 5) {
+    const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);   // cos 2pi/5, 4pi/5
+    const T s1 = T(0.95105651629515357212), s2 = T(0.58778525229247312917);    // sin 2pi/5, 4pi/5
+    const C a1 = c_add(v[1], v[4]), a2 = c_add(v[2], v[3]);
+    const C b1 = c_sub(v[1], v[4]), b2 = c_sub(v[2], v[3]);
+    const C y0 = c_add(v[0], c_add(a1, a2));
+    const C r1 = c_add(v[0], c_add(c_scl(a1, c1), c_scl(a2, c2)));
+    const C r2 = c_add(v[0], c_add(c_scl(a1, c2), c_scl(a2, c1)));
+    const C i1 = c_si(c_add(c_scl(b1, s1), c_scl(b2, s2)), sign);
+    const C i2 = c_si(c_sub(c_scl(b1, s2), c_scl(b2, s1)), sign);
+    v[0] = y0;
+    v[1] = c_add(r1, i1);
+    v[4] = c_sub(r1, i1);
+    v[2] = c_add(r2, i2);
+    v[3] = c_sub(r2, i2);
+  } else if constexpr (R == 6) {
+    C a[3] = {v[0], v[2], v[4]};
+    C b[3] = {v[1], v[3], v[5]};
+    dft<3>(a, sign);
+    dft<3>(b, sign);
+    const T h = T(0.86602540378443864676) * sign;   // sign * sin(pi/3)
+    // b_k *= exp(sign 2 pi i k / 6)
+    const C b1 = mkc<C>(T(0.5) * b[1].x - h * b[1].y, h * b[1].x + T(0.5) * b[1].y);
+    const C b2 = mkc<C>(T(-0.5) * b[2].x - h * b[2].y, h * b[2].x - T(0.5) * b[2].y);
+    v[0] = c_add(a[0], b[0]);
+    v[3] = c_sub(a[0], b[0]);
+    v[1] = c_add(a[1], b1);
+    v[4] = c_sub(a[1], b1);
+    v[2] = c_add(a[2], b2);
+    v[5] = c_sub(a[2], b2);
+  } else if constexpr (R == 8) {
+    dft_split<2, 4>(v, sign);
+  } else {
+    static_assert(R == 16, "radix");
+    dft_split<4, 4>(v, sign);
+  }
 }
 
 // exp(i 2 pi t / 16) from cos(pi/8), sin(pi/8) and sqrt(1/2) by octant
@@ -90,31 +143,32 @@ constexpr C2 w16(int t) {
 
 // v * exp(sign 2 pi i T / R) for a compile-time T, R in {2, 4, 8, 16}; the
 // multiples of pi/2 cost no multiplication.
-template <int R, int T>
-__device__ inline double2 mul_w(double2 v, double sign) {
+template <int R, int T, typename C>
+__device__ inline C mul_w(C v, RealOf<C> sign) {
+  using F = RealOf<C>;
   constexpr int t = (T * (16 / R)) % 16;
   if constexpr (t == 0) {
     return v;
   } else if constexpr (t == 4) {
     return c_si(v, sign);
   } else if constexpr (t == 8) {
-    return make_double2(-v.x, -v.y);
+    return mkc<C>(-v.x, -v.y);
   } else if constexpr (t == 12) {
     return c_si(v, -sign);
   } else {
     constexpr C2 w = w16(t);
-    const double ws = sign * w.s;
-    return make_double2(v.x * w.c - v.y * ws, v.x * ws + v.y * w.c);
+    const F wc = F(w.c), ws = sign * F(w.s);
+    return mkc<C>(v.x * wc - v.y * ws, v.x * ws + v.y * wc);
   }
 }
 
 // In-register DFT of size R1 * R2 by one Cooley-Tukey split: inner DFTs of
 // size R2 over v[n1 + R1 n2], twiddles exp(sign 2 pi i n1 k2 / R), outer DFTs
 // of size R1; output index k2 + R2 k1.
-template <int R1, int R2, int N1 = 0>
-__device__ inline void split_inner(double2 (&u)[R1][R2], const double2* v, double sign) {
+template <int R1, int R2, int N1 = 0, typename C>
+__device__ inline void split_inner(C (&u)[R1][R2], const C* v, RealOf<C> sign) {
   if constexpr (N1 < R1) {
-    double2 t[R2];
+    C t[R2];
 #pragma unroll
     for (int n2 = 0; n2 < R2; ++n2) t[n2] = v[N1 + R1 * n2];
     dft<R2>(t, sign);
@@ -124,8 +178,8 @@ __device__ inline void split_inner(double2 (&u)[R1][R2], const double2* v, doubl
   }
 }
 
-template <int R1, int R2, int N1 = 1, int K2 = 1>
-__device__ inline void split_twiddle(double2 (&u)[R1][R2], double sign) {
+template <int R1, int R2, int N1 = 1, int K2 = 1, typename C>
+__device__ inline void split_twiddle(C (&u)[R1][R2], RealOf<C> sign) {
   if constexpr (N1 < R1) {
     if constexpr (K2 < R2) {
       u[N1][K2] = mul_w<R1 * R2, N1 * K2>(u[N1][K2], sign);
@@ -136,14 +190,14 @@ __device__ inline void split_twiddle(double2 (&u)[R1][R2], double sign) {
   }
 }
 
-template <int R1, int R2>
-__device__ inline void dft_split(double2* v, double sign) {
-  double2 u[R1][R2];
+template <int R1, int R2, typename C>
+__device__ inline void dft_split(C* v, RealOf<C> sign) {
+  C u[R1][R2];
   split_inner<R1, R2>(u, v, sign);
   split_twiddle<R1, R2>(u, sign);
 #pragma unroll
   for (int k2 = 0; k2 < R2; ++k2) {
-    double2 t[R1];
+    C t[R1];
 #pragma unroll
     for (int n1 = 0; n1 < R1; ++n1) t[n1] = u[n1][k2];
     dft<R1>(t, sign);
@@ -151,12 +205,6 @@ __device__ inline void dft_split(double2* v, double sign) {
     for (int k1 = 0; k1 < R1; ++k1) v[k2 + R2 * k1] = t[k1];
   }
 }
-
-template <>
-__device__ inline void dft<8>(double2* v, double sign) { dft_split<2, 4>(v, sign); }
-
-template <>
-__device__ inline void dft<16>(double2* v, double sign) { dft_split<4, 4>(v, sign); }
 
 // ---- compile-time FFT plan for a ring of N points: radix-16 passes first,
 // then 8, 4, 2, then radix-3 and radix-5 passes ----
@@ -350,23 +398,6 @@ __device__ inline void get_pair(const double2* z, int sig, int m, double2* X, do
 // ---------------------------------------------------------------------------
 constexpr int kHThreads = 128;
 
-template <>
-__device__ inline void dft<6>(double2* v, double sign) {
-  double2 a[3] = {v[0], v[2], v[4]};
-  double2 b[3] = {v[1], v[3], v[5]};
-  dft<3>(a, sign);
-  dft<3>(b, sign);
-  const double h = 0.86602540378443864676 * sign;   // sign * sin(pi/3)
-  // b_k *= exp(sign 2 pi i k / 6)
-  const double2 b1 = make_double2(0.5 * b[1].x - h * b[1].y, h * b[1].x + 0.5 * b[1].y);
-  const double2 b2 = make_double2(-0.5 * b[2].x - h * b[2].y, h * b[2].x - 0.5 * b[2].y);
-  v[0] = c_add(a[0], b[0]);
-  v[3] = c_sub(a[0], b[0]);
-  v[1] = c_add(a[1], b1);
-  v[4] = c_sub(a[1], b1);
-  v[2] = c_add(a[2], b2);
-  v[5] = c_sub(a[2], b2);
-}
 
 constexpr int ilog2c(int n) {
   int c = 0;
@@ -408,9 +439,9 @@ struct HRing {
 };
 
 // exp(SGN 2 pi i t / N) from the table tw[t] = exp(-2 pi i t / N).
-template <int SGN>
-__device__ inline double2 twid(const double2* __restrict__ tw, int t) {
-  double2 w = tw[t];
+template <int SGN, typename C>
+__device__ inline C twid(const C* __restrict__ tw, int t) {
+  C w = tw[t];
   if constexpr (SGN > 0) w.y = -w.y;
   return w;
 }
@@ -419,8 +450,8 @@ __device__ inline double2 twid(const double2* __restrict__ tw, int t) {
 // DIF: butterfly, then twiddles W_L^{j r}; DIT: twiddles, then butterfly.
 // Butterflies touch disjoint points, so loads and stores need no barrier
 // between them; the barrier at the end orders the stage before the next.
-template <int H, int NSIG, int R, int L, bool kDif, int SGN>
-__device__ inline void ip_stage(double2* buf, const double2* __restrict__ tw, int tid) {
+template <int H, int NSIG, int R, int L, bool kDif, int SGN, typename C>
+__device__ inline void ip_stage(C* buf, const C* __restrict__ tw, int tid) {
   constexpr int S = L / R;
   constexpr int NBS = H / R;
   constexpr int TOTAL = NSIG * NBS;
@@ -444,17 +475,17 @@ __device__ inline void ip_stage(double2* buf, const double2* __restrict__ tw, in
         j = rem - blk * S;
       }
       const int base = blk * L + j;
-      double2 v[R];
+      C v[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) v[r] = buf[Lay::at(sig, base + r * S)];
       if constexpr (!kDif && S > 1) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twid<SGN>(tw, j * r * TWS));
+        for (int r = 1; r < R; ++r) v[r] = c_mul(v[r], twid<SGN>(tw, j * r * TWS));
       }
-      dft<R>(v, (double)SGN);
+      dft<R>(v, RealOf<C>(SGN));
       if constexpr (kDif && S > 1) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twid<SGN>(tw, j * r * TWS));
+        for (int r = 1; r < R; ++r) v[r] = c_mul(v[r], twid<SGN>(tw, j * r * TWS));
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) buf[Lay::at(sig, base + r * S)] = v[r];
@@ -463,8 +494,8 @@ __device__ inline void ip_stage(double2* buf, const double2* __restrict__ tw, in
   __syncthreads();
 }
 
-template <int H, int NSIG, int SGN, int I>
-__device__ inline void dif_stages(double2* buf, const double2* __restrict__ tw, int tid) {
+template <int H, int NSIG, int SGN, int I, typename C>
+__device__ inline void dif_stages(C* buf, const C* __restrict__ tw, int tid) {
   if constexpr (I < hplan_npass(H)) {
     ip_stage<H, NSIG, hplan_radix(H, I), hplan_span(H, I), true, SGN>(buf, tw, tid);
     dif_stages<H, NSIG, SGN, I + 1>(buf, tw, tid);
@@ -472,8 +503,8 @@ __device__ inline void dif_stages(double2* buf, const double2* __restrict__ tw, 
 }
 
 // DIT stages I, I-1, ..., 1 (stage 0 is done by the caller).
-template <int H, int NSIG, int SGN, int I>
-__device__ inline void dit_stages(double2* buf, const double2* __restrict__ tw, int tid) {
+template <int H, int NSIG, int SGN, int I, typename C>
+__device__ inline void dit_stages(C* buf, const C* __restrict__ tw, int tid) {
   if constexpr (I >= 1) {
     ip_stage<H, NSIG, hplan_radix(H, I), hplan_span(H, I), false, SGN>(buf, tw, tid);
     dit_stages<H, NSIG, SGN, I - 1>(buf, tw, tid);
@@ -481,29 +512,34 @@ __device__ inline void dit_stages(double2* buf, const double2* __restrict__ tw, 
 }
 
 // Z = (X1 + conj X2) + i w (X1 - conj X2)
-__device__ inline double2 hpre(double2 X1, double2 X2, double2 w) {
-  const double2 d = make_double2(X1.x - X2.x, X1.y + X2.y);
-  const double2 wd = cmul(w, d);
-  return make_double2(X1.x + X2.x - wd.y, X1.y - X2.y + wd.x);
+template <typename C>
+__device__ inline C hpre(C X1, C X2, C w) {
+  const C d = mkc<C>(X1.x - X2.x, X1.y + X2.y);
+  const C wd = c_mul(w, d);
+  return mkc<C>(X1.x + X2.x - wd.y, X1.y - X2.y + wd.x);
 }
 
 // X = 1/2 [(Za + conj Zb) - i w (Za - conj Zb)]
-__device__ inline double2 hpost(double2 Za, double2 Zb, double2 w) {
-  const double2 d = make_double2(Za.x - Zb.x, Za.y + Zb.y);
-  const double2 wd = cmul(w, d);
-  return make_double2(0.5 * (Za.x + Zb.x + wd.y), 0.5 * (Za.y - Zb.y - wd.x));
+template <typename C>
+__device__ inline C hpost(C Za, C Zb, C w) {
+  using T = RealOf<C>;
+  const C d = mkc<C>(Za.x - Zb.x, Za.y + Zb.y);
+  const C wd = c_mul(w, d);
+  return mkc<C>(T(0.5) * (Za.x + Zb.x + wd.y), T(0.5) * (Za.y - Zb.y - wd.x));
 }
 
-template <int N>
+template <int N, typename T>
 __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_ring_tendency(
-    const double* __restrict__ F, double* __restrict__ Gout, const double* __restrict__ c2,
-    const double* __restrict__ w, const double2* __restrict__ tw, int M, int nlat, int nlat2,
-    int B, double a) {
+    const T* __restrict__ F, T* __restrict__ Gout, const double* __restrict__ c2,
+    const double* __restrict__ w, const typename CxOf<T>::C* __restrict__ tw, int M, int nlat,
+    int nlat2, int B, double a) {
+  using C = typename CxOf<T>::C;
   constexpr int H = N / 2;
   static_assert(hplan_ok(H), "no half-length plan for this ring");
   constexpr int NPW = (H + kHThreads - 1) / kHThreads;   // pointwise points per thread
   using Lay = HRing<H>;
-  extern __shared__ double2 zb[];
+  extern __shared__ __align__(16) unsigned char ring_lds[];
+  C* zb = reinterpret_cast<C*>(ring_lds);
   // logical block = ((jn * B) + b) * 2 + hemisphere: the rings of one state
   // run back to back on one XCD
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -513,8 +549,8 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
   const int ncs = 12 * B;
   const int tid = threadIdx.x;
   // Fourier coefficient of field f at wavenumber m on this ring
-  auto xhat = [&](int m, int f) -> double2 {
-    return *reinterpret_cast<const double2*>(F + ((size_t)m * nlat + j) * ncs + b * 12 + 2 * f);
+  auto xhat = [&](int m, int f) -> C {
+    return *reinterpret_cast<const C*>(F + ((size_t)m * nlat + j) * ncs + b * 12 + 2 * f);
   };
   // Spectra of NS fields -> Z of the half-length signals in slots 0..NS-1.
   // fld(m, s) returns field s's Fourier coefficient at m <= M.  Every load
@@ -522,16 +558,16 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
   auto put = [&](auto fld, auto nsig) {
     constexpr int NS = decltype(nsig)::value;
     constexpr int NQ = (H / 2 + kHThreads) / kHThreads;   // pairs (k, H-k) per thread
-    double2 X1[NQ][NS], X2[NQ][NS];
+    C X1[NQ][NS], X2[NQ][NS];
 #pragma unroll
     for (int it = 0; it < NQ; ++it) {
       const int q = tid + it * kHThreads;
       const bool h1 = q <= H / 2 && q <= M, h2 = q > 0 && q <= H / 2 && H - q <= M;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        X1[it][s] = h1 ? fld(q, s) : make_double2(0.0, 0.0);
-        X2[it][s] = h2 ? fld(H - q, s) : make_double2(0.0, 0.0);
-        if (q == 0) X1[it][s].y = 0.0;              // a real field's mean
+        X1[it][s] = h1 ? fld(q, s) : mkc<C>(T(0), T(0));
+        X2[it][s] = h2 ? fld(H - q, s) : mkc<C>(T(0), T(0));
+        if (q == 0) X1[it][s].y = T(0);              // a real field's mean
       }
     }
 #pragma unroll
@@ -539,8 +575,8 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
       const int q = tid + it * kHThreads;
       if (q <= H / 2) {
         const int k1 = q, k2 = H - q;
-        const double2 w1 = twid<1>(tw, k1);        // exp(2 pi i k1 / N)
-        const double2 w2 = make_double2(-w1.x, w1.y);   // exp(2 pi i (H - k1) / N)
+        const C w1 = twid<1>(tw, k1);                // exp(2 pi i k1 / N)
+        const C w2 = mkc<C>(-w1.x, w1.y);            // exp(2 pi i (H - k1) / N)
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
           zb[Lay::at(s, k1)] = hpre(X1[it][s], X2[it][s], w1);
@@ -551,31 +587,32 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
     __syncthreads();
   };
 
-  const double ic2 = 1.0 / c2[j];
-  const double ica = ic2 / a;
-  const double sc = w[j] / N;
+  const double ic2d = 1.0 / c2[j];
+  const T ic2 = T(ic2d);
+  const T ica = T(ic2d / a);
+  const T sc = T(w[j] / N);
   // ---- group 1: xi, delta, Phi' -> keep xi and Phi' delta per point ----
-  put([&](int m, int s) -> double2 { return xhat(m, s); }, std::integral_constant<int, 3>());
+  put([&](int m, int s) -> C { return xhat(m, s); }, std::integral_constant<int, 3>());
   dif_stages<H, 3, 1, 0>(zb, tw, tid);
-  double2 Xr[NPW], Dr[NPW];
+  C Xr[NPW], Dr[NPW];
 #pragma unroll
   for (int t = 0; t < NPW; ++t) {
     const int p = tid + t * kHThreads;
     if (H % kHThreads == 0 || p < H) {
-      const double2 xi = zb[Lay::at(0, p)], de = zb[Lay::at(1, p)], ph = zb[Lay::at(2, p)];
+      const C xi = zb[Lay::at(0, p)], de = zb[Lay::at(1, p)], ph = zb[Lay::at(2, p)];
       Xr[t] = xi;
-      Dr[t] = make_double2(ph.x * de.x, ph.y * de.y);
+      Dr[t] = mkc<C>(ph.x * de.x, ph.y * de.y);
     }
   }
   __syncthreads();
 
   // ---- group 2: U, V, G, dPhi'/dlambda -> all four products ----
-  put([&](int m, int s) -> double2 {
+  put([&](int m, int s) -> C {
         if (s == 0) return xhat(m, 4);
         if (s == 1) return xhat(m, 5);
         if (s == 2) return xhat(m, 3);
-        const double2 p = xhat(m, 2);
-        return make_double2(-m * p.y, m * p.x);          // i m Phi'
+        const C p = xhat(m, 2);
+        return mkc<C>(-T(m) * p.y, T(m) * p.x);        // i m Phi'
       },
       std::integral_constant<int, 4>());
   dif_stages<H, 4, 1, 0>(zb, tw, tid);
@@ -583,15 +620,15 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
   for (int t = 0; t < NPW; ++t) {
     const int p = tid + t * kHThreads;
     if (H % kHThreads == 0 || p < H) {
-      const double2 U = zb[Lay::at(0, p)], V = zb[Lay::at(1, p)];
-      const double2 G = zb[Lay::at(2, p)], L = zb[Lay::at(3, p)];
-      const double2 xi = Xr[t], pd = Dr[t];
-      zb[Lay::at(0, p)] = make_double2((-(U.x * L.x + V.x * G.x) * ica - pd.x) * sc,
-                                       (-(U.y * L.y + V.y * G.y) * ica - pd.y) * sc);   // N_Phi
-      zb[Lay::at(1, p)] = make_double2(xi.x * U.x * ic2 * sc, xi.y * U.y * ic2 * sc);   // A
-      zb[Lay::at(2, p)] = make_double2(xi.x * V.x * ic2 * sc, xi.y * V.y * ic2 * sc);   // B
-      zb[Lay::at(3, p)] = make_double2(0.5 * (U.x * U.x + V.x * V.x) * ic2 * sc,
-                                       0.5 * (U.y * U.y + V.y * V.y) * ic2 * sc);   // K
+      const C U = zb[Lay::at(0, p)], V = zb[Lay::at(1, p)];
+      const C G = zb[Lay::at(2, p)], L = zb[Lay::at(3, p)];
+      const C xi = Xr[t], pd = Dr[t];
+      zb[Lay::at(0, p)] = mkc<C>((-(U.x * L.x + V.x * G.x) * ica - pd.x) * sc,
+                                 (-(U.y * L.y + V.y * G.y) * ica - pd.y) * sc);   // N_Phi
+      zb[Lay::at(1, p)] = mkc<C>(xi.x * U.x * ic2 * sc, xi.y * U.y * ic2 * sc);   // A
+      zb[Lay::at(2, p)] = mkc<C>(xi.x * V.x * ic2 * sc, xi.y * V.y * ic2 * sc);   // B
+      zb[Lay::at(3, p)] = mkc<C>(T(0.5) * (U.x * U.x + V.x * V.x) * ic2 * sc,
+                                 T(0.5) * (U.y * U.y + V.y * V.y) * ic2 * sc);    // K
     }
   }
   __syncthreads();
@@ -605,7 +642,7 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
   for (int u = tid; u < TOTU; u += kHThreads) {
     const int sig = u / UPS, uu = u - sig * UPS;
     const int ja = uu, jb = uu == 0 ? S1 / 2 : S1 - uu;
-    double2 za[R1], zc[R1];
+    C za[R1], zc[R1];
 #pragma unroll
     for (int r = 0; r < R1; ++r) {
       za[r] = zb[Lay::at(sig, ja + r * S1)];
@@ -613,23 +650,21 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
     }
 #pragma unroll
     for (int r = 1; r < R1; ++r) {
-      za[r] = cmul(za[r], twid<-1>(tw, ja * r * 2));
-      zc[r] = cmul(zc[r], twid<-1>(tw, jb * r * 2));
+      za[r] = c_mul(za[r], twid<-1>(tw, ja * r * 2));
+      zc[r] = c_mul(zc[r], twid<-1>(tw, jb * r * 2));
     }
-    dft<R1>(za, -1.0);
-    dft<R1>(zc, -1.0);
+    dft<R1>(za, T(-1));
+    dft<R1>(zc, T(-1));
     const int f = sig == 0 ? 0 : (sig == 3 ? 1 : sig + 1);   // slot -> (N_Phi, K, A, B)
-    double* gcol = Gout + (size_t)j * ncg + b * 8 + 2 * f;
+    T* gcol = Gout + (size_t)j * ncg + b * 8 + 2 * f;
 #pragma unroll
     for (int r = 0; r < R1; ++r) {
       const int ka = ja + r * S1, kc = jb + r * S1;
       // partners Z_{H-k}
-      const double2 pa = uu == 0 ? za[(R1 - r) % R1] : zc[R1 - 1 - r];
-      const double2 pc = uu == 0 ? zc[R1 - 1 - r] : za[R1 - 1 - r];
-      if (ka <= M)
-        *reinterpret_cast<double2*>(gcol + (size_t)ka * nlat * ncg) = hpost(za[r], pa, tw[ka]);
-      if (kc <= M)
-        *reinterpret_cast<double2*>(gcol + (size_t)kc * nlat * ncg) = hpost(zc[r], pc, tw[kc]);
+      const C pa = uu == 0 ? za[(R1 - r) % R1] : zc[R1 - 1 - r];
+      const C pc = uu == 0 ? zc[R1 - 1 - r] : za[R1 - 1 - r];
+      if (ka <= M) *reinterpret_cast<C*>(gcol + (size_t)ka * nlat * ncg) = hpost(za[r], pa, tw[ka]);
+      if (kc <= M) *reinterpret_cast<C*>(gcol + (size_t)kc * nlat * ncg) = hpost(zc[r], pc, tw[kc]);
     }
   }
 }
@@ -733,12 +768,14 @@ bool ring_supported(int nlon) {
   return false;
 }
 
-// Dynamic LDS of the tendency ring kernel: 4 half-length signals.
-size_t ring_lds_bytes(int nlon) {
+// Dynamic LDS of the tendency ring kernel: 4 half-length signals (complex
+// FP64, or FP32 in the mixed-precision mode).
+size_t ring_lds_bytes(int nlon, int prec) {
+  const size_t cx = prec == PINT_LEG_FP32 ? sizeof(float2) : sizeof(double2);
   switch (nlon) {
 #define PINT_CASE(n) \
   case n:            \
-    return (size_t)4 * HRing<n / 2>::SP * sizeof(double2);
+    return (size_t)4 * HRing<n / 2>::SP * cx;
     PINT_FOR_EACH_NLON(PINT_CASE)
 #undef PINT_CASE
     default:
@@ -746,14 +783,17 @@ size_t ring_lds_bytes(int nlon) {
   }
 }
 
-// Allow the tendency ring kernel its dynamic LDS.
+// Allow the tendency ring kernels their dynamic LDS.
 pint_status ring_prepare(int nlon) {
   switch (nlon) {
 #define PINT_CASE(n)                                                                          \
   case n:                                                                                     \
-    PINT_HIP(hipFuncSetAttribute((const void*)k_ring_tendency<n>,                             \
+    PINT_HIP(hipFuncSetAttribute((const void*)k_ring_tendency<n, double>,                     \
                                  hipFuncAttributeMaxDynamicSharedMemorySize,                  \
-                                 (int)ring_lds_bytes(n)));                                    \
+                                 (int)ring_lds_bytes(n, PINT_FP64)));                         \
+    PINT_HIP(hipFuncSetAttribute((const void*)k_ring_tendency<n, float>,                      \
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,                  \
+                                 (int)ring_lds_bytes(n, PINT_LEG_FP32)));                     \
     return PINT_OK;
     PINT_FOR_EACH_NLON(PINT_CASE)
 #undef PINT_CASE
@@ -765,12 +805,19 @@ pint_status ring_prepare(int nlon) {
 
 pint_status ring_tendency(Plan& p, int B, hipStream_t s) {
   ProfScope ps(p, PK_RING, B, s);
+  const bool f32 = p.prec == PINT_LEG_FP32;
   switch (p.nlon) {
 #define PINT_CASE(n)                                                                         \
   case n:                                                                                    \
-    hipLaunchKernelGGL(k_ring_tendency<n>, dim3(p.nlat * B), dim3(kHThreads),                \
-                       ring_lds_bytes(n), s, p.F, p.G, p.c2, p.w, p.twid, p.M, p.nlat,       \
-                       p.nlat2, B, p.a);                                                     \
+    if (f32)                                                                                 \
+      hipLaunchKernelGGL((k_ring_tendency<n, float>), dim3(p.nlat * B), dim3(kHThreads),     \
+                         ring_lds_bytes(n, p.prec), s, reinterpret_cast<const float*>(p.F),  \
+                         reinterpret_cast<float*>(p.G), p.c2, p.w, p.twid32, p.M, p.nlat,    \
+                         p.nlat2, B, p.a);                                                   \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_ring_tendency<n, double>), dim3(p.nlat * B), dim3(kHThreads),    \
+                         ring_lds_bytes(n, p.prec), s, p.F, p.G, p.c2, p.w, p.twid, p.M,     \
+                         p.nlat, p.nlat2, B, p.a);                                           \
     break;
     PINT_FOR_EACH_NLON(PINT_CASE)
 #undef PINT_CASE
@@ -790,7 +837,7 @@ pint_status scalar_synthesis(Plan& p, const double* spec, double* grid, int B, h
     const int nb = (B - b0) < p.max_batch ? (B - b0) : p.max_batch;
     pint_status st = scalar_prep(p, spec + (size_t)b0 * p.ncoef * 2, nb, s);
     if (st != PINT_OK) return st;
-    st = legendre_synth(p, nb, 1, s);
+    st = legendre_synth(p, nb, 1, PINT_FP64, s);
     if (st != PINT_OK) return st;
     {
       ProfScope ps(p, PK_SRING, nb, s);
@@ -835,7 +882,7 @@ pint_status scalar_analysis(Plan& p, const double* grid, double* spec, int B, hi
       }
       PINT_HIP(hipGetLastError());
     }
-    pint_status st = legendre_anal(p, nb, 1, s);
+    pint_status st = legendre_anal(p, nb, 1, PINT_FP64, s);
     if (st != PINT_OK) return st;
     st = scalar_post(p, spec + (size_t)b0 * p.ncoef * 2, nb, s);
     if (st != PINT_OK) return st;

@@ -248,8 +248,20 @@ __device__ inline void cn_lane(double2 (&V)[SEG][3], const WaveAt& w, int ncoef,
 //   (1-mu^2) d/dmu sum_k c_k Pbar_k = sum_n [-(n-1) eps_n c_{n-1} + (n+2) eps_{n+1} c_{n+1}] Pbar_n
 // (from (1-mu^2) dPbar_n/dmu = -n eps_{n+1} Pbar_{n+1} + (n+1) eps_n Pbar_{n-1}).
 // Row n = M+1 (state zero there) is written by the lane holding n = M.
-// Output S[row][(b*6 + f)*2 + reim].
-__device__ inline void prep_row(double* __restrict__ S, const int* __restrict__ rowoff, int m,
+// Output S[row][(b*6 + f)*2 + reim], stored in the Legendre GEMM's element
+// type SE (FP64, or FP32 in the mixed-precision mode).
+__device__ inline void put_c(double* p, double2 v) { *reinterpret_cast<double2*>(p) = v; }
+__device__ inline void put_c(float* p, double2 v) {
+  *reinterpret_cast<float2*>(p) = make_float2((float)v.x, (float)v.y);
+}
+__device__ inline double2 get_c(const double* p) { return *reinterpret_cast<const double2*>(p); }
+__device__ inline double2 get_c(const float* p) {
+  const float2 f = *reinterpret_cast<const float2*>(p);
+  return make_double2((double)f.x, (double)f.y);
+}
+
+template <typename SE>
+__device__ inline void prep_row(SE* __restrict__ S, const int* __restrict__ rowoff, int m,
                                 int n, int b, int B, double a, double phibar, const double2* cur,
                                 const double2* pv, const double2* nx) {
   const double2 xi = cur[1], de = cur[2];
@@ -267,18 +279,18 @@ __device__ inline void prep_row(double* __restrict__ S, const int* __restrict__ 
   const double2 V = cscale(cadd(cimul(psi, (double)m), dchi), ia);
   const int par = (n - m) & 1;
   const int row = rowoff[2 * m + par] + ((n - m - par) >> 1);
-  double2* out = reinterpret_cast<double2*>(S + ((size_t)row * B + b) * 12);
-  out[0] = xi;
-  out[1] = de;
-  out[2] = ph;
-  out[3] = G;
-  out[4] = U;
-  out[5] = V;
+  SE* out = S + ((size_t)row * B + b) * 12;
+  put_c(out + 0, xi);
+  put_c(out + 2, de);
+  put_c(out + 4, ph);
+  put_c(out + 6, G);
+  put_c(out + 8, U);
+  put_c(out + 10, V);
 }
 
-template <int SEG>
+template <int SEG, typename SE>
 __device__ inline void prep_lane(const double2 (&V)[SEG][3], const WaveAt& w, int B,
-                                 double* __restrict__ S, const int* __restrict__ rowoff,
+                                 SE* __restrict__ S, const int* __restrict__ rowoff,
                                  double a, double phibar) {
   double2 prev[3], next[3];
   edge_neighbours<SEG>(V, w.lane, prev, next);
@@ -304,15 +316,15 @@ __device__ inline void prep_lane(const double2 (&V)[SEG][3], const WaveAt& w, in
 //   div  = 1/(2a) [ i m Q_A(n) - (-n eps_{n+1} Q_B(n+1) + (n+1) eps_n Q_B(n-1)) ]
 //   curl = 1/(2a) [ i m Q_B(n) + (-n eps_{n+1} Q_A(n+1) + (n+1) eps_n Q_A(n-1)) ]
 //   N_xi = -div,  N_delta = curl + n(n+1)/a^2 K,   (0,0) of N_xi, N_delta = 0.
-template <int SEG>
-__device__ inline void asm_lane(const double* __restrict__ Q, const int* __restrict__ rowoff,
+template <int SEG, typename SE>
+__device__ inline void asm_lane(const SE* __restrict__ Q, const int* __restrict__ rowoff,
                                 const WaveAt& w, int B, double a, double2 (&N)[SEG][3]) {
   const double2 zero = make_double2(0.0, 0.0);
   const int m = w.m;
-  auto qrow = [&](int k) -> const double2* {
+  auto qrow = [&](int k) -> const SE* {
     const int par = (k - m) & 1;
     const int row = rowoff[2 * m + par] + ((k - m - par) >> 1);
-    return reinterpret_cast<const double2*>(Q + ((size_t)row * B + w.b) * 8);
+    return Q + ((size_t)row * B + w.b) * 8;
   };
   const double ha = 0.5 / a;
 #pragma unroll
@@ -320,21 +332,21 @@ __device__ inline void asm_lane(const double* __restrict__ Q, const int* __restr
     const int i = w.p0 + k, n = m + i;
     N[k][0] = N[k][1] = N[k][2] = zero;
     if (i < w.K) {
-      const double2* q0 = qrow(n);
-      const double2* qp = qrow(n + 1);
+      const SE* q0 = qrow(n);
+      const SE* qp = qrow(n + 1);
       double2 qAm = zero, qBm = zero;
       if (n > m) {
-        const double2* qm = qrow(n - 1);
-        qAm = qm[2];
-        qBm = qm[3];
+        const SE* qm = qrow(n - 1);
+        qAm = get_c(qm + 4);
+        qBm = get_c(qm + 6);
       }
       const double e0 = eps_nm(n, m), e1 = eps_nm(n + 1, m);
-      const double2 Kc = cscale(q0[1], 0.5);
-      const double2 hB = cadd(cscale(qp[3], -n * e1), cscale(qBm, (n + 1) * e0));
-      const double2 hA = cadd(cscale(qp[2], -n * e1), cscale(qAm, (n + 1) * e0));
-      const double2 div = cscale(csub(cimul(q0[2], (double)m), hB), ha);
-      const double2 curl = cscale(cadd(cimul(q0[3], (double)m), hA), ha);
-      N[k][0] = cscale(q0[0], 0.5);
+      const double2 Kc = cscale(get_c(q0 + 2), 0.5);
+      const double2 hB = cadd(cscale(get_c(qp + 6), -n * e1), cscale(qBm, (n + 1) * e0));
+      const double2 hA = cadd(cscale(get_c(qp + 4), -n * e1), cscale(qAm, (n + 1) * e0));
+      const double2 div = cscale(csub(cimul(get_c(q0 + 4), (double)m), hB), ha);
+      const double2 curl = cscale(cadd(cimul(get_c(q0 + 6), (double)m), hA), ha);
+      N[k][0] = cscale(get_c(q0), 0.5);
       if (!(m == 0 && n == 0)) {
         N[k][1] = cscale(div, -1.0);
         N[k][2] = cadd(curl, cscale(Kc, (double)n * (n + 1) / (a * a)));
@@ -350,9 +362,9 @@ struct SpecArgs {
 };
 
 // K_A: Ua = CN(in); S = synthesis input of Ua.
-template <int SEG>
+template <int SEG, typename SE>
 __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_cn_prep(const double* __restrict__ in,
-                                                   double* __restrict__ ua, double* __restrict__ S,
+                                                   double* __restrict__ ua, SE* __restrict__ S,
                                                    SpecArgs sa, CnArgs c) {
   const WaveAt w = wave_at<SEG>(sa.M, sa.B);
   if (w.b >= sa.B) return;                            // uniform per wave
@@ -364,10 +376,10 @@ __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_cn_prep(const double* __
 }
 
 // K_B (first explicit stage): N1 = N(Q); S = synthesis input of Ua + dt N1.
-template <int SEG>
-__global__ __launch_bounds__(64 * kSpecWaves) void k_sp_stage1(const double* __restrict__ Q,
+template <int SEG, typename SE>
+__global__ __launch_bounds__(64 * kSpecWaves) void k_sp_stage1(const SE* __restrict__ Q,
                                                   const double* __restrict__ ua,
-                                                  double* __restrict__ n1, double* __restrict__ S,
+                                                  double* __restrict__ n1, SE* __restrict__ S,
                                                   double dt, SpecArgs sa) {
   const WaveAt w = wave_at<SEG>(sa.M, sa.B);
   if (w.b >= sa.B) return;                            // uniform per wave
@@ -385,12 +397,12 @@ __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_stage1(const double* __r
 // K_C (second explicit stage and the closing half step):
 // U = D_nu CN(Ua + dt/2 (N1 + N(Q))); chain = 0: out = U; chain = 1: the next
 // step's first half step follows at once: ua = CN(U), S = its synthesis input.
-template <int SEG>
-__global__ __launch_bounds__(64 * kSpecWaves) void k_sp_stage2(const double* __restrict__ Q,
+template <int SEG, typename SE>
+__global__ __launch_bounds__(64 * kSpecWaves) void k_sp_stage2(const SE* __restrict__ Q,
                                                   double* __restrict__ ua,
                                                   const double* __restrict__ n1,
                                                   double* __restrict__ out,
-                                                  double* __restrict__ S, double dt, int chain,
+                                                  SE* __restrict__ S, double dt, int chain,
                                                   SpecArgs sa, CnArgs c) {
   const WaveAt w = wave_at<SEG>(sa.M, sa.B);
   if (w.b >= sa.B) return;                            // uniform per wave
@@ -420,9 +432,9 @@ __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_stage2(const double* __r
 }
 
 // Synthesis input of the states in (pint_tendency).
-template <int SEG>
+template <int SEG, typename SE>
 __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_prep(const double* __restrict__ in,
-                                                double* __restrict__ S, SpecArgs sa) {
+                                                SE* __restrict__ S, SpecArgs sa) {
   const WaveAt w = wave_at<SEG>(sa.M, sa.B);
   if (w.b >= sa.B) return;                            // uniform per wave
   double2 V[SEG][3];
@@ -431,8 +443,8 @@ __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_prep(const double* __res
 }
 
 // N(Q) to out (pint_tendency).
-template <int SEG>
-__global__ __launch_bounds__(64 * kSpecWaves) void k_sp_tend(const double* __restrict__ Q,
+template <int SEG, typename SE>
+__global__ __launch_bounds__(64 * kSpecWaves) void k_sp_tend(const SE* __restrict__ Q,
                                                 double* __restrict__ out, SpecArgs sa) {
   const WaveAt w = wave_at<SEG>(sa.M, sa.B);
   if (w.b >= sa.B) return;                            // uniform per wave
@@ -491,12 +503,18 @@ static CnArgs cn_args(const Plan& p, const CnFactors& f, const pint_stepper& st,
   return c;
 }
 
+// launch(SEG, SE): SEG coefficients per lane, SE the element type of the
+// Legendre GEMM operands S and Q (FP32 in the mixed-precision mode).
 #define PINT_SEG_DISPATCH(launch)                                                   \
-  switch (seg_of(p.M)) {                                                            \
-    case 1: launch(1); break;                                                       \
-    case 2: launch(2); break;                                                       \
-    case 4: launch(4); break;                                                       \
-    case 8: launch(8); break;                                                       \
+  switch (seg_of(p.M) * (p.prec == PINT_LEG_FP32 ? -1 : 1)) {                       \
+    case 1: launch(1, double); break;                                               \
+    case 2: launch(2, double); break;                                               \
+    case 4: launch(4, double); break;                                               \
+    case 8: launch(8, double); break;                                               \
+    case -1: launch(1, float); break;                                               \
+    case -2: launch(2, float); break;                                               \
+    case -4: launch(4, float); break;                                               \
+    case -8: launch(8, float); break;                                               \
     default:                                                                        \
       set_error("chains longer than 512 coefficients are not supported (M=%d)", p.M); \
       return PINT_E_INVAL;                                                          \
@@ -508,8 +526,9 @@ pint_status sp_cn_prep(Plan& p, const CnFactors& f, const pint_stepper& st, cons
   const SpecArgs sa = spec_args(p, B);
   const CnArgs c = cn_args(p, f, st, false);
   const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
-#define L(SEG) \
-  hipLaunchKernelGGL(k_sp_cn_prep<SEG>, grid, dim3(64 * kSpecWaves), 0, s, in, p.Ua, p.S, sa, c)
+#define L(SEG, SE)                                                                      \
+  hipLaunchKernelGGL((k_sp_cn_prep<SEG, SE>), grid, dim3(64 * kSpecWaves), 0, s, in, p.Ua, \
+                     reinterpret_cast<SE*>(p.S), sa, c)
   PINT_SEG_DISPATCH(L)
 #undef L
   PINT_HIP(hipGetLastError());
@@ -520,8 +539,9 @@ pint_status sp_stage1(Plan& p, double dt, int B, hipStream_t s) {
   ProfScope ps(p, PK_ASSEMBLE, B, s);
   const SpecArgs sa = spec_args(p, B);
   const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
-#define L(SEG)                                                                              \
-  hipLaunchKernelGGL(k_sp_stage1<SEG>, grid, dim3(64 * kSpecWaves), 0, s, p.Q, p.Ua, p.N1, p.S, \
+#define L(SEG, SE)                                                                    \
+  hipLaunchKernelGGL((k_sp_stage1<SEG, SE>), grid, dim3(64 * kSpecWaves), 0, s,          \
+                     reinterpret_cast<const SE*>(p.Q), p.Ua, p.N1, reinterpret_cast<SE*>(p.S), \
                      dt, sa)
   PINT_SEG_DISPATCH(L)
 #undef L
@@ -535,9 +555,10 @@ pint_status sp_stage2(Plan& p, const CnFactors& f, const pint_stepper& st, doubl
   const SpecArgs sa = spec_args(p, B);
   const CnArgs c = cn_args(p, f, st, true);
   const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
-#define L(SEG)                                                                                  \
-  hipLaunchKernelGGL(k_sp_stage2<SEG>, grid, dim3(64 * kSpecWaves), 0, s, p.Q, p.Ua, p.N1, out, \
-                     p.S, st.dt, chain ? 1 : 0, sa, c)
+#define L(SEG, SE)                                                                    \
+  hipLaunchKernelGGL((k_sp_stage2<SEG, SE>), grid, dim3(64 * kSpecWaves), 0, s,          \
+                     reinterpret_cast<const SE*>(p.Q), p.Ua, p.N1, out,                  \
+                     reinterpret_cast<SE*>(p.S), st.dt, chain ? 1 : 0, sa, c)
   PINT_SEG_DISPATCH(L)
 #undef L
   PINT_HIP(hipGetLastError());
@@ -548,8 +569,9 @@ pint_status sp_prep(Plan& p, const double* in, int B, hipStream_t s) {
   ProfScope ps(p, PK_PREP, B, s);
   const SpecArgs sa = spec_args(p, B);
   const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
-#define L(SEG) \
-  hipLaunchKernelGGL(k_sp_prep<SEG>, grid, dim3(64 * kSpecWaves), 0, s, in, p.S, sa)
+#define L(SEG, SE)                                                                 \
+  hipLaunchKernelGGL((k_sp_prep<SEG, SE>), grid, dim3(64 * kSpecWaves), 0, s, in,      \
+                     reinterpret_cast<SE*>(p.S), sa)
   PINT_SEG_DISPATCH(L)
 #undef L
   PINT_HIP(hipGetLastError());
@@ -560,8 +582,9 @@ pint_status sp_tend(Plan& p, double* out, int B, hipStream_t s) {
   ProfScope ps(p, PK_ASSEMBLE, B, s);
   const SpecArgs sa = spec_args(p, B);
   const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
-#define L(SEG) \
-  hipLaunchKernelGGL(k_sp_tend<SEG>, grid, dim3(64 * kSpecWaves), 0, s, p.Q, out, sa)
+#define L(SEG, SE)                                                                 \
+  hipLaunchKernelGGL((k_sp_tend<SEG, SE>), grid, dim3(64 * kSpecWaves), 0, s,          \
+                     reinterpret_cast<const SE*>(p.Q), out, sa)
   PINT_SEG_DISPATCH(L)
 #undef L
   PINT_HIP(hipGetLastError());
@@ -576,7 +599,7 @@ pint_status sp_cn(Plan& p, const CnFactors& f, const pint_stepper& st0, const pi
   const CnArgs c1 = st1 ? cn_args(p, f, *st1, true) : c0;
   const int two = st1 ? 1 : 0;
   const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
-#define L(SEG)                                                                               \
+#define L(SEG, SE)                                                                           \
   hipLaunchKernelGGL(k_sp_cn<SEG>, grid, dim3(64 * kSpecWaves), 0, s, in, out, two, sa, c0, c1)
   PINT_SEG_DISPATCH(L)
 #undef L

@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(HERE, "libpint.so")
 T_LG, T_LC, T_NL, T_VISC, T_ALL = 1, 2, 4, 8, 15
 PARAREAL, MGRIT = 0, 1
 
+FP64, LEG_FP32 = 0, 1          # pint_config.precision
+
 STATUS = {0: "PINT_OK", -1: "PINT_E_INVAL", -2: "PINT_E_NOMEM", -3: "PINT_E_HIP",
           -4: "PINT_E_DIVERGED", -5: "PINT_E_NOTCONV"}
 
@@ -32,7 +34,8 @@ PROF_KINDS = ["prep", "legendre_synth", "ring_tendency", "legendre_anal", "assem
 class Config(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int), ("nlon", ctypes.c_int), ("nlat", ctypes.c_int),
                 ("a", ctypes.c_double), ("omega", ctypes.c_double), ("g", ctypes.c_double),
-                ("phibar", ctypes.c_double), ("max_batch", ctypes.c_int)]
+                ("phibar", ctypes.c_double), ("max_batch", ctypes.c_int),
+                ("precision", ctypes.c_int)]
 
 
 class Stepper(ctypes.Structure):
@@ -135,12 +138,17 @@ def stepper(dt, visc_order=2, visc_nu=0.0, terms=T_ALL):
 
 
 class Plan:
-    """A truncation / grid / planet and the device tables and workspace."""
+    """A truncation / grid / planet and the device tables and workspace.
+
+    precision: FP64 (default), or LEG_FP32 for Legendre GEMMs, Fourier rows
+    and the grid-space tendencies in FP32 (state, implicit solve and time
+    integration stay FP64)."""
 
     def __init__(self, M, nlon, nlat, a=6.37122e6, omega=7.292e-5, g=9.80616,
-                 phibar=2.94e4, max_batch=64, stream=None):
+                 phibar=2.94e4, max_batch=64, stream=None, precision=FP64):
         lib = load()
-        self.cfg = Config(M, nlon, nlat, a, omega, g, phibar, max_batch)
+        self.cfg = Config(M, nlon, nlat, a, omega, g, phibar, max_batch, precision)
+        self.precision = precision
         h = ctypes.c_void_p()
         _check(lib.pint_plan_create(ctypes.byref(self.cfg), _stream(stream), ctypes.byref(h)))
         self._h = h
