@@ -149,6 +149,11 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
 
   const bool mgrit = q->method == 1;
   const int nrelax = mgrit ? q->nrelax : 0;
+  // Crank-Nicolson factors of both propagators, made on s before any work
+  // goes to the sweep stream
+  const CnFactors* cf = nullptr;
+  PINT_TRY(cn_factors(p, q->fine.dt, q->fine.terms, s, &cf));
+  PINT_TRY(cn_factors(p, q->coarse.dt, q->coarse.terms, s, &cf));
   if (q->resume) {
     // continue from the iterate held in U; the coarse values of its slice
     // starts are recomputed (bitwise what the previous sweep produced)
@@ -184,22 +189,43 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
       PINT_TRY(propagate(p, q->coarse, U, Gold.p, N, q->coarse_steps, s));
       r->coarse_steps += (long long)N * q->coarse_steps;
     }
-    // fine propagation of every active slice (the parallel part)
-    PINT_TRY(propagate(p, q->fine, src + first * sd, Fv.p + first * sd, N - first, q->fine_steps,
-                       s));
-    r->fine_slice_steps += (long long)(N - first) * q->fine_steps;
-    // serial correction sweep: U_{n+1} = (G(U_n^new) - G(U_n^old)) + F(U_n^old)
-    for (int n = first; n < N; ++n) {
-      const double* gnew = Gold.p + n * sd;          // unchanged input at n == first
-      if (n > first) {
-        PINT_TRY(propagate(p, q->coarse, U + n * sd, Gtmp.p, 1, q->coarse_steps, s));
-        r->coarse_steps += q->coarse_steps;
-        gnew = Gtmp.p;
-      }
-      PINT_TRY(pr_update(p, gnew, Gold.p + n * sd, Fv.p + n * sd, U + (n + 1) * sd, sd, s));
-      if (n > first)
-        PINT_HIP(hipMemcpyAsync(Gold.p + n * sd, Gtmp.p, sb, hipMemcpyDeviceToDevice, s));
+    // fine propagation of every active slice (the parallel part), in chunks
+    // of cs slices; chunk c's event releases the sweep steps that need it
+    const int nact = N - first;
+    const int cs = (nact + p.sweep_chunks - 1) / p.sweep_chunks;
+    const int nchunk = (nact + cs - 1) / cs;
+    for (int c = 0; c < nchunk; ++c) {
+      const int n0 = first + c * cs;
+      const int nb = cs < N - n0 ? cs : N - n0;
+      PINT_TRY(propagate(p, q->fine, src + n0 * sd, Fv.p + n0 * sd, nb, q->fine_steps, s));
+      PINT_HIP(hipEventRecord(p.chunk_ev[c], s));
     }
+    r->fine_slice_steps += (long long)nact * q->fine_steps;
+    // serial correction sweep U_{n+1} = (G(U_n^new) - G(U_n^old)) + F(U_n^old)
+    // on the sweep stream and workspace, beside the later chunks.  Step n
+    // reads F(U_n^old) (chunk (n-first)/cs) and overwrites U_{n+1}, the start
+    // of chunk (n+1-first)/cs when it begins one: it waits for both.
+    {
+      SideWork side(p);
+      hipStream_t ss = p.side_stream;
+      int waited = -1;
+      for (int n = first; n < N; ++n) {
+        int need = (n + 1 - first) / cs;
+        if (need > nchunk - 1) need = nchunk - 1;
+        while (waited < need) PINT_HIP(hipStreamWaitEvent(ss, p.chunk_ev[++waited], 0));
+        const double* gnew = Gold.p + n * sd;        // unchanged input at n == first
+        if (n > first) {
+          PINT_TRY(propagate(p, q->coarse, U + n * sd, Gtmp.p, 1, q->coarse_steps, ss));
+          r->coarse_steps += q->coarse_steps;
+          gnew = Gtmp.p;
+        }
+        PINT_TRY(pr_update(p, gnew, Gold.p + n * sd, Fv.p + n * sd, U + (n + 1) * sd, sd, ss));
+        if (n > first)
+          PINT_HIP(hipMemcpyAsync(Gold.p + n * sd, Gtmp.p, sb, hipMemcpyDeviceToDevice, ss));
+      }
+      PINT_HIP(hipEventRecord(p.join_ev, ss));
+    }
+    PINT_HIP(hipStreamWaitEvent(s, p.join_ev, 0));
     // increments (synchronises)
     PINT_TRY(rel_diff(p, U + sd, Uprev.p + sd, incr.data(), N, s));
     // stopping measure: Phi' and the wind (entries 0 and 3 of each slice)

@@ -20,6 +20,7 @@
 
 #include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/pint.h"
@@ -34,6 +35,7 @@ constexpr int kGemmTRAnal = 32;  // Legendre GEMM tile rows per parity (analysis
 constexpr int kGemmTC = 64;      // Legendre GEMM tile columns
 constexpr int kGemmTK = 16;      // Legendre GEMM k-slab staged in LDS
 constexpr int kRingThreads = 512;
+constexpr int kMaxSweepChunks = 64;  // fine-propagation chunks per PinT iteration
 
 void set_error(const char* fmt, ...);
 
@@ -100,6 +102,16 @@ struct Plan {
   double* Q = nullptr;         // [nrows][8 B]    analysis output
   double* Ua = nullptr;        // states [B][3][ncoef] complex: first half-step result
   double* N1 = nullptr;        //   and first-stage tendencies of the IMEX step
+  // serial correction sweep of the PinT drivers: a B = 1 workspace and a
+  // stream of its own, so that the sweep runs beside the fine propagation of
+  // later slices (chunks released by events)
+  struct Work {
+    double *S = nullptr, *F = nullptr, *G = nullptr, *Q = nullptr, *Ua = nullptr, *N1 = nullptr;
+  } side;
+  hipStream_t side_stream = nullptr;
+  std::vector<hipEvent_t> chunk_ev;  // one per fine-propagation chunk
+  hipEvent_t join_ev = nullptr;      // end of a sweep on side_stream
+  int sweep_chunks = 4;
   double* red = nullptr;       // reduction scratch
   double* h_red = nullptr;     // pinned host mirror
   size_t ws_bytes = 0;
@@ -111,6 +123,23 @@ struct Plan {
   std::vector<ProfRec> prof;       // launches recorded since the last read
   std::vector<hipEvent_t> ev_pool; // reusable events
   size_t prof_used = 0;
+};
+
+// While in scope, kernels enqueued on the plan use its B = 1 sweep workspace
+// (enqueueing is sequential on the host, so each launch captures the
+// pointers current at its enqueue).
+struct SideWork {
+  Plan& p;
+  explicit SideWork(Plan& pl) : p(pl) { swap(); }
+  ~SideWork() { swap(); }
+  void swap() {
+    std::swap(p.S, p.side.S);
+    std::swap(p.F, p.side.F);
+    std::swap(p.G, p.side.G);
+    std::swap(p.Q, p.side.Q);
+    std::swap(p.Ua, p.side.Ua);
+    std::swap(p.N1, p.side.N1);
+  }
 };
 
 // Bracket one kernel launch with events when profiling is enabled.

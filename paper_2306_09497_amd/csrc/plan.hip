@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include "pint_internal.h"
@@ -159,9 +160,16 @@ static pint_status dalloc(T** ptr, size_t count, size_t* total) {
 static void free_plan(Plan& p) {
   void* ptrs[] = {p.mu, p.w, p.c2, p.ptab, p.ptabT, p.ptab32, p.ptabT32, p.twid32,
                   p.rowoff, p.rowinfo, p.coefmn, p.twid, p.cnco, p.syn_tiles.dev,
-                  p.ana_tiles.dev, p.S, p.F, p.G, p.Q, p.Ua, p.N1, p.red};
+                  p.ana_tiles.dev, p.S, p.F, p.G, p.Q, p.Ua, p.N1, p.red,
+                  p.side.S, p.side.F, p.side.G, p.side.Q, p.side.Ua, p.side.N1};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
+  for (hipEvent_t e : p.chunk_ev) (void)hipEventDestroy(e);
+  p.chunk_ev.clear();
+  if (p.join_ev) (void)hipEventDestroy(p.join_ev);
+  p.join_ev = nullptr;
+  if (p.side_stream) (void)hipStreamDestroy(p.side_stream);
+  p.side_stream = nullptr;
   if (p.h_red) (void)hipHostFree(p.h_red);
   for (hipEvent_t e : p.ev_pool) (void)hipEventDestroy(e);
   p.ev_pool.clear();
@@ -313,6 +321,12 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
   const size_t sw = (size_t)p.ncoef * B * 3 * 2;
   PLAN_TRY(dalloc(&p.Ua, sw, &tot));
   PLAN_TRY(dalloc(&p.N1, sw, &tot));
+  PLAN_TRY(dalloc(&p.side.S, (size_t)p.nrows * 12, &tot));
+  PLAN_TRY(dalloc(&p.side.F, (size_t)2 * (M + 1) * p.nlat2 * 12, &tot));
+  PLAN_TRY(dalloc(&p.side.G, (size_t)(M + 1) * nlat * 8, &tot));
+  PLAN_TRY(dalloc(&p.side.Q, (size_t)p.nrows * 8, &tot));
+  PLAN_TRY(dalloc(&p.side.Ua, (size_t)p.ncoef * 3 * 2, &tot));
+  PLAN_TRY(dalloc(&p.side.N1, (size_t)p.ncoef * 3 * 2, &tot));
   PLAN_TRY(dalloc(&p.red, (size_t)8 * B + 64, &tot));
   if (hipHostMalloc((void**)&p.h_red, (8 * B + 64) * sizeof(double), 0) != hipSuccess) {
     free_plan(p);
@@ -321,6 +335,28 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
     return PINT_E_NOMEM;
   }
   p.ws_bytes = tot;
+  // the sweep stream does not synchronise with the legacy null stream:
+  // ordering against the caller's stream is by events only
+  if (hipStreamCreateWithFlags(&p.side_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&p.join_ev, hipEventDisableTiming) != hipSuccess) {
+    free_plan(p);
+    delete pp;
+    set_error("hipStreamCreateWithFlags / hipEventCreateWithFlags failed");
+    return PINT_E_HIP;
+  }
+  p.chunk_ev.assign(kMaxSweepChunks, nullptr);
+  for (hipEvent_t& e : p.chunk_ev) {
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      free_plan(p);
+      delete pp;
+      set_error("hipEventCreateWithFlags failed");
+      return PINT_E_HIP;
+    }
+  }
+  if (const char* env = getenv("PINT_SWEEP_CHUNKS")) {
+    const int v = atoi(env);
+    p.sweep_chunks = v < 1 ? 1 : (v > kMaxSweepChunks ? kMaxSweepChunks : v);
+  }
   auto fail_hip = [&](hipError_t e, const char* what) {
     set_error("%s failed: %s", what, hipGetErrorString(e));
     free_plan(p);

@@ -165,3 +165,40 @@ def test_invalid_params_and_divergence(setup):
         pl.step(pint.stepper(-1.0), u0, u0, 1, 1)
     with pytest.raises(pint.PintError):
         pl.step(pint.stepper(60.0, 3, 1e5, T_ALL), u0, u0, 1, 1)
+
+
+@pytest.mark.parametrize("method,nrelax", [(pint.PARAREAL, 0), (pint.MGRIT, 1)])
+def test_sweep_overlap_chunks_bitwise(method, nrelax):
+    """The fine propagation runs in chunks whose events release the serial
+    correction sweep on a second stream: 1, 3 and 8 chunks (the last one
+    slice per chunk) give bitwise the same iterates, and match the oracle."""
+    import os
+    md = Model(M, NLON, NLAT, phibar=PHIBAR)
+    U0 = workloads.solid_body(M, noise=1e-3, seed=4)
+    f = pint.stepper(300.0, 2, 0.0, T_ALL)
+    c = pint.stepper(1200.0, 4, 1e15, T_ALL)
+    prm = pint.params(method, 8, f, 4, c, 1, nrelax=nrelax, max_iter=2)
+    res = []
+    old = os.environ.get("PINT_SWEEP_CHUNKS")
+    try:
+        for chunks in ("1", "3", "8"):
+            os.environ["PINT_SWEEP_CHUNKS"] = chunks
+            pl = pint.Plan(M, NLON, NLAT, phibar=PHIBAR, max_batch=8)
+            got, _ = run_solve(pl, prm, U0, 8)
+            pl.close()
+            res.append(got)
+    finally:
+        if old is None:
+            os.environ.pop("PINT_SWEEP_CHUNKS", None)
+        else:
+            os.environ["PINT_SWEEP_CHUNKS"] = old
+    assert np.array_equal(res[0], res[1]) and np.array_equal(res[0], res[2])
+    phi0 = lambda u: md.propagate(u, 300.0, 4)
+    phi1 = lambda u: md.propagate(u, 1200.0, 1, 1e15, 4, T_ALL)
+    if method == pint.MGRIT:
+        phi0s = lambda u: md.propagate(u, 300.0, 1)
+        ref, _ = opint.mgrit2(U0, 8, 4, phi0s, phi1, 1, 2)
+    else:
+        ref, _ = opint.parareal(U0, 8, phi0, phi1, 2)
+    for i in range(9):
+        assert_parity(res[0][i], ref[i], M)
