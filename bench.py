@@ -36,6 +36,7 @@ NU_COARSE, Q_COARSE = 1.0e17, 4
 PHIBAR = 9.80616e4          # g * 10 km mean depth
 PEAK_FP64 = 78.6e12         # MI355X dense FP64 (matrix and vector), FLOP/s
 PEAK_FP32 = 157.3e12        # MI355X dense FP32 matrix, FLOP/s
+PEAK_BF16 = 2.5e15          # MI355X dense BF16 matrix (3 products per useful one)
 PEAK_HBM = 8.0e12           # MI355X HBM3E, B/s
 
 
@@ -45,9 +46,9 @@ def algorithmic_work(kind, B, prec=0):
     Legendre GEMMs (N/S folded): rows n = m..M+1 per m, parity-split, against
     the nlat/2 northern latitudes; synthesis has 6 fields x (re, im) columns
     per state, analysis 4.  Bytes: table once + operands + result once, at 8
-    bytes per value (FP64) or 4 (FP32 Legendre mode, prec = 1).
+    bytes per value (FP64) or 4 (the mixed modes, prec = 1 or 2).
     """
-    w = 4.0 if prec == 1 else 8.0
+    w = 4.0 if prec in (1, 2) else 8.0
     nrows = (M + 1) * (M + 4) // 2          # sum_m (M - m + 2)
     nl2 = NLAT // 2
     if kind == "legendre_synth":
@@ -291,9 +292,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
-                    help="Legendre/ring precision of the headline (fp32: FP32 Legendre GEMMs, "
-                         "Fourier rows and tendencies; state and solves FP64)")
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16x3"], default="fp64",
+                    help="transform precision of the headline (fp32: FP32 Legendre GEMMs, "
+                         "Fourier rows and tendencies; bf16x3: the same with split-BF16 "
+                         "GEMM products; state and solves FP64 in both)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the FP32-Legendre side measurement of the default run")
     ap.add_argument("--time-to-tol", action="store_true",
@@ -313,11 +315,12 @@ def main():
     from paper_2306_09497_amd import pint
 
     torch.cuda.init()
-    prec = pint.LEG_FP32 if args.precision == "fp32" else pint.FP64
+    prec = {"fp64": pint.FP64, "fp32": pint.LEG_FP32, "bf16x3": pint.LEG_BF16X3}[args.precision]
     res = measure(prec, args.steps, args.warmup)
     prof, elapsed, fine_steps, value = res["prof"], res["elapsed"], res["fine_steps"], res["value"]
     incr = res["incr"]
-    peak_mfma = PEAK_FP32 if prec == pint.LEG_FP32 else PEAK_FP64
+    peak_mfma = {pint.FP64: PEAK_FP64, pint.LEG_FP32: PEAK_FP32,
+                 pint.LEG_BF16X3: PEAK_BF16 / 3.0}[prec]
 
     # dominant kernel of the timed region and its roofline
     per_kind = {}
@@ -359,7 +362,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == pint.FP64 else "f32+f64",
+        "dtype": {pint.FP64: "f64", pint.LEG_FP32: "f32+f64",
+                  pint.LEG_BF16X3: "bf16x3+f32+f64"}[prec],
         "data": "synthetic",
         "config": {
             "workload": "T255 768x384, two-level MGRIT FCF iteration over one slice group: "
@@ -374,17 +378,23 @@ def main():
         "mgrit_increment": incr,
     }
     if prec == pint.FP64 and not args.no_mixed:
-        # the same iterations with FP32 Legendre GEMMs, Fourier rows and
-        # tendencies: throughput and per-field difference of all slice states
-        # from the FP64 path after warmup + steps iterations
-        r32 = measure(pint.LEG_FP32, args.steps, args.warmup)
-        out["fp32_legendre"] = {
-            "value": r32["value"], "unit": "slice-steps/s",
-            "ms_per_step": r32["elapsed"] / args.steps * 1e3,
-            "speedup_vs_fp64": r32["value"] / value,
-            "rel_l2_vs_fp64_path": field_errors(r32["slices"], res["slices"]),
-            "iterations_compared": args.warmup + args.steps,
-        }
+        # the same iterations in the mixed-precision modes (FP32 Fourier rows
+        # and tendencies; FP32 or split-BF16 Legendre GEMM products):
+        # throughput and per-field difference of all slice states from the
+        # FP64 path after warmup + steps iterations
+        mixed = {}
+        for name, mode in (("fp32_legendre", pint.LEG_FP32),
+                           ("bf16x3_legendre", pint.LEG_BF16X3)):
+            rm = measure(mode, args.steps, args.warmup)
+            mixed[name] = {
+                "value": rm["value"], "unit": "slice-steps/s",
+                "ms_per_step": rm["elapsed"] / args.steps * 1e3,
+                "speedup_vs_fp64": rm["value"] / value,
+                "rel_l2_vs_fp64_path": field_errors(rm["slices"], res["slices"]),
+                "iterations_compared": args.warmup + args.steps,
+            }
+            del rm
+        out["mixed_precision"] = mixed
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -64,9 +64,14 @@ enum {
  *   FP32 accumulation), the Fourier intermediates and the ring FFTs with the
  *   pointwise tendencies run in FP32; the spectral state, the Crank-Nicolson
  *   solve, viscosity, the RK combine, table generation, the Parareal/MGRIT
- *   corrections and the norms stay FP64.  The public scalar transforms
- *   (pint_synthesis, pint_analysis) stay FP64 in both modes.  */
-enum { PINT_FP64 = 0, PINT_LEG_FP32 = 1 };
+ *   corrections and the norms stay FP64.
+ * PINT_LEG_BF16X3: as PINT_LEG_FP32, except that each Legendre GEMM product
+ *   runs on the BF16 matrix cores with both FP32 operands split into a BF16
+ *   pair x = hi + lo and three products lo*hi + hi*lo + hi*hi accumulated in
+ *   FP32 (relative rounding near 2^-16 per product).
+ * The public scalar transforms (pint_synthesis, pint_analysis) stay FP64 in
+ * every mode.  Every mode is deterministic and batch invariant.  */
+enum { PINT_FP64 = 0, PINT_LEG_FP32 = 1, PINT_LEG_BF16X3 = 2 };
 
 /* Truncation, grid and planet.  Requires M >= 1, nlat even, nlat >= M+2,
  * nlon >= 2M+2, nlon = 2^a 3^b 5^c <= 1024; the 3/2 rule (nlon >= 3M+3,
@@ -74,7 +79,7 @@ enum { PINT_FP64 = 0, PINT_LEG_FP32 = 1 };
  * phibar is the constant mean geopotential Phibar of L_G (Sec. 2.1).
  * max_batch bounds the number of states one internal launch processes; the
  * plan's workspace is sized for it (larger calls are split into chunks).
- * precision is PINT_FP64 or PINT_LEG_FP32.  */
+ * precision is PINT_FP64, PINT_LEG_FP32 or PINT_LEG_BF16X3.  */
 typedef struct {
   int M, nlon, nlat;
   double a, omega, g, phibar;

@@ -306,6 +306,297 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   }
 }
 
+// ---------------------------------------------------------------------------
+// Split-BF16 variant (PINT_LEG_BF16X3): FP32 operands x = hi + lo with hi the
+// BF16 rounding of x and lo the BF16 rounding of x - hi (exact in FP32);
+// each product sums lo_a hi_b + hi_a lo_b + hi_a hi_b on the BF16 matrix
+// cores (v_mfma_f32_16x16x32_bf16) with FP32 accumulation, dropping lo_a lo_b
+// (three products: Henry, Tang and Heinecke, ARITH 2019).  The split is made
+// while a slab is staged in LDS.  One instruction consumes k in blocks of 32,
+// lane l holding the 8 values k = 8(l/16) + e of row (A) or column (B) l%16,
+// so LDS holds each row and column k-contiguous (one 16-byte read per lane
+// and operand).  Slabs start at k = 0 of each parity for every tile shape:
+// the k-order of every output element is independent of the batch.
+// ---------------------------------------------------------------------------
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__device__ inline void split8(const float (&x)[8], v8bf& hi, v8bf& lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 h = (__bf16)x[e];
+    hi[e] = h;
+    lo[e] = (__bf16)(x[e] - (float)h);
+  }
+}
+
+__device__ inline v4f mma3(v8bf ah, v8bf al, v8bf bh, v8bf bl, v4f c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+}
+
+constexpr int kBfTK = 32;                 // k per slab (one instruction)
+constexpr int kBfKG = kBfTK / 8;          // 8-value groups per row per slab
+constexpr int kBfLD = kBfKG + 1;          // padded LDS row, in 8-value groups
+
+// Synthesis tile as k_legendre_synth: TR = 64 latitudes x TC columns, both
+// parities of one m, epilogue E +- O.  One LDS slab, the next one held in
+// registers while the current one is consumed.
+template <int TC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_legendre_synth_bf3(
+    const float* __restrict__ T, const int* __restrict__ rowoff, const int* __restrict__ tiles,
+    const float* __restrict__ S, float* __restrict__ F, int nlat, int nlat2, int ncol) {
+  constexpr int TR = 64;
+  constexpr int WC = TC == 64 ? 2 : 1;               // waves across columns
+  constexpr int WR = 4 / WC;                         // waves across rows
+  constexpr int BI = TR / WR / 16, BJ = TC / WC / 16;
+  static_assert(BI >= 1 && BJ >= 1 && TR * kBfKG == 256 && TC * kBfKG <= 256, "tile shape");
+  __shared__ v8bf Ah[TR * kBfLD], Al[TR * kBfLD];
+  __shared__ v8bf Bh[TC * kBfLD], Bl[TC * kBfLD];
+
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int nct = (ncol + TC - 1) / TC;
+  const int rt = lb / nct;
+  const int m = tiles[2 * rt] >> 1;
+  const int row0 = tiles[2 * rt + 1];
+  const int col0 = (lb - rt * nct) * TC;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave / WC) * (TR / WR), wc = (wave % WC) * (TC / WC);
+  const int li = lane & 15, lk = lane >> 4;
+  const size_t gbase = (size_t)m * nlat;
+
+  v4f acc[2][BI][BJ];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int i = 0; i < BI; ++i)
+#pragma unroll
+      for (int j = 0; j < BJ; ++j) acc[q][i][j] = (v4f){0.0f, 0.0f, 0.0f, 0.0f};
+
+  const int roff0 = rowoff[2 * m], K0 = rowoff[2 * m + 1] - roff0;
+  const int roff1 = rowoff[2 * m + 1], K1 = rowoff[2 * m + 2] - roff1;
+  const int ns0 = (K0 + kBfTK - 1) / kBfTK, ns1 = (K1 + kBfTK - 1) / kBfTK;
+  const int nslab = ns0 + ns1;
+  // loader roles: A row ra_r (lanes along latitudes), k-group ra_g; B column
+  // rb_c (lanes along columns), k-group rb_g, for the first TC * 4 threads
+  const int ra_r = tid % TR, ra_g = tid / TR;
+  const bool bload = tid < TC * kBfKG;
+  const int rb_c = tid % TC, rb_g = tid / TC;
+  float xa[8], xb[8];
+  auto fetch = [&](int sl) {
+    const bool second = sl >= ns0;
+    const int roff = second ? roff1 : roff0;
+    const int K = second ? K1 : K0;
+    const int k0 = (second ? sl - ns0 : sl) * kBfTK + 8 * ra_g;
+    const int r = row0 + ra_r;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = k0 + e;
+      xa[e] = (k < K && r < nlat2) ? T[(size_t)(roff + k) * nlat2 + r] : 0.0f;
+    }
+    if (bload) {
+      const int kb = (second ? sl - ns0 : sl) * kBfTK + 8 * rb_g;
+      const int c = col0 + rb_c;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = kb + e;
+        xb[e] = (k < K && c < ncol) ? S[(size_t)(roff + k) * ncol + c] : 0.0f;
+      }
+    }
+  };
+  auto stash = [&]() {
+    v8bf h, l;
+    split8(xa, h, l);
+    Ah[ra_r * kBfLD + ra_g] = h;
+    Al[ra_r * kBfLD + ra_g] = l;
+    if (bload) {
+      split8(xb, h, l);
+      Bh[rb_c * kBfLD + rb_g] = h;
+      Bl[rb_c * kBfLD + rb_g] = l;
+    }
+  };
+  auto mma = [&](v4f (&ac)[BI][BJ]) {
+    v8bf ah[BI], al[BI], bh[BJ], bl[BJ];
+#pragma unroll
+    for (int i = 0; i < BI; ++i) {
+      ah[i] = Ah[(wr + 16 * i + li) * kBfLD + lk];
+      al[i] = Al[(wr + 16 * i + li) * kBfLD + lk];
+    }
+#pragma unroll
+    for (int j = 0; j < BJ; ++j) {
+      bh[j] = Bh[(wc + 16 * j + li) * kBfLD + lk];
+      bl[j] = Bl[(wc + 16 * j + li) * kBfLD + lk];
+    }
+#pragma unroll
+    for (int i = 0; i < BI; ++i)
+#pragma unroll
+      for (int j = 0; j < BJ; ++j) ac[i][j] = mma3(ah[i], al[i], bh[j], bl[j], ac[i][j]);
+  };
+
+  if (nslab > 0) {
+    fetch(0);
+    stash();
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    for (int sl = q ? ns0 : 0; sl < (q ? nslab : ns0); ++sl) {
+      if (sl + 1 < nslab) fetch(sl + 1);
+      mma(acc[q]);
+      if (sl + 1 < nslab) {
+        __syncthreads();                             // every wave has read the slab
+        stash();
+      }
+      __syncthreads();
+    }
+  }
+  // store: register i of lane l holds D[4(l/16) + i][l%16]
+#pragma unroll
+  for (int bi = 0; bi < BI; ++bi) {
+#pragma unroll
+    for (int bj = 0; bj < BJ; ++bj) {
+      const int c = col0 + wc + bj * 16 + li;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = row0 + wr + bi * 16 + 4 * lk + i;
+        if (r < nlat2 && c < ncol) {
+          const float e = acc[0][bi][bj][i], o = acc[1][bi][bj][i];
+          F[(gbase + r) * ncol + c] = e + o;
+          F[(gbase + (nlat - 1 - r)) * ncol + c] = e - o;
+        }
+      }
+    }
+  }
+}
+
+// Analysis tile as k_legendre_anal: 32 rows of each parity x TC columns,
+// contraction over the northern latitudes with B_E = G(k) + G(nlat-1-k),
+// B_O = G(k) - G(nlat-1-k).  One LDS slab (the next one is held in registers
+// while the current one is consumed) keeps four workgroups per CU.
+template <int TC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_legendre_anal_bf3(
+    const float* __restrict__ Tt, const int* __restrict__ rowoff, const int* __restrict__ tiles,
+    const float* __restrict__ G, float* __restrict__ Q, int nlat, int nlat2, int ncol,
+    int nrows) {
+  constexpr int TR2 = 32, TR = 2 * TR2;
+  constexpr int WC = TC >= 32 ? TC / 32 : 1;
+  constexpr int WR = 4 / WC;
+  constexpr int BI = TR / WR / 16, BJ = TC / WC / 16;
+  static_assert(BI >= 1 && BJ >= 1 && (TR / WR) <= TR2 && TR * kBfKG == 256 &&
+                    TC * kBfKG <= 256, "tile shape");
+  __shared__ v8bf Ah[TR * kBfLD], Al[TR * kBfLD];
+  __shared__ v8bf Bh[2][TC * kBfLD], Bl[2][TC * kBfLD];         // [parity]
+
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int nct = (ncol + TC - 1) / TC;
+  const int rt = lb / nct;
+  const int m = tiles[2 * rt] >> 1;
+  const int row0 = tiles[2 * rt + 1];
+  const int col0 = (lb - rt * nct) * TC;
+  const int roffE = rowoff[2 * m], cntE = rowoff[2 * m + 1] - roffE;
+  const int roffO = rowoff[2 * m + 1], cntO = rowoff[2 * m + 2] - roffO;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave / WC) * (TR / WR), wc = (wave % WC) * (TC / WC);
+  const int par = wr >= TR2;                         // uniform per wave
+  const int li = lane & 15, lk = lane >> 4;
+  const size_t gbase = (size_t)m * nlat;
+
+  v4f acc[BI][BJ];
+#pragma unroll
+  for (int i = 0; i < BI; ++i)
+#pragma unroll
+    for (int j = 0; j < BJ; ++j) acc[i][j] = (v4f){0.0f, 0.0f, 0.0f, 0.0f};
+
+  const int ra_r = tid % TR, ra_g = tid / TR;
+  const bool a_odd = ra_r >= TR2;
+  const int a_row = row0 + (a_odd ? ra_r - TR2 : ra_r);
+  const bool a_ok = a_row < (a_odd ? cntO : cntE);
+  const int a_off = (a_odd ? roffO : roffE) + a_row;
+  const bool bload = tid < TC * kBfKG;
+  const int rb_c = tid % TC, rb_g = tid / TC;
+  float xa[8], xe[8], xo[8];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = k0 + 8 * ra_g + e;
+      xa[e] = (a_ok && k < nlat2) ? Tt[(size_t)k * nrows + a_off] : 0.0f;
+    }
+    if (bload) {
+      const int c = col0 + rb_c;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = k0 + 8 * rb_g + e;
+        float ve = 0.0f, vo = 0.0f;
+        if (k < nlat2 && c < ncol) {
+          const float gn = G[(gbase + k) * ncol + c];
+          const float gs = G[(gbase + (nlat - 1 - k)) * ncol + c];
+          ve = gn + gs;
+          vo = gn - gs;
+        }
+        xe[e] = ve;
+        xo[e] = vo;
+      }
+    }
+  };
+  auto stash = [&]() {
+    v8bf h, l;
+    split8(xa, h, l);
+    Ah[ra_r * kBfLD + ra_g] = h;
+    Al[ra_r * kBfLD + ra_g] = l;
+    if (bload) {
+      split8(xe, h, l);
+      Bh[0][rb_c * kBfLD + rb_g] = h;
+      Bl[0][rb_c * kBfLD + rb_g] = l;
+      split8(xo, h, l);
+      Bh[1][rb_c * kBfLD + rb_g] = h;
+      Bl[1][rb_c * kBfLD + rb_g] = l;
+    }
+  };
+  const int nslab = (nlat2 + kBfTK - 1) / kBfTK;
+  fetch(0);
+  stash();
+  __syncthreads();
+  for (int sl = 0; sl < nslab; ++sl) {
+    if (sl + 1 < nslab) fetch((sl + 1) * kBfTK);
+    v8bf ah[BI], al[BI], bh[BJ], bl[BJ];
+#pragma unroll
+    for (int i = 0; i < BI; ++i) {
+      ah[i] = Ah[(wr + 16 * i + li) * kBfLD + lk];
+      al[i] = Al[(wr + 16 * i + li) * kBfLD + lk];
+    }
+#pragma unroll
+    for (int j = 0; j < BJ; ++j) {
+      bh[j] = Bh[par][(wc + 16 * j + li) * kBfLD + lk];
+      bl[j] = Bl[par][(wc + 16 * j + li) * kBfLD + lk];
+    }
+#pragma unroll
+    for (int i = 0; i < BI; ++i)
+#pragma unroll
+      for (int j = 0; j < BJ; ++j) acc[i][j] = mma3(ah[i], al[i], bh[j], bl[j], acc[i][j]);
+    if (sl + 1 < nslab) {
+      __syncthreads();                               // every wave has read the slab
+      stash();
+    }
+    __syncthreads();
+  }
+  const int roff = par ? roffO : roffE, cnt = par ? cntO : cntE;
+  const int wrp = wr - par * TR2;
+#pragma unroll
+  for (int bi = 0; bi < BI; ++bi) {
+#pragma unroll
+    for (int bj = 0; bj < BJ; ++bj) {
+      const int c = col0 + wc + bj * 16 + li;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = row0 + wrp + bi * 16 + 4 * lk + i;
+        if (r < cnt && c < ncol) Q[(size_t)(roff + r) * ncol + c] = acc[bi][bj][i];
+      }
+    }
+  }
+}
+
 template <typename E>
 static void launch_synth(Plan& p, const E* T, const E* S, E* F, int ncol, hipStream_t s) {
   if (ncol <= 32) {
@@ -332,10 +623,42 @@ static void launch_anal(Plan& p, const E* Tt, const E* G, E* Q, int ncol, hipStr
   }
 }
 
+static void launch_synth_bf3(Plan& p, int ncol, hipStream_t s) {
+  const float* T = p.ptab32;
+  const float* S = reinterpret_cast<const float*>(p.S);
+  float* F = reinterpret_cast<float*>(p.F);
+  if (ncol <= 32) {
+    dim3 grid(((ncol + 15) / 16) * p.syn_tiles.count);
+    hipLaunchKernelGGL(k_legendre_synth_bf3<16>, grid, dim3(256), 0, s, T, p.rowoff,
+                       p.syn_tiles.dev, S, F, p.nlat, p.nlat2, ncol);
+  } else {
+    dim3 grid(((ncol + 63) / 64) * p.syn_tiles.count);
+    hipLaunchKernelGGL(k_legendre_synth_bf3<64>, grid, dim3(256), 0, s, T, p.rowoff,
+                       p.syn_tiles.dev, S, F, p.nlat, p.nlat2, ncol);
+  }
+}
+
+static void launch_anal_bf3(Plan& p, int ncol, hipStream_t s) {
+  const float* Tt = p.ptabT32;
+  const float* G = reinterpret_cast<const float*>(p.G);
+  float* Q = reinterpret_cast<float*>(p.Q);
+  if (ncol <= 32) {
+    dim3 grid(((ncol + 15) / 16) * p.ana_tiles.count);
+    hipLaunchKernelGGL(k_legendre_anal_bf3<16>, grid, dim3(256), 0, s, Tt, p.rowoff,
+                       p.ana_tiles.dev, G, Q, p.nlat, p.nlat2, ncol, p.nrows);
+  } else {
+    dim3 grid(((ncol + 63) / 64) * p.ana_tiles.count);
+    hipLaunchKernelGGL(k_legendre_anal_bf3<64>, grid, dim3(256), 0, s, Tt, p.rowoff,
+                       p.ana_tiles.dev, G, Q, p.nlat, p.nlat2, ncol, p.nrows);
+  }
+}
+
 pint_status legendre_synth(Plan& p, int B, int nf, int prec, hipStream_t s) {
   ProfScope ps(p, PK_SYNTH, nf == kSynFields ? B : -B, s);
   const int ncol = 2 * nf * B;
-  if (prec == PINT_LEG_FP32)
+  if (prec == PINT_LEG_BF16X3)
+    launch_synth_bf3(p, ncol, s);
+  else if (prec == PINT_LEG_FP32)
     launch_synth<float>(p, p.ptab32, reinterpret_cast<const float*>(p.S),
                         reinterpret_cast<float*>(p.F), ncol, s);
   else
@@ -347,7 +670,9 @@ pint_status legendre_synth(Plan& p, int B, int nf, int prec, hipStream_t s) {
 pint_status legendre_anal(Plan& p, int B, int nf, int prec, hipStream_t s) {
   ProfScope ps(p, PK_ANAL, nf == kAnaFields ? B : -B, s);
   const int ncol = 2 * nf * B;
-  if (prec == PINT_LEG_FP32)
+  if (prec == PINT_LEG_BF16X3)
+    launch_anal_bf3(p, ncol, s);
+  else if (prec == PINT_LEG_FP32)
     launch_anal<float>(p, p.ptabT32, reinterpret_cast<const float*>(p.G),
                        reinterpret_cast<float*>(p.Q), ncol, s);
   else

@@ -230,8 +230,10 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
               "256 384 512 640 768 1024)", nlon);
     return PINT_E_INVAL;
   }
-  if (cfg->precision != PINT_FP64 && cfg->precision != PINT_LEG_FP32) {
-    set_error("pint_plan_create: precision must be PINT_FP64 or PINT_LEG_FP32 (got %d)",
+  if (cfg->precision != PINT_FP64 && cfg->precision != PINT_LEG_FP32 &&
+      cfg->precision != PINT_LEG_BF16X3) {
+    set_error("pint_plan_create: precision must be PINT_FP64, PINT_LEG_FP32 or PINT_LEG_BF16X3 "
+              "(got %d)",
               cfg->precision);
     return PINT_E_INVAL;
   }
@@ -305,7 +307,7 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
   PLAN_TRY(dalloc(&p.rowinfo, rowinfo.size(), &tot));
   PLAN_TRY(dalloc(&p.coefmn, coefmn.size(), &tot));
   PLAN_TRY(dalloc(&p.twid, nlon, &tot));
-  if (p.prec == PINT_LEG_FP32) {
+  if (p.prec != PINT_FP64) {
     PLAN_TRY(dalloc(&p.ptab32, (size_t)p.nrows * p.nlat2, &tot));
     PLAN_TRY(dalloc(&p.ptabT32, (size_t)p.nrows * p.nlat2, &tot));
     PLAN_TRY(dalloc(&p.twid32, nlon, &tot));
@@ -377,7 +379,7 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
   hipLaunchKernelGGL(k_ptab, dim3((p.nlat2 + 63) / 64, M + 1), dim3(64), 0, s, M, p.nlat2,
                      p.nrows, p.mu, p.c2, p.rowoff, p.ptab, p.ptabT);
   hipLaunchKernelGGL(k_twiddle, dim3((nlon + 255) / 256), dim3(256), 0, s, nlon, p.twid);
-  if (p.prec == PINT_LEG_FP32) {
+  if (p.prec != PINT_FP64) {
     const size_t nt = (size_t)p.nrows * p.nlat2;
     hipLaunchKernelGGL(k_to_float, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, p.ptab,
                        p.ptab32, nt);

@@ -771,7 +771,7 @@ bool ring_supported(int nlon) {
 // Dynamic LDS of the tendency ring kernel: 4 half-length signals (complex
 // FP64, or FP32 in the mixed-precision mode).
 size_t ring_lds_bytes(int nlon, int prec) {
-  const size_t cx = prec == PINT_LEG_FP32 ? sizeof(float2) : sizeof(double2);
+  const size_t cx = prec != PINT_FP64 ? sizeof(float2) : sizeof(double2);
   switch (nlon) {
 #define PINT_CASE(n) \
   case n:            \
@@ -805,7 +805,7 @@ pint_status ring_prepare(int nlon) {
 
 pint_status ring_tendency(Plan& p, int B, hipStream_t s) {
   ProfScope ps(p, PK_RING, B, s);
-  const bool f32 = p.prec == PINT_LEG_FP32;
+  const bool f32 = p.prec != PINT_FP64;
   switch (p.nlon) {
 #define PINT_CASE(n)                                                                         \
   case n:                                                                                    \

@@ -504,9 +504,9 @@ static CnArgs cn_args(const Plan& p, const CnFactors& f, const pint_stepper& st,
 }
 
 // launch(SEG, SE): SEG coefficients per lane, SE the element type of the
-// Legendre GEMM operands S and Q (FP32 in the mixed-precision mode).
+// Legendre GEMM operands S and Q (FP32 in the mixed-precision modes).
 #define PINT_SEG_DISPATCH(launch)                                                   \
-  switch (seg_of(p.M) * (p.prec == PINT_LEG_FP32 ? -1 : 1)) {                       \
+  switch (seg_of(p.M) * (p.prec != PINT_FP64 ? -1 : 1)) {                           \
     case 1: launch(1, double); break;                                               \
     case 2: launch(2, double); break;                                               \
     case 4: launch(4, double); break;                                               \

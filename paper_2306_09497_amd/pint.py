@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libpint.so")
 T_LG, T_LC, T_NL, T_VISC, T_ALL = 1, 2, 4, 8, 15
 PARAREAL, MGRIT = 0, 1
 
-FP64, LEG_FP32 = 0, 1          # pint_config.precision
+FP64, LEG_FP32, LEG_BF16X3 = 0, 1, 2    # pint_config.precision
 
 STATUS = {0: "PINT_OK", -1: "PINT_E_INVAL", -2: "PINT_E_NOMEM", -3: "PINT_E_HIP",
           -4: "PINT_E_DIVERGED", -5: "PINT_E_NOTCONV"}
@@ -140,9 +140,10 @@ def stepper(dt, visc_order=2, visc_nu=0.0, terms=T_ALL):
 class Plan:
     """A truncation / grid / planet and the device tables and workspace.
 
-    precision: FP64 (default), or LEG_FP32 for Legendre GEMMs, Fourier rows
-    and the grid-space tendencies in FP32 (state, implicit solve and time
-    integration stay FP64)."""
+    precision: FP64 (default); LEG_FP32 for Legendre GEMMs, Fourier rows and
+    the grid-space tendencies in FP32 (state, implicit solve and time
+    integration stay FP64); LEG_BF16X3 as LEG_FP32 with the GEMM products as
+    three BF16 matrix-core products of split operands."""
 
     def __init__(self, M, nlon, nlat, a=6.37122e6, omega=7.292e-5, g=9.80616,
                  phibar=2.94e4, max_batch=64, stream=None, precision=FP64):

@@ -1,7 +1,8 @@
-"""GPU tests of the FP32 Legendre mode (PINT_LEG_FP32): the Legendre GEMMs,
+"""GPU tests of the mixed-precision modes.  PINT_LEG_FP32: the Legendre GEMMs,
 the Fourier rows and the ring FFT + pointwise tendencies run in FP32, while
 the state, the implicit solve, viscosity, the RK combine, the tables and the
-PinT corrections stay FP64.
+PinT corrections stay FP64.  PINT_LEG_BF16X3: the same, with each GEMM
+product as three BF16 matrix-core products of split FP32 operands.
 
 The error of this mode against the FP64 oracle is stated, not pinned by the
 paper: the bounds below are measured on MI355X with a margin, per field and
@@ -37,11 +38,23 @@ CONFIGS = {
 # divergence carries n(n+1)/a^2 times the FP32 rounding of the analysed
 # kinetic energy, which grows with the truncation and is large against the
 # small divergence tendency of a balanced jet.
-TOL_TEND = {"T63": (2e-6, 2e-6, 2e-4), "T127": (2e-6, 2e-6, 1e-3),
-            "T255": (2e-6, 2e-6, 5e-3)}
-TOL_STEP = {"T63": (2e-7, 2e-7, 5e-5), "T127": (2e-7, 2e-7, 2e-4),
-            "T255": (2e-7, 2e-7, 2e-3)}
-TOL_STATE_STEP = 2e-7         # (Phi', wind) after the steps
+TOL = {
+    "fp32": {
+        "tend": {"T63": (2e-6, 2e-6, 2e-4), "T127": (2e-6, 2e-6, 1e-3),
+                 "T255": (2e-6, 2e-6, 5e-3)},
+        "step": {"T63": (2e-7, 2e-7, 5e-5), "T127": (2e-7, 2e-7, 2e-4),
+                 "T255": (2e-7, 2e-7, 2e-3)},
+        "state": 2e-7,            # (Phi', wind) after the steps
+    },
+    "bf16x3": {
+        "tend": {"T63": (1e-4, 1e-4, 3e-3), "T127": (1e-4, 1e-4, 2e-2),
+                 "T255": (1e-4, 1e-4, 6e-2)},
+        "step": {"T63": (5e-6, 5e-6, 1e-3), "T127": (5e-6, 5e-6, 1e-2),
+                 "T255": (5e-6, 5e-6, 5e-2)},
+        "state": 5e-6,
+    },
+}
+MODES = {"fp32": pint.LEG_FP32, "bf16x3": pint.LEG_BF16X3}
 FLOOR = 1e-10                 # FP32 arithmetic must show above FP64 rounding
 
 _models, _plans = {}, {}
@@ -87,10 +100,11 @@ def check_mixed(errs, tol):
         assert np.max(e) > FLOOR, (what, "error at FP64 level: FP32 path not taken?", e)
 
 
+@pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("key", ["T63", "T127", "T255"])
-def test_fp32_tendency(key):
-    """Rows a1-a7 in FP32 Legendre mode: one N-eval of two states."""
-    md, pl = model(key), plan(key)
+def test_mixed_tendency(key, mode):
+    """Rows a1-a7 in the mixed modes: one N-eval of two states."""
+    md, pl = model(key), plan(key, MODES[mode])
     U1 = jet(key, lam_c=1.0)
     U2 = jet(key, lam_c=4.0, amp=80.0, extra_noise=1e-3, seed=3)
     u = to_dev(np.stack([U1, U2]), torch)
@@ -98,16 +112,27 @@ def test_fp32_tendency(key):
     pl.tendency(u, out, 2)
     torch.cuda.synchronize()
     got = from_dev(out)
-    errs = [(f"{key} tendency b={b}", mixed_errors(got[b], md.tendencies(U), md.M, key))
+    errs = [(f"{mode} {key} tendency b={b}",
+             mixed_errors(got[b], md.tendencies(U), md.M, f"{mode} {key} tendency b={b}"))
             for b, U in enumerate((U1, U2))]
-    check_mixed(errs, TOL_TEND[key])
+    check_mixed(errs, TOL[mode]["tend"][key])
+    if mode == "bf16x3":
+        # the split-BF16 products round near 2^-16: well above the FP32 mode
+        o32 = torch.zeros_like(u)
+        plan(key, pint.LEG_FP32).tendency(u, o32, 2)
+        torch.cuda.synchronize()
+        g32 = from_dev(o32)
+        for b, U in enumerate((U1, U2)):
+            e32 = rel_err(g32[b], md.tendencies(U), md.M)
+            assert np.max(errs[b][1]) > 4 * np.max(e32), (errs[b][1], e32)
 
 
+@pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("key,dt,nsteps", [("T63", 240.0, 10), ("T127", 30.0, 4),
                                            ("T255", 45.0, 1)])
-def test_fp32_step(key, dt, nsteps):
-    """Row a10 in FP32 Legendre mode: IMEX steps with viscosity."""
-    md, pl = model(key), plan(key)
+def test_mixed_step(key, dt, nsteps, mode):
+    """Row a10 in the mixed modes: IMEX steps with viscosity."""
+    md, pl = model(key), plan(key, MODES[mode])
     U1 = jet(key, lam_c=2.0)
     U2 = jet(key, lam_c=5.0, amp=150.0, extra_noise=1e-4, seed=5)
     nu = 1e15 if md.M <= 127 else 1e14
@@ -122,20 +147,22 @@ def test_fp32_step(key, dt, nsteps):
     errs = []
     for b, U in enumerate((U1, U2)):
         ref = md.propagate(U, dt, nsteps, nu, 4, T_ALL)
-        e = mixed_errors(got[b], ref, md.M, f"{key} {nsteps} steps b={b}")
+        e = mixed_errors(got[b], ref, md.M, f"{mode} {key} {nsteps} steps b={b}")
         st_e = state_rel_err(got[b], ref, md.M)
         print(f"  state (Phi', wind) rel L2 = {st_e}", flush=True)
         # the FP64 GPU path is at the oracle to 1e-11, so both differences agree
         e64 = rel_err(got[b], g64[b], md.M)
         assert np.allclose(e, e64, rtol=1e-2, atol=1e-11), (e, e64)
-        assert np.all(st_e < TOL_STATE_STEP), st_e
-        errs.append((f"{key} {nsteps} steps b={b}", e))
-    check_mixed(errs, TOL_STEP[key])
+        assert np.all(st_e < TOL[mode]["state"]), st_e
+        errs.append((f"{mode} {key} {nsteps} steps b={b}", e))
+    check_mixed(errs, TOL[mode]["step"][key])
 
 
-def test_fp32_batch_invariance_bitwise():
-    """FP32 mode keeps a slice's result bitwise independent of the batch."""
-    pl = plan("T63", max_batch=16)
+@pytest.mark.parametrize("mode", list(MODES))
+def test_mixed_batch_invariance_bitwise(mode):
+    """The mixed modes keep a slice's result bitwise independent of the
+    batch (the narrow and the wide GEMM tiles sum in the same k-order)."""
+    pl = plan("T63", MODES[mode], max_batch=16)
     Us = [jet("T63", lam_c=0.3 * i, amp=50.0 + 7 * i) for i in range(9)]
     st = pint.stepper(240.0, 4, 1e15, T_ALL)
     single = []
@@ -151,12 +178,13 @@ def test_fp32_batch_invariance_bitwise():
         assert torch.equal(u[order.index(i)], single[i][0])
 
 
-def test_fp32_parareal_exact_bitwise():
+@pytest.mark.parametrize("mode", list(MODES))
+def test_mixed_parareal_exact_bitwise(mode):
     """Parareal after N iterations reproduces the serial fine states bitwise
-    in FP32 mode too (the fine propagator is deterministic and batch
+    in the mixed modes too (the fine propagator is deterministic and batch
     invariant)."""
     M, nlon, nlat = CONFIGS["T21"]
-    pl = pint.Plan(M, nlon, nlat, phibar=2.94e4, max_batch=8, precision=pint.LEG_FP32)
+    pl = pint.Plan(M, nlon, nlat, phibar=2.94e4, max_batch=8, precision=MODES[mode])
     U0 = workloads.solid_body(M, noise=1e-6, seed=0)
     f = pint.stepper(60.0, 2, 0.0, T_ALL)
     c = pint.stepper(3600.0, 2, 0.0, T_ALL)
@@ -171,10 +199,11 @@ def test_fp32_parareal_exact_bitwise():
     pl.close()
 
 
-def test_fp32_mode_keeps_fp64_parts():
+@pytest.mark.parametrize("mode", list(MODES))
+def test_mixed_mode_keeps_fp64_parts(mode):
     """The implicit solve and the public scalar transforms stay FP64 in the
-    FP32 Legendre mode: bitwise equal to the FP64 plan's."""
-    p32, p64 = plan("T63"), plan("T63", pint.FP64)
+    mixed modes: bitwise equal to the FP64 plan's."""
+    p32, p64 = plan("T63", MODES[mode]), plan("T63", pint.FP64)
     U = jet("T63", extra_noise=1e-3, seed=1)
     st = pint.stepper(240.0, 4, 1e15, T_ALL)
     u = to_dev(U, torch)
