@@ -69,28 +69,30 @@ def algorithmic_work(kind, B, prec=0):
 
 
 # HBM bytes per launch (64 states) measured with rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE on `python -m paper_2306_09497_amd.profile_drivers tendency 64 3`,
-# each counter scaled by what it reads for a plain 1 GiB copy (FETCH x 2.0,
-# WRITE x 1.0), together with the SHA-256 prefixes of the kernel sources the
-# counters were taken on: a changed kernel reports traffic null until measured
-# again.
+# WRITE_SIZE on `python -m paper_2306_09497_amd.profile_drivers tendency 64 3
+# <precision>`, each counter scaled by what it reads for a plain 1 GiB copy
+# (FETCH x 2.0, WRITE x 1.0), keyed by (kernel, precision), together with the
+# SHA-256 prefixes of the kernel sources the counters were taken on: a changed
+# kernel reports traffic null until measured again.
+_RING = {"ring.hip": "ffd9b9bcd31936cf", "pint_internal.h": "31c926f598b6c803"}
+_LEG = {"legendre.hip": "1339305e6e6a217c", "pint_internal.h": "31c926f598b6c803"}
 MEASURED_TRAFFIC = {
-    "ring_tendency": (426840 * 1024 * 2.0 + 526943 * 1024 * 1.0,
-                      {"ring.hip": "2c8cf9d65eca3ab5", "pint_internal.h": "94cdad926a991421"}),
-    "legendre_synth": (139669 * 1024 * 2.0 + 589824 * 1024 * 1.0,
-                       {"legendre.hip": "8710d86473a8fcae", "pint_internal.h": "94cdad926a991421"}),
-    "legendre_anal": (246535 * 1024 * 2.0 + 132608 * 1024 * 1.0,
-                      {"legendre.hip": "8710d86473a8fcae", "pint_internal.h": "94cdad926a991421"}),
+    ("ring_tendency", 0): (422539 * 1024 * 2.0 + 529465 * 1024 * 1.0, _RING),
+    ("legendre_synth", 0): (140736 * 1024 * 2.0 + 589824 * 1024 * 1.0, _LEG),
+    ("legendre_anal", 0): (247966 * 1024 * 2.0 + 132608 * 1024 * 1.0, _LEG),
+    ("ring_tendency", 1): (154575 * 1024 * 2.0 + 214128 * 1024 * 1.0, _RING),
+    ("legendre_synth", 1): (63824 * 1024 * 2.0 + 296308 * 1024 * 1.0, _LEG),
+    ("legendre_anal", 1): (120178 * 1024 * 2.0 + 66304 * 1024 * 1.0, _LEG),
 }
 
 
-def measured_traffic(kind):
-    """Counter-measured HBM bytes per launch of `kind`, or None if absent or
-    if its sources changed since the counters were taken."""
+def measured_traffic(kind, prec=0):
+    """Counter-measured HBM bytes per launch of `kind` at precision `prec`, or
+    None if absent or if its sources changed since the counters were taken."""
     import hashlib
-    if kind not in MEASURED_TRAFFIC:
+    if (kind, prec) not in MEASURED_TRAFFIC:
         return None
-    byts, srcs = MEASURED_TRAFFIC[kind]
+    byts, srcs = MEASURED_TRAFFIC[(kind, prec)]
     csrc = os.path.join(ROOT, "paper_2306_09497_amd", "csrc")
     for name, digest in srcs.items():
         with open(os.path.join(csrc, name), "rb") as f:
@@ -338,7 +340,7 @@ def main():
         roof = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": PEAK_HBM / 1e9,
                 "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(dom) if prec == pint.FP64 else None
+    roof["traffic"] = measured_traffic(dom, prec)
     roof["kernel"] = dom
     roof["avg_launch_ms"] = tot_ms / n_launch
 

@@ -1,9 +1,10 @@
 """Small fixed workloads for hardware-counter runs (rocprofv3 --pmc).
 
-    python -m paper_2306_09497_amd.profile_drivers tendency [B] [reps]
+    python -m paper_2306_09497_amd.profile_drivers tendency [B] [reps] [precision]
         N(U) of B T255 768x384 jet + bump states, `reps` times: one spectral
         prep, Legendre synthesis GEMM, ring FFT + tendency kernel, Legendre
-        analysis GEMM and assembly per call (Sec. 2.2).
+        analysis GEMM and assembly per call (Sec. 2.2); precision 0 (FP64),
+        1 (FP32 Legendre) or 2 (split-BF16 Legendre).
     python -m paper_2306_09497_amd.profile_drivers copy [reps]
         a plain 1 GiB device-to-device copy, the calibration of FETCH_SIZE and
         WRITE_SIZE against a known byte count.
@@ -15,12 +16,12 @@ M, NLON, NLAT = 255, 768, 384
 PHIBAR = 9.80616e4
 
 
-def tendency(B=64, reps=3):
+def tendency(B=64, reps=3, precision=0):
     import numpy as np
     import torch
     from paper_2306_09497_amd import pint, workloads
 
-    plan = pint.Plan(M, NLON, NLAT, phibar=PHIBAR, max_batch=B)
+    plan = pint.Plan(M, NLON, NLAT, phibar=PHIBAR, max_batch=B, precision=precision)
     mu, _ = plan.grid_coords()
     G = workloads.jet_bump_grid(mu, NLON, phibar=PHIBAR, **workloads.jet_bump_params(0))
     grid = torch.from_numpy(np.ascontiguousarray(G)).cuda()
@@ -32,7 +33,8 @@ def tendency(B=64, reps=3):
         plan.tendency(u, out, B)
     torch.cuda.synchronize()
     plan.close()
-    print(f"tendency: {reps} calls of B={B} at T{M} {NLON}x{NLAT}", flush=True)
+    print(f"tendency: {reps} calls of B={B} at T{M} {NLON}x{NLAT}, precision {precision}",
+          flush=True)
 
 
 def copy(reps=3):
