@@ -478,14 +478,23 @@ __device__ inline void ip_stage(C* buf, const C* __restrict__ tw, int tid) {
       C v[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) v[r] = buf[Lay::at(sig, base + r * S)];
+      // twiddles W^{j r}, r = 1..R-1: W and W^2 from the table, higher powers
+      // as products of those (one rounding each)
+      C w[R];
+      if constexpr (S > 1) {
+        w[1] = twid<SGN>(tw, j * TWS);
+        if constexpr (R > 2) w[2] = twid<SGN>(tw, 2 * j * TWS);
+#pragma unroll
+        for (int r = 3; r < R; ++r) w[r] = c_mul(w[r - 2], w[2]);
+      }
       if constexpr (!kDif && S > 1) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[r] = c_mul(v[r], twid<SGN>(tw, j * r * TWS));
+        for (int r = 1; r < R; ++r) v[r] = c_mul(v[r], w[r]);
       }
       dft<R>(v, RealOf<C>(SGN));
       if constexpr (kDif && S > 1) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[r] = c_mul(v[r], twid<SGN>(tw, j * r * TWS));
+        for (int r = 1; r < R; ++r) v[r] = c_mul(v[r], w[r]);
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) buf[Lay::at(sig, base + r * S)] = v[r];
@@ -648,10 +657,22 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
       za[r] = zb[Lay::at(sig, ja + r * S1)];
       zc[r] = zb[Lay::at(sig, jb + r * S1)];
     }
+    C wa[R1], wc[R1];                                // W^{j r}: W, W^2 loaded
+    wa[1] = twid<-1>(tw, ja * 2);
+    wc[1] = twid<-1>(tw, jb * 2);
+    if constexpr (R1 > 2) {
+      wa[2] = twid<-1>(tw, ja * 4);
+      wc[2] = twid<-1>(tw, jb * 4);
+    }
+#pragma unroll
+    for (int r = 3; r < R1; ++r) {
+      wa[r] = c_mul(wa[r - 2], wa[2]);
+      wc[r] = c_mul(wc[r - 2], wc[2]);
+    }
 #pragma unroll
     for (int r = 1; r < R1; ++r) {
-      za[r] = c_mul(za[r], twid<-1>(tw, ja * r * 2));
-      zc[r] = c_mul(zc[r], twid<-1>(tw, jb * r * 2));
+      za[r] = c_mul(za[r], wa[r]);
+      zc[r] = c_mul(zc[r], wc[r]);
     }
     dft<R1>(za, T(-1));
     dft<R1>(zc, T(-1));
