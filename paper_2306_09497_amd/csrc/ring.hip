@@ -432,9 +432,14 @@ constexpr bool hplan_ok(int H) {
 }
 
 // LDS layout of the half-length signals: signal s, point i at s*SP + i + i/16.
+// SP is the padded signal length raised to 4 (mod 8) points, so that the
+// four signals' points i start in different bank groups (record-wise staging
+// touches all four signals at one i).
 template <int H>
 struct HRing {
-  static constexpr int SP = H + H / 16;
+  static constexpr int SP0 = H + H / 16;
+  static constexpr int SP = SP0 + (12 - SP0 % 8) % 8;
+  static_assert(SP % 8 == 4 && SP >= SP0, "signal stride");
   __device__ static inline int at(int s, int i) { return s * SP + i + (i >> 4); }
 };
 
@@ -446,23 +451,39 @@ __device__ inline C twid(const C* __restrict__ tw, int t) {
   return w;
 }
 
+// Orders one wave's LDS accesses across this point: the LDS executes a
+// wave's instructions in order, so only the compiler must not move them.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One in-place stage (span L, radix R, stride S = L/R) over NSIG signals.
 // DIF: butterfly, then twiddles W_L^{j r}; DIT: twiddles, then butterfly.
-// Butterflies touch disjoint points, so loads and stores need no barrier
-// between them; the barrier at the end orders the stage before the next.
+// Each wave of the workgroup owns whole signals (wave w: signals
+// [w NW, (w+1) NW)), so the stages of a transform need no workgroup barrier:
+// a wave only reads points it wrote itself.  The caller separates the
+// transform from phases that mix signals with a workgroup barrier.
 template <int H, int NSIG, int R, int L, bool kDif, int SGN, typename C>
 __device__ inline void ip_stage(C* buf, const C* __restrict__ tw, int tid) {
   constexpr int S = L / R;
   constexpr int NBS = H / R;
-  constexpr int TOTAL = NSIG * NBS;
-  constexpr int NIT = (TOTAL + kHThreads - 1) / kHThreads;
+  constexpr int NWAVE = kHThreads / 64;
+  constexpr int NW = (NSIG + NWAVE - 1) / NWAVE;     // signals per wave
+  constexpr int TOTW = NW * NBS;
+  constexpr int NIT = (TOTW + 63) / 64;
   constexpr int TWS = 2 * H / L;        // table step per unit of j r
   using Lay = HRing<H>;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int s0 = wave * NW;
+  const int tot = (NSIG - s0 < NW ? NSIG - s0 : NW) * NBS;   // this wave's butterflies
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
-    const int id = tid + it * kHThreads;
-    if (TOTAL % kHThreads == 0 || id < TOTAL) {
-      const int sig = id / NBS, rem = id - sig * NBS;
+    const int id = lane + it * 64;
+    if (id < tot) {
+      const int sw = id / NBS, rem = id - sw * NBS;
+      const int sig = s0 + sw;
       // lanes run along j for wide strides and along the blocks for strides
       // <= 4, so that the lanes of one LDS access hit distinct banks
       int blk, j;
@@ -478,12 +499,12 @@ __device__ inline void ip_stage(C* buf, const C* __restrict__ tw, int tid) {
       C v[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) v[r] = buf[Lay::at(sig, base + r * S)];
-      // twiddles W^{j r}, r = 1..R-1: W and W^2 from the table, higher powers
-      // as products of those (one rounding each)
+      // twiddles W^{j r}, r = 1..R-1: W from the table, its powers as
+      // complex products (a few roundings each, far below the tolerances)
       C w[R];
       if constexpr (S > 1) {
         w[1] = twid<SGN>(tw, j * TWS);
-        if constexpr (R > 2) w[2] = twid<SGN>(tw, 2 * j * TWS);
+        if constexpr (R > 2) w[2] = c_mul(w[1], w[1]);
 #pragma unroll
         for (int r = 3; r < R; ++r) w[r] = c_mul(w[r - 2], w[2]);
       }
@@ -500,7 +521,7 @@ __device__ inline void ip_stage(C* buf, const C* __restrict__ tw, int tid) {
       for (int r = 0; r < R; ++r) buf[Lay::at(sig, base + r * S)] = v[r];
     }
   }
-  __syncthreads();
+  wave_lds_sync();
 }
 
 template <int H, int NSIG, int SGN, int I, typename C>
@@ -557,52 +578,83 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
   const int j = hemi ? nlat - 1 - jn : jn;
   const int ncs = 12 * B;
   const int tid = threadIdx.x;
-  // Fourier coefficient of field f at wavenumber m on this ring
-  auto xhat = [&](int m, int f) -> C {
-    return *reinterpret_cast<const C*>(F + ((size_t)m * nlat + j) * ncs + b * 12 + 2 * f);
-  };
-  // Spectra of NS fields -> Z of the half-length signals in slots 0..NS-1.
-  // fld(m, s) returns field s's Fourier coefficient at m <= M.  Every load
-  // of the phase is issued before the first use.
-  auto put = [&](auto fld, auto nsig) {
+  // Fourier coefficients of this ring: record (m, j, b) holds the six
+  // synthesised fields contiguously
+  const T* frow = F + (size_t)j * ncs + b * 12;
+  const size_t fstride = (size_t)nlat * ncs;         // between m and m + 1
+  // Stage NS fields' coefficients in LDS, slot s at point m for m <= M.
+  // Lanes run over the fields of a record (a few cache lines per wave
+  // access); a thread's loads are all issued before its first LDS store.
+  auto stage_in = [&](auto nsig, auto field_of) {
     constexpr int NS = decltype(nsig)::value;
-    constexpr int NQ = (H / 2 + kHThreads) / kHThreads;   // pairs (k, H-k) per thread
-    C X1[NQ][NS], X2[NQ][NS];
+    constexpr int NIT = (H * NS + kHThreads - 1) / kHThreads;   // M < H
+    constexpr int CH = 6;                                        // loads in flight
+    const int total = (M + 1) * NS;
 #pragma unroll
-    for (int it = 0; it < NQ; ++it) {
-      const int q = tid + it * kHThreads;
-      const bool h1 = q <= H / 2 && q <= M, h2 = q > 0 && q <= H / 2 && H - q <= M;
+    for (int c0 = 0; c0 < NIT; c0 += CH) {
+      C v[CH];
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        X1[it][s] = h1 ? fld(q, s) : mkc<C>(T(0), T(0));
-        X2[it][s] = h2 ? fld(H - q, s) : mkc<C>(T(0), T(0));
-        if (q == 0) X1[it][s].y = T(0);              // a real field's mean
+      for (int e = 0; e < CH; ++e) {
+        const int it = (c0 + e) * kHThreads + tid;
+        const int m = it / NS, sl = it - m * NS;
+        v[e] = (c0 + e < NIT && it < total)
+                   ? *reinterpret_cast<const C*>(frow + m * fstride + 2 * field_of(sl))
+                   : mkc<C>(T(0), T(0));
       }
-    }
 #pragma unroll
-    for (int it = 0; it < NQ; ++it) {
-      const int q = tid + it * kHThreads;
-      if (q <= H / 2) {
-        const int k1 = q, k2 = H - q;
-        const C w1 = twid<1>(tw, k1);                // exp(2 pi i k1 / N)
-        const C w2 = mkc<C>(-w1.x, w1.y);            // exp(2 pi i (H - k1) / N)
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-          zb[Lay::at(s, k1)] = hpre(X1[it][s], X2[it][s], w1);
-          if (q > 0 && k2 != k1) zb[Lay::at(s, k2)] = hpre(X2[it][s], X1[it][s], w2);
+      for (int e = 0; e < CH; ++e) {
+        const int it = (c0 + e) * kHThreads + tid;
+        if (c0 + e < NIT && it < total) {
+          const int m = it / NS, sl = it - m * NS;
+          zb[Lay::at(sl, m)] = v[e];
         }
       }
     }
     __syncthreads();
   };
+  // Staged spectra of NS fields -> Z of the half-length signals, in place.
+  // Thread q reads points q and H - q of each slot and writes Z at the same
+  // two points, so no other thread touches them.  post(s, m, x) maps the
+  // staged coefficient to the transformed one (i m x for a longitude
+  // derivative).
+  auto put = [&](auto nsig, auto post) {
+    constexpr int NS = decltype(nsig)::value;
+    constexpr int NQ = (H / 2 + kHThreads) / kHThreads;   // pairs (k, H-k) per thread
+#pragma unroll
+    for (int it = 0; it < NQ; ++it) {
+      const int q = tid + it * kHThreads;
+      if (q <= H / 2) {
+        const int k1 = q, k2 = H - q;
+        const bool h1 = q <= M, h2 = q > 0 && k2 <= M;
+        const C w1 = twid<1>(tw, k1);                // exp(2 pi i k1 / N)
+        const C w2 = mkc<C>(-w1.x, w1.y);            // exp(2 pi i (H - k1) / N)
+        C X1[NS], X2[NS];
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) {
+          X1[sl] = h1 ? post(sl, k1, zb[Lay::at(sl, k1)]) : mkc<C>(T(0), T(0));
+          X2[sl] = h2 ? post(sl, k2, zb[Lay::at(sl, k2)]) : mkc<C>(T(0), T(0));
+          if (q == 0) X1[sl].y = T(0);               // a real field's mean
+        }
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) {
+          zb[Lay::at(sl, k1)] = hpre(X1[sl], X2[sl], w1);
+          if (q > 0 && k2 != k1) zb[Lay::at(sl, k2)] = hpre(X2[sl], X1[sl], w2);
+        }
+      }
+    }
+    __syncthreads();
+  };
+  auto ident = [](int, int, C x) -> C { return x; };
 
   const double ic2d = 1.0 / c2[j];
   const T ic2 = T(ic2d);
   const T ica = T(ic2d / a);
   const T sc = T(w[j] / N);
   // ---- group 1: xi, delta, Phi' -> keep xi and Phi' delta per point ----
-  put([&](int m, int s) -> C { return xhat(m, s); }, std::integral_constant<int, 3>());
+  stage_in(std::integral_constant<int, 3>(), [](int sl) { return sl; });
+  put(std::integral_constant<int, 3>(), ident);
   dif_stages<H, 3, 1, 0>(zb, tw, tid);
+  __syncthreads();
   C Xr[NPW], Dr[NPW];
 #pragma unroll
   for (int t = 0; t < NPW; ++t) {
@@ -616,15 +668,13 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
   __syncthreads();
 
   // ---- group 2: U, V, G, dPhi'/dlambda -> all four products ----
-  put([&](int m, int s) -> C {
-        if (s == 0) return xhat(m, 4);
-        if (s == 1) return xhat(m, 5);
-        if (s == 2) return xhat(m, 3);
-        const C p = xhat(m, 2);
-        return mkc<C>(-T(m) * p.y, T(m) * p.x);        // i m Phi'
-      },
-      std::integral_constant<int, 4>());
+  // slots (U, V, G, Phi') from fields 4, 5, 3, 2; slot 3 becomes i m Phi'
+  stage_in(std::integral_constant<int, 4>(), [](int sl) { return sl < 2 ? sl + 4 : 5 - sl; });
+  put(std::integral_constant<int, 4>(), [](int sl, int m, C x) -> C {
+    return sl == 3 ? mkc<C>(-T(m) * x.y, T(m) * x.x) : x;
+  });
   dif_stages<H, 4, 1, 0>(zb, tw, tid);
+  __syncthreads();
 #pragma unroll
   for (int t = 0; t < NPW; ++t) {
     const int p = tid + t * kHThreads;
@@ -644,7 +694,9 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
 
   // ---- forward transforms of (N_Phi, A, B, K) in slots 0..3 ----
   dit_stages<H, 4, -1, hplan_npass(H) - 1>(zb, tw, tid);
-  // last stage (span H) with the pairing k <-> H - k and the unpacking
+  __syncthreads();
+  // last stage (span H) with the pairing k <-> H - k and the unpacking,
+  // written back in place (a thread writes only the points it read)
   constexpr int R1 = hplan_first(H), S1 = H / R1, UPS = S1 / 2;
   constexpr int TOTU = 4 * UPS;
   const int ncg = 8 * B;
@@ -657,12 +709,12 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
       za[r] = zb[Lay::at(sig, ja + r * S1)];
       zc[r] = zb[Lay::at(sig, jb + r * S1)];
     }
-    C wa[R1], wc[R1];                                // W^{j r}: W, W^2 loaded
+    C wa[R1], wc[R1];                                // W^{j r}: W loaded
     wa[1] = twid<-1>(tw, ja * 2);
     wc[1] = twid<-1>(tw, jb * 2);
     if constexpr (R1 > 2) {
-      wa[2] = twid<-1>(tw, ja * 4);
-      wc[2] = twid<-1>(tw, jb * 4);
+      wa[2] = c_mul(wa[1], wa[1]);
+      wc[2] = c_mul(wc[1], wc[1]);
     }
 #pragma unroll
     for (int r = 3; r < R1; ++r) {
@@ -676,17 +728,32 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
     }
     dft<R1>(za, T(-1));
     dft<R1>(zc, T(-1));
-    const int f = sig == 0 ? 0 : (sig == 3 ? 1 : sig + 1);   // slot -> (N_Phi, K, A, B)
-    T* gcol = Gout + (size_t)j * ncg + b * 8 + 2 * f;
+    C xa[R1], xc[R1];
 #pragma unroll
     for (int r = 0; r < R1; ++r) {
       const int ka = ja + r * S1, kc = jb + r * S1;
       // partners Z_{H-k}
       const C pa = uu == 0 ? za[(R1 - r) % R1] : zc[R1 - 1 - r];
       const C pc = uu == 0 ? zc[R1 - 1 - r] : za[R1 - 1 - r];
-      if (ka <= M) *reinterpret_cast<C*>(gcol + (size_t)ka * nlat * ncg) = hpost(za[r], pa, tw[ka]);
-      if (kc <= M) *reinterpret_cast<C*>(gcol + (size_t)kc * nlat * ncg) = hpost(zc[r], pc, tw[kc]);
+      xa[r] = hpost(za[r], pa, tw[ka]);
+      xc[r] = hpost(zc[r], pc, tw[kc]);
     }
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const int ka = ja + r * S1, kc = jb + r * S1;
+      if (ka <= M) zb[Lay::at(sig, ka)] = xa[r];
+      if (kc <= M) zb[Lay::at(sig, kc)] = xc[r];
+    }
+  }
+  __syncthreads();
+  // results (N_Phi, K, A, B) = slots (0, 3, 1, 2) to G, lanes over the four
+  // fields of a record
+  T* grow = Gout + (size_t)j * ncg + b * 8;
+  const size_t gstride = (size_t)nlat * ncg;
+  for (int it = tid; it < (M + 1) * 4; it += kHThreads) {
+    const int m = it >> 2, f = it & 3;
+    const int sl = f == 0 ? 0 : (f == 1 ? 3 : f - 1);
+    *reinterpret_cast<C*>(grow + m * gstride + 2 * f) = zb[Lay::at(sl, m)];
   }
 }
 
