@@ -29,8 +29,26 @@ the same floating-point order as Parareal.  With nu = 0 the iteration is then
 identical to Parareal with G = Phi_1 and F = Phi_0^m (Sec. 3.2.4).  Exact
 convergence after at most N_1/(nu+1) iterations (Sec. 3.2.3).
 
+Three-level MGRIT (Sec. 3.2, multilevel recursion): the two-level iteration
+with step 5 replaced by `cycles` two-level iterations of the level-1 problem
+on levels (1, 2).  The level-1 problem is w_0 = v_0,
+    w_i = psi_i(w_{i-1}) = (Phi_1(w_{i-1}) - Phi_1(v_{i-1})) + Phi_0(u_{mi-1}),
+i.e. Phi_1 plus the FAS forcing, with initial guess v.  Its level-2 points
+are every m1-th level-1 point; Phi_2 spans m1 level-1 intervals.  One
+iteration on levels (1, 2): F(CF)^nu relaxation with psi; level-2 FAS with
+F2_j = psi_{m1 j}(w_{m1 j - 1}), v2_j = w_{m1 j}; serial level-2 solve
+z_0 = v2_0, z_j = (Phi_2(z_{j-1}) - Phi_2(v2_{j-1})) + F2_j; w_{m1 j} <- z_j;
+F-relaxation with psi.  Then u_{mi} <- w_i for every level-1 point.  The
+paper runs F-cycles followed by one post-V-cycle (Sec. 3.2, deferring the
+definition to XBraid); reading: `cycles` = 1 is a V-cycle, 2 adds the post
+cycle.  Every update keeps the difference-first order, so an exact prefix
+stays bitwise exact and the finite termination bound of the two-level
+iteration holds.
+
 Pins: tests/test_oracle_pint.py (Parareal stability function on the scalar
-test equation, finite termination, MGRIT(2,0) = Parareal, MGRIT termination).
+test equation, finite termination, MGRIT(2,0) = Parareal, MGRIT termination;
+three-level: one level-2 interval = two-level bitwise, exact level-2
+propagator on a linear problem = two-level, finite termination).
 """
 
 import numpy as np
@@ -107,6 +125,95 @@ def mgrit2(u0, n_coarse, m, phi0, phi1, nu, n_iter, record=False,
         for i in range(N1):
             Gw = Gv[i] if i == 0 else phi1(W[i])
             W[i + 1] = (Gw - Gv[i]) + Fv[i]
+        if incr_fn is not None:
+            incrs.append(incr_fn(W, C_start))
+        C = W
+        if record:
+            history.append(list(C))
+        if tol > 0 and incrs and incrs[-1] <= tol:
+            break
+    return C, (history, incrs)
+
+
+def _two_level_on_level1(W, psi, phi2, m1, nu, cycles):
+    """`cycles` two-level MGRIT iterations on levels (1, 2) of the level-1
+    problem w_i = psi(i, w_{i-1}) (i = 1..N1), starting from the list W
+    (W[0] fixed).  Returns the new list."""
+    N1 = len(W) - 1
+    N2 = N1 // m1
+
+    def f_relax(W):
+        W = list(W)
+        for j in range(N2):
+            for s in range(1, m1):
+                i = m1 * j + s
+                W[i] = psi(i, W[i - 1])
+        return W
+
+    def c_relax(W):
+        W = list(W)
+        for j in range(1, N2 + 1):
+            i = m1 * j
+            W[i] = psi(i, W[i - 1])
+        return W
+
+    for _ in range(cycles):
+        W = f_relax(W)
+        for _ in range(nu):
+            W = c_relax(W)
+            W = f_relax(W)
+        F2 = [None] + [psi(m1 * j, W[m1 * j - 1]) for j in range(1, N2 + 1)]
+        V2 = [W[m1 * j] for j in range(N2 + 1)]
+        G2 = [None] + [phi2(V2[j - 1]) for j in range(1, N2 + 1)]
+        Z = [V2[0]] + [None] * N2
+        for j in range(1, N2 + 1):
+            Gz = G2[j] if j == 1 else phi2(Z[j - 1])
+            Z[j] = (Gz - G2[j]) + F2[j]
+        W = list(W)
+        for j in range(1, N2 + 1):
+            W[m1 * j] = Z[j]
+        W = f_relax(W)
+    return W
+
+
+def mgrit3(u0, n_coarse, m, phi0, phi1, phi2, nu, n_iter, m1=None, cycles=1,
+           record=False, incr_fn=None, tol=0.0):
+    """Three-level MGRIT, F(CF)^nu relaxation on levels 0 and 1.  n_coarse =
+    N_1 level-1 points (C-points of level 0, m fine points apart); level-2
+    points every m1 (default m) level-1 points (N_1 divisible by m1); phi2
+    spans m1 level-1 intervals.  Returns the level-0 C-point states after
+    n_iter iterations, as mgrit2."""
+    m1 = m if m1 is None else m1
+    N1 = n_coarse
+    assert N1 % m1 == 0, "level-1 points must fill whole level-2 intervals"
+    C = [u0] + [None] * N1
+    for i in range(N1):
+        C[i + 1] = phi1(C[i])
+    history = [list(C)] if record else None
+    incrs = []
+
+    def f_relax(Cpts):
+        last = [None] * N1
+        for i in range(N1):
+            u = Cpts[i]
+            for _ in range(m - 1):
+                u = phi0(u)
+            last[i] = u
+        return last
+
+    for _ in range(n_iter):
+        C_start = C
+        last = f_relax(C)
+        for _ in range(nu):
+            C = [C[0]] + [phi0(last[i]) for i in range(N1)]
+            last = f_relax(C)
+        Fv = [phi0(last[i]) for i in range(N1)]        # Phi_0(u_{m(i+1)-1})
+        Gv = [phi1(C[i]) for i in range(N1)]           # Phi_1(v_i)
+
+        def psi(i, w, Fv=Fv, Gv=Gv):                   # level-1 map into point i
+            return (phi1(w) - Gv[i - 1]) + Fv[i - 1]
+
+        W = _two_level_on_level1(list(C), psi, phi2, m1, nu, cycles)
         if incr_fn is not None:
             incrs.append(incr_fn(W, C_start))
         C = W

@@ -115,3 +115,116 @@ def test_mgrit_swe(c1_small):
     # and not yet exact after one FCF iteration
     C1, _ = pint.mgrit2(U0, 4, 20, phi0, coarse, 1, 1)
     assert np.max(rel_err(C1[4], ser[4], 21)) > 1e-9
+
+
+def _logistic(h):
+    """One explicit Euler step of u' = u (1 - u): a nonlinear scalar stand-in
+    for a propagator (the coarse levels take longer steps)."""
+    return lambda u: u + h * (u * (1.0 - u))
+
+
+@pytest.mark.parametrize("nu", [0, 1])
+def test_mgrit3_single_level2_interval_is_two_level(nu):
+    """Three-level MGRIT whose level 1 holds a single level-2 interval solves
+    the level-1 problem exactly by relaxation: bitwise the two-level iterate."""
+    h, m, N1 = 0.05, 3, 4
+    phi0, phi1, phi2 = _logistic(h), _logistic(m * h), _logistic(m * N1 * h)
+    for k in (1, 2, 3):
+        C3, _ = pint.mgrit3(0.1, N1, m, phi0, phi1, phi2, nu, k, m1=N1)
+        C2, _ = pint.mgrit2(0.1, N1, m, phi0, phi1, nu, k)
+        assert all(a == b for a, b in zip(C3, C2)), (k, C3, C2)
+
+
+@pytest.mark.parametrize("nu", [0, 1])
+def test_mgrit3_exact_level2_linear_is_two_level(nu):
+    """On a linear problem with Phi_2 = Phi_1^m1 the level-2 correction of the
+    FAS level-1 problem is exact, so one cycle on levels (1, 2) reproduces the
+    two-level iterate (up to rounding): pins the signs and indices of the
+    level-1 and level-2 right-hand sides."""
+    f, g, m, m1, N1 = 0.995 + 0.02j, 0.98 + 0.06j, 3, 2, 8
+    phi0 = lambda u: f * u
+    phi1 = lambda u: g * u
+    phi2 = lambda u: g * (g * u)
+    for k in (1, 2, 3):
+        C3, _ = pint.mgrit3(1.0 + 0j, N1, m, phi0, phi1, phi2, nu, k, m1=m1)
+        C2, _ = pint.mgrit2(1.0 + 0j, N1, m, phi0, phi1, nu, k)
+        for a, b in zip(C3, C2):
+            assert abs(a - b) < 1e-14, (k, a, b)
+    # an inexact Phi_2 gives a different iterate (the level-2 solve matters)
+    C3x, _ = pint.mgrit3(1.0 + 0j, N1, m, phi0, phi1, lambda u: 0.96 * u, nu, 1, m1=m1)
+    C2x, _ = pint.mgrit2(1.0 + 0j, N1, m, phi0, phi1, nu, 1)
+    assert max(abs(a - b) for a, b in zip(C3x, C2x)) > 1e-6
+
+
+@pytest.mark.parametrize("nu,cycles", [(0, 1), (1, 1), (1, 2)])
+def test_mgrit3_finite_termination(nu, cycles):
+    """An exact prefix stays bitwise exact through both levels' corrections,
+    so three-level MGRIT reproduces the serial fine C-points after
+    ceil(N_1/(nu+1)) iterations, and not one iteration earlier."""
+    h, m, m1, N1 = 0.05, 2, 2, 8
+    phi0, phi1, phi2 = _logistic(h), _logistic(0.9 * m * h), _logistic(0.8 * m * m1 * h)
+    ser = pint.serial(0.1, N1, lambda u: phi0(phi0(u)))
+    kmax = -(-N1 // (nu + 1))
+    C, _ = pint.mgrit3(0.1, N1, m, phi0, phi1, phi2, nu, kmax, m1=m1, cycles=cycles)
+    assert all(a == b for a, b in zip(C, ser))
+    Cm, _ = pint.mgrit3(0.1, N1, m, phi0, phi1, phi2, nu, kmax - 1, m1=m1, cycles=cycles)
+    assert abs(Cm[N1] - ser[N1]) > 0
+
+
+def test_mgrit3_swe_single_level2_interval(c1_small):
+    """The same identity on the SWE: one level-2 interval reproduces the
+    two-level MGRIT iterate bitwise."""
+    md, U0, fine, coarse = c1_small
+    phi0 = lambda u: md.propagate(u, 60.0, 1)
+    phi2 = lambda u: md.propagate(u, 2400.0, 1)
+    C3, _ = pint.mgrit3(U0, 4, 20, phi0, coarse, phi2, 1, 1, m1=4)
+    C2, _ = pint.mgrit2(U0, 4, 20, phi0, coarse, 1, 1)
+    for a, b in zip(C3, C2):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("nu,cycles", [(0, 1), (1, 1), (2, 1), (1, 2)])
+def test_mgrit3_level1_cycle_matches_matrix_form(nu, cycles):
+    """One two-level cycle on levels (1, 2) of a linear level-1 problem
+    w_i = g w_{i-1} + c_i, written independently as block relaxation and
+    coarse-grid correction on the bidiagonal system A w = b: F-relaxation
+    solves the F rows given the C values, C-relaxation the C rows given the F
+    values, and the level-2 correction adds e = A_2^{-1} r on the C points
+    (A_2 bidiagonal with the inexact level-2 factor g2), with FAS and
+    injection; then F-relaxation."""
+    rng = np.random.default_rng(5)
+    N1, m1 = 12, 3
+    N2 = N1 // m1
+    g, g2 = 0.97 + 0.05j, 0.90 + 0.12j
+    c = rng.standard_normal(N1 + 1) + 1j * rng.standard_normal(N1 + 1)
+    W0 = rng.standard_normal(N1 + 1) + 1j * rng.standard_normal(N1 + 1)
+
+    got = pint._two_level_on_level1(list(W0), lambda i, w: g * w + c[i],
+                                    lambda u: g2 * u, m1, nu, cycles)
+
+    # matrix form: unknowns w_1..w_N1, A w = b
+    A = np.eye(N1, dtype=complex) - g * np.eye(N1, k=-1)
+    b = c[1:].copy()
+    b[0] += g * W0[0]
+    Cset = [m1 * j - 1 for j in range(1, N2 + 1)]          # rows of w_{m1 j}
+    Fset = [r for r in range(N1) if r not in Cset]
+    w = W0[1:].copy()
+
+    def relax(w, rows):
+        w = w.copy()
+        other = [r for r in range(N1) if r not in rows]
+        rhs = b[rows] - A[np.ix_(rows, other)] @ w[other]
+        w[rows] = np.linalg.solve(A[np.ix_(rows, rows)], rhs)
+        return w
+
+    A2 = np.eye(N2, dtype=complex) - g2 * np.eye(N2, k=-1)
+    for _ in range(cycles):
+        w = relax(w, Fset)
+        for _ in range(nu):
+            w = relax(w, Cset)
+            w = relax(w, Fset)
+        r = b - A @ w
+        w[Cset] += np.linalg.solve(A2, r[Cset])
+        w = relax(w, Fset)
+    assert np.allclose(np.array(got[1:]), w, rtol=0, atol=1e-12)
+    assert got[0] == W0[0]
