@@ -226,10 +226,12 @@ def time_to_tol():
     return out
 
 
-def measure(precision, steps, warmup):
-    """Time `steps` MGRIT iterations at the given Legendre precision; return
-    the throughput, the per-kernel profile of the batched transform kernels
-    and the slice states after warmup + steps iterations."""
+def measure(precision, steps, warmup, levels=2):
+    """Time `steps` MGRIT iterations at the given Legendre precision (levels 2,
+    or 3 with level-2 points every CFACTOR level-1 points, one level-2 step of
+    CFACTOR * DT_COARSE, two cycles on levels 1 and 2 per iteration); return
+    the throughput, the per-kernel profile of the batched transform kernels,
+    the increments and the slice states after warmup + steps iterations."""
     import numpy as np
     import torch
     from paper_2306_09497_amd import pint, workloads
@@ -246,8 +248,12 @@ def measure(precision, steps, warmup):
     coarse = pint.stepper(DT_COARSE, Q_COARSE, NU_COARSE, pint.T_ALL)
     plan.solve(pint.params(pint.MGRIT, GROUP, fine, CFACTOR, coarse, 1, nrelax=1, max_iter=0),
                u0, slices)                                     # initial coarse sweep
+    extra = {}
+    if levels == 3:
+        extra = dict(levels=3, cfactor1=CFACTOR, coarse2_steps=1, cycles1=2,
+                     coarse2=pint.stepper(DT_COARSE * CFACTOR, Q_COARSE, NU_COARSE, pint.T_ALL))
     it = pint.params(pint.MGRIT, GROUP, fine, CFACTOR, coarse, 1, nrelax=1, max_iter=1,
-                     resume=True)
+                     resume=True, **extra)
     for _ in range(warmup):
         plan.solve(it, u0, slices)
     torch.cuda.synchronize()
@@ -300,6 +306,8 @@ def main():
                          "GEMM products; state and solves FP64 in both)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the FP32-Legendre side measurement of the default run")
+    ap.add_argument("--no-mgrit3", action="store_true",
+                    help="skip the three-level MGRIT side measurement of the default run")
     ap.add_argument("--time-to-tol", action="store_true",
                     help="print the T127 Parareal time-to-tolerance measurement instead")
     args = ap.parse_args()
@@ -397,6 +405,21 @@ def main():
             }
             del rm
         out["mixed_precision"] = mixed
+    if prec == pint.FP64 and not args.no_mgrit3:
+        # the same slice group with three MGRIT levels: the level-1 problem by
+        # two cycles on levels 1 and 2 instead of the serial sweep
+        try:
+            r3 = measure(pint.FP64, args.steps, args.warmup, levels=3)
+            out["mgrit3"] = {
+                "value": r3["value"], "unit": "slice-steps/s",
+                "ms_per_step": r3["elapsed"] / args.steps * 1e3,
+                "increment": r3["incr"],
+                "config": "levels 3: level-2 point every 4 C-points (16 level-2 intervals), "
+                          "level-2 step 720 s q=4 nu=1e17, FCF on levels 0 and 1, 2 cycles "
+                          "on levels (1, 2) per iteration",
+            }
+        except Exception as e:                      # reported, not fatal
+            out["mgrit3"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

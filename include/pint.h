@@ -151,10 +151,22 @@ pint_status pint_step(pint_plan* plan, const pint_stepper* st, const double* u_i
  * method 0 = Parareal (Sec. 3.1): slices of length DT = fine.dt *
  *   fine_steps = coarse.dt * coarse_steps; fine propagator = fine_steps
  *   fine steps, coarse propagator = coarse_steps coarse steps.
- * method 1 = two-level MGRIT with F(CF)^nrelax relaxation and FAS (Sec. 3.2):
+ * method 1 = MGRIT with F(CF)^nrelax relaxation and FAS (Sec. 3.2):
  *   fine level = fine.dt, cfactor = fine_steps fine steps per C-interval,
- *   coarse level = coarse_steps coarse steps per C-interval.
- *   With nrelax = 0 it is identical to Parareal.
+ *   level 1 = coarse_steps coarse steps per C-interval.
+ *   levels = 2 (or 0): the level-1 problem is solved by a serial sweep.
+ *     With nrelax = 0 it is identical to Parareal.
+ *   levels = 3 (multilevel recursion, Sec. 3.2): the level-1 problem (the
+ *     level-1 propagator plus the FAS forcing) is solved approximately by
+ *     cycles1 two-level MGRIT iterations on levels 1 and 2, starting from
+ *     the injected C-points: F(CF)^nrelax relaxation of level 1, level-2
+ *     points every cfactor1 level-1 points (n_intervals divisible by
+ *     cfactor1), level-2 propagator = coarse2_steps steps of coarse2
+ *     spanning cfactor1 level-1 intervals, serial level-2 solve, then an
+ *     F-relaxation of level 1.  cycles1 = 1 is a V-cycle; the paper's
+ *     F-cycle followed by a post V-cycle reads as cycles1 = 2.  Every update
+ *     is formed difference first, (Phi(w) - Phi(v)) + F, so exact slices
+ *     stay bitwise exact (finite termination as with two levels).
  * Iterates until the largest relative L2 increment of a slice state is
  * <= tol, or max_iter iterations (tol = 0: exactly max_iter).  The increment
  * of a slice is the larger of the relative changes of Phi' (Phi without its
@@ -175,6 +187,12 @@ typedef struct {
   int resume;             /* 1: u_slices already holds an iterate (all
                              n_intervals+1 states, e.g. a checkpoint); skip
                              the initial coarse sweep and continue from it  */
+  int levels;             /* MGRIT levels: 0 or 2 (two-level), 3          */
+  int cfactor1;           /* levels 3: level-1 points per level-2 interval */
+  pint_stepper coarse2;   /* levels 3: level-2 propagator step             */
+  int coarse2_steps;      /* levels 3: coarse2 steps per level-2 interval  */
+  int cycles1;            /* levels 3: cycles on levels (1, 2) per
+                             iteration, >= 1                              */
 } pint_pint_params;
 
 typedef struct {
@@ -182,7 +200,8 @@ typedef struct {
   double incr[128];              /* max relative increment per iteration      */
   double seconds[128];           /* wall time per iteration                   */
   long long fine_slice_steps;    /* fine IMEX steps executed (sum over slices)*/
-  long long coarse_steps;        /* coarse IMEX steps executed                */
+  long long coarse_steps;        /* coarse IMEX steps executed (all coarse
+                                    levels, single-state and batched)        */
 } pint_report;
 
 pint_status pint_solve(pint_plan* plan, const pint_pint_params* p, const double* u0,

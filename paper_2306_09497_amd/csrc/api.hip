@@ -128,6 +128,118 @@ static pint_status check_params(const Plan& p, const pint_pint_params* q) {
     set_error("fine (%g s) and coarse (%g s) propagators must span the same interval", DTf, DTc);
     return PINT_E_INVAL;
   }
+  if (q->levels != 0 && q->levels != 2 && q->levels != 3) {
+    set_error("levels must be 2 (or 0) or 3");
+    return PINT_E_INVAL;
+  }
+  if (q->levels == 3) {
+    if (q->method != 1) {
+      set_error("three levels need method 1 (MGRIT)");
+      return PINT_E_INVAL;
+    }
+    if (q->cfactor1 < 2 || q->n_intervals % q->cfactor1 != 0 || q->coarse2_steps < 1 ||
+        q->cycles1 < 1 || q->cycles1 > 8) {
+      set_error("three levels need cfactor1 >= 2 dividing n_intervals, coarse2_steps >= 1, "
+                "1 <= cycles1 <= 8");
+      return PINT_E_INVAL;
+    }
+    PINT_TRY(check_stepper(p, &q->coarse2));
+    const double DT2 = q->coarse2.dt * q->coarse2_steps;
+    if (fabs(DT2 - q->cfactor1 * DTc) > 1e-9 * DT2) {
+      set_error("level-2 propagator (%g s) must span cfactor1 level-1 intervals (%g s)", DT2,
+                q->cfactor1 * DTc);
+      return PINT_E_INVAL;
+    }
+  }
+  return PINT_OK;
+}
+
+// Strided gather/scatter of states: dst[k] = src[k * stride] (in states).
+static pint_status copy_states(double* dst, size_t dstride, const double* src, size_t sstride,
+                               int count, size_t sd, hipStream_t s) {
+  if (count <= 0) return PINT_OK;
+  PINT_HIP(hipMemcpy2DAsync(dst, dstride * sd * sizeof(double), src, sstride * sd * sizeof(double),
+                            sd * sizeof(double), count, hipMemcpyDeviceToDevice, s));
+  return PINT_OK;
+}
+
+// Three-level MGRIT, level-1 part (Sec. 3.2, multilevel recursion): cycles1
+// two-level iterations on levels (1, 2) of the level-1 problem
+//   w_0 = U_0,  w_i = psi_i(w_{i-1}) = (Phi_1(w_{i-1}) - G_i) + F_i,
+// G_i = Phi_1(v_{i-1}) = Gold[i-1], F_i = Phi_0(u_{mi-1}) = Fv[i-1], starting
+// from w = v = U.  Level-1 points are held as W[s][j] = w_{m1 j + s} (rows of
+// N2 + 1 entries; row s = 0 uses all, rows s > 0 the first N2), so that the
+// points at one s of all level-2 intervals form one contiguous batch.  On
+// return U[1..N1] = w.
+struct Level1Bufs {
+  DevBuf W, Fl, Gl, tmp, F2, G2, gz;
+  pint_status alloc(size_t sd, int m1, int N2) {
+    const size_t rows = (size_t)m1 * (N2 + 1);
+    PINT_TRY(W.alloc(sd * rows));
+    PINT_TRY(Fl.alloc(sd * rows));
+    PINT_TRY(Gl.alloc(sd * rows));
+    PINT_TRY(tmp.alloc(sd * N2));
+    PINT_TRY(F2.alloc(sd * N2));
+    PINT_TRY(G2.alloc(sd * N2));
+    return gz.alloc(sd);
+  }
+};
+
+static pint_status level1_cycles(Plan& p, const pint_pint_params* q, Level1Bufs& b, double* U,
+                                 const double* Fv, const double* Gold, pint_report* r,
+                                 hipStream_t s) {
+  const int N1 = q->n_intervals, m1 = q->cfactor1, N2 = N1 / m1;
+  const size_t sd = (size_t)3 * p.ncoef * 2;
+  const size_t row = (size_t)(N2 + 1);
+  auto at = [&](double* base, int sr, int j) { return base + ((size_t)sr * row + j) * sd; };
+  // gather W[s][j] = U[m1 j + s]; F and G of point i = m1 j + s >= 1
+  for (int sr = 0; sr < m1; ++sr) {
+    PINT_TRY(copy_states(at(b.W.p, sr, 0), 1, U + (size_t)sr * sd, m1, sr == 0 ? N2 + 1 : N2, sd,
+                         s));
+    const int j0 = sr == 0 ? 1 : 0;
+    const size_t src = (size_t)(m1 * j0 + sr - 1) * sd;
+    PINT_TRY(copy_states(at(b.Fl.p, sr, j0), 1, Fv + src, m1, N2, sd, s));
+    PINT_TRY(copy_states(at(b.Gl.p, sr, j0), 1, Gold + src, m1, N2, sd, s));
+  }
+  const size_t nb = (size_t)N2 * sd;                  // doubles of one batch
+  // out = psi applied to row sin (entries 0..N2-1), forcing of row sr from j0
+  auto psi_row = [&](int sin, int sr, int j0, double* out) -> pint_status {
+    PINT_TRY(propagate(p, q->coarse, at(b.W.p, sin, 0), b.tmp.p, N2, q->coarse_steps, s));
+    r->coarse_steps += (long long)N2 * q->coarse_steps;
+    return pr_update(p, b.tmp.p, at(b.Gl.p, sr, j0), at(b.Fl.p, sr, j0), out, nb, s);
+  };
+  auto f_relax = [&]() -> pint_status {
+    for (int sr = 1; sr < m1; ++sr) PINT_TRY(psi_row(sr - 1, sr, 0, at(b.W.p, sr, 0)));
+    return PINT_OK;
+  };
+  for (int cyc = 0; cyc < q->cycles1; ++cyc) {
+    PINT_TRY(f_relax());
+    for (int it = 0; it < q->nrelax; ++it) {
+      PINT_TRY(psi_row(m1 - 1, 0, 1, at(b.W.p, 0, 1)));   // C-relaxation
+      PINT_TRY(f_relax());
+    }
+    // level 2: F2_j = psi(w_{m1 j - 1}), G2_j = Phi_2(v2_{j-1}), j = 1..N2
+    PINT_TRY(psi_row(m1 - 1, 0, 1, b.F2.p));
+    PINT_TRY(propagate(p, q->coarse2, at(b.W.p, 0, 0), b.G2.p, N2, q->coarse2_steps, s));
+    r->coarse_steps += (long long)N2 * q->coarse2_steps;
+    // serial level-2 solve z_j = (Phi_2(z_{j-1}) - G2_j) + F2_j into W[0][j]
+    for (int j = 1; j <= N2; ++j) {
+      const double* g2 = b.G2.p + (size_t)(j - 1) * sd;
+      const double* gnew = g2;                        // Phi_2(z_0) = Phi_2(v2_0)
+      if (j > 1) {
+        PINT_TRY(propagate(p, q->coarse2, at(b.W.p, 0, j - 1), b.gz.p, 1, q->coarse2_steps, s));
+        r->coarse_steps += q->coarse2_steps;
+        gnew = b.gz.p;
+      }
+      PINT_TRY(pr_update(p, gnew, g2, b.F2.p + (size_t)(j - 1) * sd, at(b.W.p, 0, j), sd, s));
+    }
+    PINT_TRY(f_relax());
+  }
+  // scatter w back to the slice states U[1..N1]
+  for (int sr = 0; sr < m1; ++sr) {
+    const int j0 = sr == 0 ? 1 : 0;
+    PINT_TRY(copy_states(U + (size_t)(m1 * j0 + sr) * sd, m1, at(b.W.p, sr, j0), 1, N2, sd, s));
+  }
   return PINT_OK;
 }
 
@@ -149,15 +261,19 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
 
   const bool mgrit = q->method == 1;
   const int nrelax = mgrit ? q->nrelax : 0;
-  // Crank-Nicolson factors of both propagators, made on s before any work
+  const bool three = mgrit && q->levels == 3;
+  Level1Bufs l1;
+  if (three) PINT_TRY(l1.alloc(sd, q->cfactor1, N / q->cfactor1));
+  // Crank-Nicolson factors of the propagators, made on s before any work
   // goes to the sweep stream
   const CnFactors* cf = nullptr;
   PINT_TRY(cn_factors(p, q->fine.dt, q->fine.terms, s, &cf));
   PINT_TRY(cn_factors(p, q->coarse.dt, q->coarse.terms, s, &cf));
+  if (three) PINT_TRY(cn_factors(p, q->coarse2.dt, q->coarse2.terms, s, &cf));
   if (q->resume) {
     // continue from the iterate held in U; the coarse values of its slice
     // starts are recomputed (bitwise what the previous sweep produced)
-    if (nrelax == 0) {
+    if (nrelax == 0 && !three) {
       PINT_TRY(propagate(p, q->coarse, U, Gold.p, N, q->coarse_steps, s));
       r->coarse_steps += (long long)N * q->coarse_steps;
     }
@@ -189,43 +305,55 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
       PINT_TRY(propagate(p, q->coarse, U, Gold.p, N, q->coarse_steps, s));
       r->coarse_steps += (long long)N * q->coarse_steps;
     }
-    // fine propagation of every active slice (the parallel part), in chunks
-    // of cs slices; chunk c's event releases the sweep steps that need it
-    const int nact = N - first;
-    const int cs = (nact + p.sweep_chunks - 1) / p.sweep_chunks;
-    const int nchunk = (nact + cs - 1) / cs;
-    for (int c = 0; c < nchunk; ++c) {
-      const int n0 = first + c * cs;
-      const int nb = cs < N - n0 ? cs : N - n0;
-      PINT_TRY(propagate(p, q->fine, src + n0 * sd, Fv.p + n0 * sd, nb, q->fine_steps, s));
-      PINT_HIP(hipEventRecord(p.chunk_ev[c], s));
-    }
-    r->fine_slice_steps += (long long)nact * q->fine_steps;
-    // serial correction sweep U_{n+1} = (G(U_n^new) - G(U_n^old)) + F(U_n^old)
-    // on the sweep stream and workspace, beside the later chunks.  Step n
-    // reads F(U_n^old) (chunk (n-first)/cs) and overwrites U_{n+1}, the start
-    // of chunk (n+1-first)/cs when it begins one: it waits for both.
-    {
-      SideWork side(p);
-      hipStream_t ss = p.side_stream;
-      int waited = -1;
-      for (int n = first; n < N; ++n) {
-        int need = (n + 1 - first) / cs;
-        if (need > nchunk - 1) need = nchunk - 1;
-        while (waited < need) PINT_HIP(hipStreamWaitEvent(ss, p.chunk_ev[++waited], 0));
-        const double* gnew = Gold.p + n * sd;        // unchanged input at n == first
-        if (n > first) {
-          PINT_TRY(propagate(p, q->coarse, U + n * sd, Gtmp.p, 1, q->coarse_steps, ss));
-          r->coarse_steps += q->coarse_steps;
-          gnew = Gtmp.p;
-        }
-        PINT_TRY(pr_update(p, gnew, Gold.p + n * sd, Fv.p + n * sd, U + (n + 1) * sd, sd, ss));
-        if (n > first)
-          PINT_HIP(hipMemcpyAsync(Gold.p + n * sd, Gtmp.p, sb, hipMemcpyDeviceToDevice, ss));
+    if (three) {
+      // three levels: Phi_1(v_i) of the (relaxed) C-points, F_i of every
+      // interval, then the level-1 problem by cycles on levels (1, 2)
+      if (nrelax == 0) {
+        PINT_TRY(propagate(p, q->coarse, U, Gold.p, N, q->coarse_steps, s));
+        r->coarse_steps += (long long)N * q->coarse_steps;
       }
-      PINT_HIP(hipEventRecord(p.join_ev, ss));
+      PINT_TRY(propagate(p, q->fine, U, Fv.p, N, q->fine_steps, s));
+      r->fine_slice_steps += (long long)N * q->fine_steps;
+      PINT_TRY(level1_cycles(p, q, l1, U, Fv.p, Gold.p, r, s));
+    } else {
+      // fine propagation of every active slice (the parallel part), in chunks
+      // of cs slices; chunk c's event releases the sweep steps that need it
+      const int nact = N - first;
+      const int cs = (nact + p.sweep_chunks - 1) / p.sweep_chunks;
+      const int nchunk = (nact + cs - 1) / cs;
+      for (int c = 0; c < nchunk; ++c) {
+        const int n0 = first + c * cs;
+        const int nb = cs < N - n0 ? cs : N - n0;
+        PINT_TRY(propagate(p, q->fine, src + n0 * sd, Fv.p + n0 * sd, nb, q->fine_steps, s));
+        PINT_HIP(hipEventRecord(p.chunk_ev[c], s));
+      }
+      r->fine_slice_steps += (long long)nact * q->fine_steps;
+      // serial correction sweep U_{n+1} = (G(U_n^new) - G(U_n^old)) + F(U_n^old)
+      // on the sweep stream and workspace, beside the later chunks.  Step n
+      // reads F(U_n^old) (chunk (n-first)/cs) and overwrites U_{n+1}, the start
+      // of chunk (n+1-first)/cs when it begins one: it waits for both.
+      {
+        SideWork side(p);
+        hipStream_t ss = p.side_stream;
+        int waited = -1;
+        for (int n = first; n < N; ++n) {
+          int need = (n + 1 - first) / cs;
+          if (need > nchunk - 1) need = nchunk - 1;
+          while (waited < need) PINT_HIP(hipStreamWaitEvent(ss, p.chunk_ev[++waited], 0));
+          const double* gnew = Gold.p + n * sd;        // unchanged input at n == first
+          if (n > first) {
+            PINT_TRY(propagate(p, q->coarse, U + n * sd, Gtmp.p, 1, q->coarse_steps, ss));
+            r->coarse_steps += q->coarse_steps;
+            gnew = Gtmp.p;
+          }
+          PINT_TRY(pr_update(p, gnew, Gold.p + n * sd, Fv.p + n * sd, U + (n + 1) * sd, sd, ss));
+          if (n > first)
+            PINT_HIP(hipMemcpyAsync(Gold.p + n * sd, Gtmp.p, sb, hipMemcpyDeviceToDevice, ss));
+        }
+        PINT_HIP(hipEventRecord(p.join_ev, ss));
+      }
+      PINT_HIP(hipStreamWaitEvent(s, p.join_ev, 0));
     }
-    PINT_HIP(hipStreamWaitEvent(s, p.join_ev, 0));
     // increments (synchronises)
     PINT_TRY(rel_diff(p, U + sd, Uprev.p + sd, incr.data(), N, s));
     // stopping measure: Phi' and the wind (entries 0 and 3 of each slice)

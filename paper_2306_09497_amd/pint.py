@@ -54,7 +54,8 @@ class PintParams(ctypes.Structure):
                 ("fine", Stepper), ("fine_steps", ctypes.c_int),
                 ("coarse", Stepper), ("coarse_steps", ctypes.c_int),
                 ("nrelax", ctypes.c_int), ("max_iter", ctypes.c_int), ("tol", ctypes.c_double),
-                ("resume", ctypes.c_int)]
+                ("resume", ctypes.c_int), ("levels", ctypes.c_int), ("cfactor1", ctypes.c_int),
+                ("coarse2", Stepper), ("coarse2_steps", ctypes.c_int), ("cycles1", ctypes.c_int)]
 
 
 class ProfEntry(ctypes.Structure):
@@ -243,6 +244,9 @@ class Plan:
 
 
 def params(method, n_intervals, fine, fine_steps, coarse, coarse_steps, nrelax=0, max_iter=1,
-           tol=0.0, resume=False):
+           tol=0.0, resume=False, levels=2, cfactor1=0, coarse2=None, coarse2_steps=1,
+           cycles1=1):
+    c2 = coarse2 if coarse2 is not None else Stepper(0.0, 2, 0.0, 0)
     return PintParams(int(method), int(n_intervals), fine, int(fine_steps), coarse,
-                      int(coarse_steps), int(nrelax), int(max_iter), float(tol), int(resume))
+                      int(coarse_steps), int(nrelax), int(max_iter), float(tol), int(resume),
+                      int(levels), int(cfactor1), c2, int(coarse2_steps), int(cycles1))

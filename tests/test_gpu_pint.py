@@ -202,3 +202,77 @@ def test_sweep_overlap_chunks_bitwise(method, nrelax):
         ref, _ = opint.parareal(U0, 8, phi0, phi1, 2)
     for i in range(9):
         assert_parity(res[0][i], ref[i], M)
+
+
+def mgrit3_params(k, nrelax=1, cycles1=1, cfactor1=2, n=8):
+    f = pint.stepper(300.0, 2, 0.0, T_ALL)
+    c = pint.stepper(600.0, 4, 1e15, T_ALL)
+    c2 = pint.stepper(600.0 * cfactor1, 4, 1e15, T_ALL)
+    return pint.params(pint.MGRIT, n, f, 2, c, 1, nrelax=nrelax, max_iter=k, levels=3,
+                       cfactor1=cfactor1, coarse2=c2, coarse2_steps=1, cycles1=cycles1)
+
+
+@pytest.mark.parametrize("cycles1", [1, 2])
+def test_mgrit3_vs_oracle(setup, cycles1):
+    """NEXT-2: three-level MGRIT (FCF on levels 0 and 1, 8 C-intervals of two
+    300 s fine steps, level 1 600 s, level 2 1200 s with hyperviscosity)
+    against the oracle, every C-point of iterations 1 and 2."""
+    md, pl = setup
+    U0 = workloads.solid_body(M, noise=1e-3, seed=6)
+    phi0 = lambda u: md.propagate(u, 300.0, 1)
+    phi1 = lambda u: md.propagate(u, 600.0, 1, 1e15, 4, T_ALL)
+    phi2 = lambda u: md.propagate(u, 1200.0, 1, 1e15, 4, T_ALL)
+    for k in (1, 2):
+        ref, _ = opint.mgrit3(U0, 8, 2, phi0, phi1, phi2, 1, k, m1=2, cycles=cycles1)
+        got, rep = run_solve(pl, mgrit3_params(k, cycles1=cycles1), U0, 8)
+        assert rep.iters == k
+        for i in range(9):
+            assert_parity(got[i], ref[i], M)
+
+
+def test_mgrit3_one_level2_interval_is_two_level_bitwise(setup):
+    """With a single level-2 interval the level-1 relaxation solves the
+    level-1 problem exactly: bitwise the two-level iterate."""
+    md, pl = setup
+    U0 = workloads.solid_body(M, noise=1e-3, seed=7)
+    f = pint.stepper(300.0, 2, 0.0, T_ALL)
+    c = pint.stepper(600.0, 4, 1e15, T_ALL)
+    for k in (1, 2):
+        a, _ = run_solve(pl, mgrit3_params(k, cfactor1=8), U0, 8)
+        b, _ = run_solve(pl, pint.params(pint.MGRIT, 8, f, 2, c, 1, nrelax=1, max_iter=k), U0, 8)
+        assert np.array_equal(a, b)
+
+
+def test_mgrit3_finite_termination(setup):
+    """Exact slices stay bitwise exact through both corrections: after
+    ceil(N_1/(nu+1)) = 4 FCF iterations the C-points equal serial fine
+    stepping bitwise, and not after 3."""
+    md, pl = setup
+    U0 = workloads.solid_body(M, noise=1e-3, seed=8)
+    f = pint.stepper(300.0, 2, 0.0, T_ALL)
+    got, _ = run_solve(pl, mgrit3_params(4), U0, 8)
+    early, _ = run_solve(pl, mgrit3_params(3), U0, 8)
+    u = to_dev(U0, torch)
+    for i in range(1, 9):
+        pl.step(f, u, u, 1, 2)
+        torch.cuda.synchronize()
+        assert np.array_equal(from_dev(u)[0], got[i])
+    assert not np.array_equal(early[8], got[8])
+
+
+def test_mgrit3_invalid_params(setup):
+    md, pl = setup
+    U0 = workloads.solid_body(M)
+    u0 = to_dev(U0, torch)
+    out = torch.zeros((9, 3, pl.ncoef, 2), dtype=torch.float64, device="cuda")
+    bad = mgrit3_params(1, cfactor1=3)                       # 3 does not divide 8
+    st, _, msg = pl.solve_status(bad, u0, out)
+    assert st == -1 and "cfactor1" in msg
+    bad = mgrit3_params(1)
+    bad.coarse2 = pint.stepper(900.0, 4, 1e15, T_ALL)        # spans 900 s, not 1200 s
+    st, _, msg = pl.solve_status(bad, u0, out)
+    assert st == -1 and "level-2" in msg
+    bad = mgrit3_params(1)
+    bad.method = pint.PARAREAL
+    st, _, msg = pl.solve_status(bad, u0, out)
+    assert st == -1 and "MGRIT" in msg
