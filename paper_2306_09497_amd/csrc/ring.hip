@@ -396,7 +396,12 @@ __device__ inline void get_pair(const double2* z, int sig, int m, double2* X, do
 // (xi, delta, Phi'), whose xi and Phi' delta stay in registers, then
 // (U, V, G, dPhi'/dlambda).
 // ---------------------------------------------------------------------------
+// Workgroup size: 128 threads (two waves) for batched launches, 256 (four
+// waves, one signal each) for one or two states, where the ring's own
+// latency sets the kernel time.  The arithmetic of a ring is the same for
+// both (batch invariance).
 constexpr int kHThreads = 128;
+constexpr int kHThreadsSmall = 256;
 
 
 constexpr int ilog2c(int n) {
@@ -465,11 +470,11 @@ __device__ inline void wave_lds_sync() {
 // [w NW, (w+1) NW)), so the stages of a transform need no workgroup barrier:
 // a wave only reads points it wrote itself.  The caller separates the
 // transform from phases that mix signals with a workgroup barrier.
-template <int H, int NSIG, int R, int L, bool kDif, int SGN, typename C>
+template <int H, int NSIG, int R, int L, bool kDif, int SGN, int NT, typename C>
 __device__ inline void ip_stage(C* buf, const C* __restrict__ tw, int tid) {
   constexpr int S = L / R;
   constexpr int NBS = H / R;
-  constexpr int NWAVE = kHThreads / 64;
+  constexpr int NWAVE = NT / 64;
   constexpr int NW = (NSIG + NWAVE - 1) / NWAVE;     // signals per wave
   constexpr int TOTW = NW * NBS;
   constexpr int NIT = (TOTW + 63) / 64;
@@ -524,20 +529,20 @@ __device__ inline void ip_stage(C* buf, const C* __restrict__ tw, int tid) {
   wave_lds_sync();
 }
 
-template <int H, int NSIG, int SGN, int I, typename C>
+template <int H, int NSIG, int SGN, int I, int NT, typename C>
 __device__ inline void dif_stages(C* buf, const C* __restrict__ tw, int tid) {
   if constexpr (I < hplan_npass(H)) {
-    ip_stage<H, NSIG, hplan_radix(H, I), hplan_span(H, I), true, SGN>(buf, tw, tid);
-    dif_stages<H, NSIG, SGN, I + 1>(buf, tw, tid);
+    ip_stage<H, NSIG, hplan_radix(H, I), hplan_span(H, I), true, SGN, NT>(buf, tw, tid);
+    dif_stages<H, NSIG, SGN, I + 1, NT>(buf, tw, tid);
   }
 }
 
 // DIT stages I, I-1, ..., 1 (stage 0 is done by the caller).
-template <int H, int NSIG, int SGN, int I, typename C>
+template <int H, int NSIG, int SGN, int I, int NT, typename C>
 __device__ inline void dit_stages(C* buf, const C* __restrict__ tw, int tid) {
   if constexpr (I >= 1) {
-    ip_stage<H, NSIG, hplan_radix(H, I), hplan_span(H, I), false, SGN>(buf, tw, tid);
-    dit_stages<H, NSIG, SGN, I - 1>(buf, tw, tid);
+    ip_stage<H, NSIG, hplan_radix(H, I), hplan_span(H, I), false, SGN, NT>(buf, tw, tid);
+    dit_stages<H, NSIG, SGN, I - 1, NT>(buf, tw, tid);
   }
 }
 
@@ -558,15 +563,15 @@ __device__ inline C hpost(C Za, C Zb, C w) {
   return mkc<C>(T(0.5) * (Za.x + Zb.x + wd.y), T(0.5) * (Za.y - Zb.y - wd.x));
 }
 
-template <int N, typename T>
-__global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_ring_tendency(
+template <int N, typename T, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_ring_tendency(
     const T* __restrict__ F, T* __restrict__ Gout, const double* __restrict__ c2,
     const double* __restrict__ w, const typename CxOf<T>::C* __restrict__ tw, int M, int nlat,
     int nlat2, int B, double a) {
   using C = typename CxOf<T>::C;
   constexpr int H = N / 2;
   static_assert(hplan_ok(H), "no half-length plan for this ring");
-  constexpr int NPW = (H + kHThreads - 1) / kHThreads;   // pointwise points per thread
+  constexpr int NPW = (H + NT - 1) / NT;   // pointwise points per thread
   using Lay = HRing<H>;
   extern __shared__ __align__(16) unsigned char ring_lds[];
   C* zb = reinterpret_cast<C*>(ring_lds);
@@ -587,7 +592,7 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
   // access); a thread's loads are all issued before its first LDS store.
   auto stage_in = [&](auto nsig, auto field_of) {
     constexpr int NS = decltype(nsig)::value;
-    constexpr int NIT = (H * NS + kHThreads - 1) / kHThreads;   // M < H
+    constexpr int NIT = (H * NS + NT - 1) / NT;   // M < H
     constexpr int CH = 6;                                        // loads in flight
     const int total = (M + 1) * NS;
 #pragma unroll
@@ -595,7 +600,7 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
       C v[CH];
 #pragma unroll
       for (int e = 0; e < CH; ++e) {
-        const int it = (c0 + e) * kHThreads + tid;
+        const int it = (c0 + e) * NT + tid;
         const int m = it / NS, sl = it - m * NS;
         v[e] = (c0 + e < NIT && it < total)
                    ? *reinterpret_cast<const C*>(frow + m * fstride + 2 * field_of(sl))
@@ -603,7 +608,7 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
       }
 #pragma unroll
       for (int e = 0; e < CH; ++e) {
-        const int it = (c0 + e) * kHThreads + tid;
+        const int it = (c0 + e) * NT + tid;
         if (c0 + e < NIT && it < total) {
           const int m = it / NS, sl = it - m * NS;
           zb[Lay::at(sl, m)] = v[e];
@@ -619,10 +624,10 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
   // derivative).
   auto put = [&](auto nsig, auto post) {
     constexpr int NS = decltype(nsig)::value;
-    constexpr int NQ = (H / 2 + kHThreads) / kHThreads;   // pairs (k, H-k) per thread
+    constexpr int NQ = (H / 2 + NT) / NT;   // pairs (k, H-k) per thread
 #pragma unroll
     for (int it = 0; it < NQ; ++it) {
-      const int q = tid + it * kHThreads;
+      const int q = tid + it * NT;
       if (q <= H / 2) {
         const int k1 = q, k2 = H - q;
         const bool h1 = q <= M, h2 = q > 0 && k2 <= M;
@@ -653,13 +658,13 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
   // ---- group 1: xi, delta, Phi' -> keep xi and Phi' delta per point ----
   stage_in(std::integral_constant<int, 3>(), [](int sl) { return sl; });
   put(std::integral_constant<int, 3>(), ident);
-  dif_stages<H, 3, 1, 0>(zb, tw, tid);
+  dif_stages<H, 3, 1, 0, NT>(zb, tw, tid);
   __syncthreads();
   C Xr[NPW], Dr[NPW];
 #pragma unroll
   for (int t = 0; t < NPW; ++t) {
-    const int p = tid + t * kHThreads;
-    if (H % kHThreads == 0 || p < H) {
+    const int p = tid + t * NT;
+    if (H % NT == 0 || p < H) {
       const C xi = zb[Lay::at(0, p)], de = zb[Lay::at(1, p)], ph = zb[Lay::at(2, p)];
       Xr[t] = xi;
       Dr[t] = mkc<C>(ph.x * de.x, ph.y * de.y);
@@ -673,12 +678,12 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
   put(std::integral_constant<int, 4>(), [](int sl, int m, C x) -> C {
     return sl == 3 ? mkc<C>(-T(m) * x.y, T(m) * x.x) : x;
   });
-  dif_stages<H, 4, 1, 0>(zb, tw, tid);
+  dif_stages<H, 4, 1, 0, NT>(zb, tw, tid);
   __syncthreads();
 #pragma unroll
   for (int t = 0; t < NPW; ++t) {
-    const int p = tid + t * kHThreads;
-    if (H % kHThreads == 0 || p < H) {
+    const int p = tid + t * NT;
+    if (H % NT == 0 || p < H) {
       const C U = zb[Lay::at(0, p)], V = zb[Lay::at(1, p)];
       const C G = zb[Lay::at(2, p)], L = zb[Lay::at(3, p)];
       const C xi = Xr[t], pd = Dr[t];
@@ -693,14 +698,14 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
   __syncthreads();
 
   // ---- forward transforms of (N_Phi, A, B, K) in slots 0..3 ----
-  dit_stages<H, 4, -1, hplan_npass(H) - 1>(zb, tw, tid);
+  dit_stages<H, 4, -1, hplan_npass(H) - 1, NT>(zb, tw, tid);
   __syncthreads();
   // last stage (span H) with the pairing k <-> H - k and the unpacking,
   // written back in place (a thread writes only the points it read)
   constexpr int R1 = hplan_first(H), S1 = H / R1, UPS = S1 / 2;
   constexpr int TOTU = 4 * UPS;
   const int ncg = 8 * B;
-  for (int u = tid; u < TOTU; u += kHThreads) {
+  for (int u = tid; u < TOTU; u += NT) {
     const int sig = u / UPS, uu = u - sig * UPS;
     const int ja = uu, jb = uu == 0 ? S1 / 2 : S1 - uu;
     C za[R1], zc[R1];
@@ -750,7 +755,7 @@ __global__ __launch_bounds__(kHThreads) __attribute__((amdgpu_waves_per_eu(3))) 
   // fields of a record
   T* grow = Gout + (size_t)j * ncg + b * 8;
   const size_t gstride = (size_t)nlat * ncg;
-  for (int it = tid; it < (M + 1) * 4; it += kHThreads) {
+  for (int it = tid; it < (M + 1) * 4; it += NT) {
     const int m = it >> 2, f = it & 3;
     const int sl = f == 0 ? 0 : (f == 1 ? 3 : f - 1);
     *reinterpret_cast<C*>(grow + m * gstride + 2 * f) = zb[Lay::at(sl, m)];
@@ -876,10 +881,16 @@ pint_status ring_prepare(int nlon) {
   switch (nlon) {
 #define PINT_CASE(n)                                                                          \
   case n:                                                                                     \
-    PINT_HIP(hipFuncSetAttribute((const void*)k_ring_tendency<n, double>,                     \
+    PINT_HIP(hipFuncSetAttribute((const void*)k_ring_tendency<n, double, kHThreads>,          \
                                  hipFuncAttributeMaxDynamicSharedMemorySize,                  \
                                  (int)ring_lds_bytes(n, PINT_FP64)));                         \
-    PINT_HIP(hipFuncSetAttribute((const void*)k_ring_tendency<n, float>,                      \
+    PINT_HIP(hipFuncSetAttribute((const void*)k_ring_tendency<n, float, kHThreads>,           \
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,                  \
+                                 (int)ring_lds_bytes(n, PINT_LEG_FP32)));                     \
+    PINT_HIP(hipFuncSetAttribute((const void*)k_ring_tendency<n, double, kHThreadsSmall>,     \
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,                  \
+                                 (int)ring_lds_bytes(n, PINT_FP64)));                         \
+    PINT_HIP(hipFuncSetAttribute((const void*)k_ring_tendency<n, float, kHThreadsSmall>,      \
                                  hipFuncAttributeMaxDynamicSharedMemorySize,                  \
                                  (int)ring_lds_bytes(n, PINT_LEG_FP32)));                     \
     return PINT_OK;
@@ -894,21 +905,28 @@ pint_status ring_prepare(int nlon) {
 pint_status ring_tendency(Plan& p, int B, hipStream_t s) {
   ProfScope ps(p, PK_RING, B, s);
   const bool f32 = p.prec != PINT_FP64;
+  const bool small = B <= 2;
   switch (p.nlon) {
+#define PINT_LAUNCH(n, T, NT, f, g, tw)                                                      \
+  hipLaunchKernelGGL((k_ring_tendency<n, T, NT>), dim3(p.nlat * B), dim3(NT),                \
+                     ring_lds_bytes(n, p.prec), s, f, g, p.c2, p.w, tw, p.M, p.nlat, p.nlat2, B, \
+                     p.a)
 #define PINT_CASE(n)                                                                         \
   case n:                                                                                    \
-    if (f32)                                                                                 \
-      hipLaunchKernelGGL((k_ring_tendency<n, float>), dim3(p.nlat * B), dim3(kHThreads),     \
-                         ring_lds_bytes(n, p.prec), s, reinterpret_cast<const float*>(p.F),  \
-                         reinterpret_cast<float*>(p.G), p.c2, p.w, p.twid32, p.M, p.nlat,    \
-                         p.nlat2, B, p.a);                                                   \
+    if (f32 && small)                                                                        \
+      PINT_LAUNCH(n, float, kHThreadsSmall, reinterpret_cast<const float*>(p.F),             \
+                  reinterpret_cast<float*>(p.G), p.twid32);                                  \
+    else if (f32)                                                                            \
+      PINT_LAUNCH(n, float, kHThreads, reinterpret_cast<const float*>(p.F),                  \
+                  reinterpret_cast<float*>(p.G), p.twid32);                                  \
+    else if (small)                                                                          \
+      PINT_LAUNCH(n, double, kHThreadsSmall, p.F, p.G, p.twid);                             \
     else                                                                                     \
-      hipLaunchKernelGGL((k_ring_tendency<n, double>), dim3(p.nlat * B), dim3(kHThreads),    \
-                         ring_lds_bytes(n, p.prec), s, p.F, p.G, p.c2, p.w, p.twid, p.M,     \
-                         p.nlat, p.nlat2, B, p.a);                                           \
+      PINT_LAUNCH(n, double, kHThreads, p.F, p.G, p.twid);                                  \
     break;
     PINT_FOR_EACH_NLON(PINT_CASE)
 #undef PINT_CASE
+#undef PINT_LAUNCH
     default:
       set_error("no ring FFT for nlon=%d", p.nlon);
       return PINT_E_INVAL;
