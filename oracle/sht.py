@@ -49,6 +49,29 @@ def m_slice(M, m):
     return slice(s, s + (M - m + 1))
 
 
+def truncate(c, M, Mc):
+    """Spectral restriction (spatial coarsening of a coarse level): the
+    coefficients (m, n) with n <= Mc of a truncation-M state, in the
+    truncation-Mc packing.  c: (..., ncoef(M)) -> (..., ncoef(Mc))."""
+    c = np.asarray(c)
+    out = np.zeros(c.shape[:-1] + (ncoef(Mc),), dtype=c.dtype)
+    for m in range(Mc + 1):
+        for n in range(m, Mc + 1):
+            out[..., idx(Mc, m, n)] = c[..., idx(M, m, n)]
+    return out
+
+
+def pad(c, Mc, M):
+    """Spectral prolongation: a truncation-Mc state in the truncation-M packing
+    with zero coefficients for n > Mc."""
+    c = np.asarray(c)
+    out = np.zeros(c.shape[:-1] + (ncoef(M),), dtype=c.dtype)
+    for m in range(Mc + 1):
+        for n in range(m, Mc + 1):
+            out[..., idx(M, m, n)] = c[..., idx(Mc, m, n)]
+    return out
+
+
 def eps(m, n, dtype=np.float64):
     """eps_n^m = sqrt((n^2 - m^2) / (4 n^2 - 1)); zero for n <= m."""
     n = np.asarray(n, dtype=dtype)

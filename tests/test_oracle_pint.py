@@ -228,3 +228,24 @@ def test_mgrit3_level1_cycle_matches_matrix_form(nu, cycles):
         w = relax(w, Fset)
     assert np.allclose(np.array(got[1:]), w, rtol=0, atol=1e-12)
     assert got[0] == W0[0]
+
+
+def test_spatial_coarsening_parareal(c1_small):
+    """Coarse level at truncation Mc < M (reading: coarse propagator =
+    pad(coarse model step(truncate(u)))): the difference-first update leaves
+    every coefficient above Mc equal to the fine propagator's bitwise, and
+    k = N still reproduces serial fine."""
+    from oracle import sht
+    md, U0, fine, _ = c1_small
+    Mc = 10
+    mdc = Model(Mc, 32, 16, phibar=2.94e4)
+    coarse = lambda u: sht.pad(mdc.propagate(sht.truncate(u, 21, Mc), 600.0, 2), Mc, 21)
+    U1, _ = pint.parareal(U0, 4, fine, coarse, 1)
+    hi = np.array([n > Mc for m in range(22) for n in range(m, 22)])
+    for n in range(4):
+        assert np.array_equal(U1[n + 1][:, hi], fine(U0 if n == 0 else pint.serial(
+            U0, 4, coarse)[n])[:, hi])
+    U, _ = pint.parareal(U0, 4, fine, coarse, 4)
+    ser = pint.serial(U0, 4, fine)
+    for a, b in zip(U, ser):
+        assert np.array_equal(a, b)

@@ -159,3 +159,29 @@ def test_wind_norm_parseval():
     Ug, Vg = g.fourier_to_grid(U), g.fourier_to_grid(V)
     ms = 0.5 * np.sum(g.w[:, None] * (Ug ** 2 + Vg ** 2) / g.coslat2[:, None]) / g.nlon
     assert abs(wind_norm(xi, de, M, A) ** 2 - ms) < 1e-12 * ms
+
+
+def test_truncate_pad_against_transforms():
+    """Spectral restriction and prolongation between truncations M and Mc
+    (spatial coarsening of coarse levels): on the fine grid's nodes, a
+    truncation-Mc grid synthesises a coarse state exactly as the fine grid
+    synthesises its zero-padded copy, and analyses any fine field to the
+    truncation of its fine coefficients (exact Gauss quadrature)."""
+    M, Mc, nlon, nlat = 21, 10, 64, 32
+    Gf = sht.Grid(M, nlon, nlat)
+    Gcf = sht.Grid(Mc, nlon, nlat)                 # truncation Mc on the fine nodes
+    rng = np.random.default_rng(11)
+    cc = rng.standard_normal(sht.ncoef(Mc)) + 1j * rng.standard_normal(sht.ncoef(Mc))
+    cc[:Mc + 1] = cc[:Mc + 1].real                 # m = 0 coefficients real
+    assert np.allclose(Gcf.synth(cc), Gf.synth(sht.pad(cc, Mc, M)), rtol=0, atol=1e-13)
+    cf = rng.standard_normal(sht.ncoef(M)) + 1j * rng.standard_normal(sht.ncoef(M))
+    cf[:M + 1] = cf[:M + 1].real
+    g = Gf.synth(cf)
+    assert np.allclose(Gcf.anal(g), sht.truncate(cf, M, Mc), rtol=0, atol=1e-13)
+    # round trip and the zeros above Mc
+    assert np.array_equal(sht.truncate(sht.pad(cc, Mc, M), M, Mc), cc)
+    padded = sht.pad(cc, Mc, M)
+    for m in range(M + 1):
+        for n in range(m, M + 1):
+            if n > Mc:
+                assert padded[sht.idx(M, m, n)] == 0
