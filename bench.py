@@ -226,12 +226,14 @@ def time_to_tol():
     return out
 
 
-def measure(precision, steps, warmup, levels=2):
+def measure(precision, steps, warmup, levels=2, coarse_grid=None):
     """Time `steps` MGRIT iterations at the given Legendre precision (levels 2,
     or 3 with level-2 points every CFACTOR level-1 points, one level-2 step of
     CFACTOR * DT_COARSE, two cycles on levels 1 and 2 per iteration); return
     the throughput, the per-kernel profile of the batched transform kernels,
-    the increments and the slice states after warmup + steps iterations."""
+    the increments and the slice states after warmup + steps iterations.
+    coarse_grid = (Mc, nlon, nlat): coarse level on a plan of that truncation
+    (spatial coarsening)."""
     import numpy as np
     import torch
     from paper_2306_09497_amd import pint, workloads
@@ -246,12 +248,16 @@ def measure(precision, steps, warmup, levels=2):
     slices = torch.zeros((GROUP + 1, 3, plan.ncoef, 2), dtype=torch.float64, device="cuda")
     fine = pint.stepper(DT_FINE, 2, 0.0, pint.T_ALL)
     coarse = pint.stepper(DT_COARSE, Q_COARSE, NU_COARSE, pint.T_ALL)
-    plan.solve(pint.params(pint.MGRIT, GROUP, fine, CFACTOR, coarse, 1, nrelax=1, max_iter=0),
-               u0, slices)                                     # initial coarse sweep
     extra = {}
+    cplan = None
+    if coarse_grid is not None:
+        cplan = pint.Plan(*coarse_grid, phibar=PHIBAR, max_batch=GROUP, precision=precision)
+        extra["coarse_plan"] = cplan
     if levels == 3:
-        extra = dict(levels=3, cfactor1=CFACTOR, coarse2_steps=1, cycles1=2,
+        extra.update(levels=3, cfactor1=CFACTOR, coarse2_steps=1, cycles1=2,
                      coarse2=pint.stepper(DT_COARSE * CFACTOR, Q_COARSE, NU_COARSE, pint.T_ALL))
+    plan.solve(pint.params(pint.MGRIT, GROUP, fine, CFACTOR, coarse, 1, nrelax=1, max_iter=0,
+                           coarse_plan=cplan), u0, slices)     # initial coarse sweep
     it = pint.params(pint.MGRIT, GROUP, fine, CFACTOR, coarse, 1, nrelax=1, max_iter=1,
                      resume=True, **extra)
     for _ in range(warmup):
@@ -274,6 +280,8 @@ def measure(precision, steps, warmup, levels=2):
     prof = plan.profile_read()
     plan.profile([])
     plan.close()
+    if cplan is not None:
+        cplan.close()
     elapsed = t1 - t0
     return {"value": fine_steps / elapsed, "elapsed": elapsed, "fine_steps": fine_steps,
             "prof": prof, "incr": incr, "slices": slices}
@@ -420,6 +428,29 @@ def main():
             }
         except Exception as e:                      # reported, not fatal
             out["mgrit3"] = {"error": str(e)}
+        # two levels with spatial coarsening: the coarse level at T127 (384x192)
+        try:
+            rc = measure(pint.FP64, args.steps, args.warmup, coarse_grid=(127, 384, 192))
+            out["mgrit2_coarse_t127"] = {
+                "value": rc["value"], "unit": "slice-steps/s",
+                "ms_per_step": rc["elapsed"] / args.steps * 1e3,
+                "increment": rc["incr"],
+                "config": "two levels, coarse level at T127 on 384x192 (truncate, step, pad), "
+                          "coarse dt 180 s q=4 nu=1e17",
+            }
+        except Exception as e:
+            out["mgrit2_coarse_t127"] = {"error": str(e)}
+        try:
+            rc3 = measure(pint.FP64, args.steps, args.warmup, levels=3,
+                          coarse_grid=(127, 384, 192))
+            out["mgrit3_coarse_t127"] = {
+                "value": rc3["value"], "unit": "slice-steps/s",
+                "ms_per_step": rc3["elapsed"] / args.steps * 1e3,
+                "increment": rc3["incr"],
+                "config": "three levels as mgrit3, both coarse levels at T127 on 384x192",
+            }
+        except Exception as e:
+            out["mgrit3_coarse_t127"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

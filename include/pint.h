@@ -193,6 +193,16 @@ typedef struct {
   int coarse2_steps;      /* levels 3: coarse2 steps per level-2 interval  */
   int cycles1;            /* levels 3: cycles on levels (1, 2) per
                              iteration, >= 1                              */
+  pint_plan* coarse_plan; /* NULL: coarse levels at the plan's truncation.
+                             Otherwise spatial coarsening (Sec. 5): every
+                             coarse-level step runs on this plan (truncation
+                             Mc <= M, same planet and Phibar) as
+                             pad(step(truncate(u))): coefficients with
+                             n > Mc are dropped before and zero after it.
+                             The difference-first updates then keep the
+                             fine values of those coefficients exactly.
+                             Not thread-safe with other calls on either
+                             plan.                                         */
 } pint_pint_params;
 
 typedef struct {

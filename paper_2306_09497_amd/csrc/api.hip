@@ -128,6 +128,14 @@ static pint_status check_params(const Plan& p, const pint_pint_params* q) {
     set_error("fine (%g s) and coarse (%g s) propagators must span the same interval", DTf, DTc);
     return PINT_E_INVAL;
   }
+  if (q->coarse_plan) {
+    const Plan& c = q->coarse_plan->p;
+    if (c.M > p.M || c.a != p.a || c.omega != p.omega || c.g != p.g || c.phibar != p.phibar) {
+      set_error("coarse_plan needs a truncation <= the plan's (%d > %d?) and the same planet and "
+                "Phibar", c.M, p.M);
+      return PINT_E_INVAL;
+    }
+  }
   if (q->levels != 0 && q->levels != 2 && q->levels != 3) {
     set_error("levels must be 2 (or 0) or 3");
     return PINT_E_INVAL;
@@ -163,6 +171,51 @@ static pint_status copy_states(double* dst, size_t dstride, const double* src, s
   return PINT_OK;
 }
 
+// Coarse-level propagation: on the plan itself, or with spatial coarsening
+// (Sec. 5) on the coarse plan as pad(step(truncate(u))).  side: the serial
+// sweep's stream, with the stepping plan's sweep workspace.
+struct CoarseProp {
+  Plan& p;
+  Plan* pc = nullptr;
+  DevBuf cin, cin_side;   // truncation-Mc states
+  int cap = 0;            // states cin holds
+  explicit CoarseProp(Plan& fine) : p(fine) {}
+  pint_status init(const pint_pint_params* q, int cap_states) {
+    if (!q->coarse_plan) return PINT_OK;
+    pc = &q->coarse_plan->p;
+    cap = cap_states;
+    const size_t sdc = (size_t)3 * pc->ncoef * 2;
+    PINT_TRY(cin.alloc(sdc * cap));
+    return cin_side.alloc(sdc);
+  }
+  Plan& stepping() { return pc ? *pc : p; }
+  pint_status run(const pint_stepper& st, int nsteps, const double* in, double* out, int B,
+                  hipStream_t s, bool side) {
+    if (!pc) {
+      if (side) {
+        SideWork sw(p);
+        return propagate(p, st, in, out, B, nsteps, s);
+      }
+      return propagate(p, st, in, out, B, nsteps, s);
+    }
+    const size_t sdf = (size_t)3 * p.ncoef * 2;
+    const int chunk = side ? 1 : cap;
+    double* cb = side ? cin_side.p : cin.p;
+    for (int b0 = 0; b0 < B; b0 += chunk) {
+      const int nb = B - b0 < chunk ? B - b0 : chunk;
+      PINT_TRY(spec_truncate(in + b0 * sdf, p.M, cb, pc->M, nb, s));
+      if (side) {
+        SideWork sw(*pc);
+        PINT_TRY(propagate(*pc, st, cb, cb, nb, nsteps, s));
+      } else {
+        PINT_TRY(propagate(*pc, st, cb, cb, nb, nsteps, s));
+      }
+      PINT_TRY(spec_pad(cb, pc->M, out + b0 * sdf, p.M, nb, s));
+    }
+    return PINT_OK;
+  }
+};
+
 // Three-level MGRIT, level-1 part (Sec. 3.2, multilevel recursion): cycles1
 // two-level iterations on levels (1, 2) of the level-1 problem
 //   w_0 = U_0,  w_i = psi_i(w_{i-1}) = (Phi_1(w_{i-1}) - G_i) + F_i,
@@ -185,9 +238,9 @@ struct Level1Bufs {
   }
 };
 
-static pint_status level1_cycles(Plan& p, const pint_pint_params* q, Level1Bufs& b, double* U,
-                                 const double* Fv, const double* Gold, pint_report* r,
-                                 hipStream_t s) {
+static pint_status level1_cycles(Plan& p, const pint_pint_params* q, Level1Bufs& b,
+                                 CoarseProp& cp, double* U, const double* Fv,
+                                 const double* Gold, pint_report* r, hipStream_t s) {
   const int N1 = q->n_intervals, m1 = q->cfactor1, N2 = N1 / m1;
   const size_t sd = (size_t)3 * p.ncoef * 2;
   const size_t row = (size_t)(N2 + 1);
@@ -204,7 +257,7 @@ static pint_status level1_cycles(Plan& p, const pint_pint_params* q, Level1Bufs&
   const size_t nb = (size_t)N2 * sd;                  // doubles of one batch
   // out = psi applied to row sin (entries 0..N2-1), forcing of row sr from j0
   auto psi_row = [&](int sin, int sr, int j0, double* out) -> pint_status {
-    PINT_TRY(propagate(p, q->coarse, at(b.W.p, sin, 0), b.tmp.p, N2, q->coarse_steps, s));
+    PINT_TRY(cp.run(q->coarse, q->coarse_steps, at(b.W.p, sin, 0), b.tmp.p, N2, s, false));
     r->coarse_steps += (long long)N2 * q->coarse_steps;
     return pr_update(p, b.tmp.p, at(b.Gl.p, sr, j0), at(b.Fl.p, sr, j0), out, nb, s);
   };
@@ -220,14 +273,14 @@ static pint_status level1_cycles(Plan& p, const pint_pint_params* q, Level1Bufs&
     }
     // level 2: F2_j = psi(w_{m1 j - 1}), G2_j = Phi_2(v2_{j-1}), j = 1..N2
     PINT_TRY(psi_row(m1 - 1, 0, 1, b.F2.p));
-    PINT_TRY(propagate(p, q->coarse2, at(b.W.p, 0, 0), b.G2.p, N2, q->coarse2_steps, s));
+    PINT_TRY(cp.run(q->coarse2, q->coarse2_steps, at(b.W.p, 0, 0), b.G2.p, N2, s, false));
     r->coarse_steps += (long long)N2 * q->coarse2_steps;
     // serial level-2 solve z_j = (Phi_2(z_{j-1}) - G2_j) + F2_j into W[0][j]
     for (int j = 1; j <= N2; ++j) {
       const double* g2 = b.G2.p + (size_t)(j - 1) * sd;
       const double* gnew = g2;                        // Phi_2(z_0) = Phi_2(v2_0)
       if (j > 1) {
-        PINT_TRY(propagate(p, q->coarse2, at(b.W.p, 0, j - 1), b.gz.p, 1, q->coarse2_steps, s));
+        PINT_TRY(cp.run(q->coarse2, q->coarse2_steps, at(b.W.p, 0, j - 1), b.gz.p, 1, s, false));
         r->coarse_steps += q->coarse2_steps;
         gnew = b.gz.p;
       }
@@ -264,24 +317,26 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
   const bool three = mgrit && q->levels == 3;
   Level1Bufs l1;
   if (three) PINT_TRY(l1.alloc(sd, q->cfactor1, N / q->cfactor1));
+  CoarseProp coarse(p);
+  PINT_TRY(coarse.init(q, N));
   // Crank-Nicolson factors of the propagators, made on s before any work
   // goes to the sweep stream
   const CnFactors* cf = nullptr;
   PINT_TRY(cn_factors(p, q->fine.dt, q->fine.terms, s, &cf));
-  PINT_TRY(cn_factors(p, q->coarse.dt, q->coarse.terms, s, &cf));
-  if (three) PINT_TRY(cn_factors(p, q->coarse2.dt, q->coarse2.terms, s, &cf));
+  PINT_TRY(cn_factors(coarse.stepping(), q->coarse.dt, q->coarse.terms, s, &cf));
+  if (three) PINT_TRY(cn_factors(coarse.stepping(), q->coarse2.dt, q->coarse2.terms, s, &cf));
   if (q->resume) {
     // continue from the iterate held in U; the coarse values of its slice
     // starts are recomputed (bitwise what the previous sweep produced)
     if (nrelax == 0 && !three) {
-      PINT_TRY(propagate(p, q->coarse, U, Gold.p, N, q->coarse_steps, s));
+      PINT_TRY(coarse.run(q->coarse, q->coarse_steps, U, Gold.p, N, s, false));
       r->coarse_steps += (long long)N * q->coarse_steps;
     }
   } else {
     if (U != u0) PINT_HIP(hipMemcpyAsync(U, u0, sb, hipMemcpyDeviceToDevice, s));
     // iteration 0: serial coarse sweep, G_n = phi_c(U_n), U_{n+1} = G_n
     for (int n = 0; n < N; ++n) {
-      PINT_TRY(propagate(p, q->coarse, U + n * sd, Gold.p + n * sd, 1, q->coarse_steps, s));
+      PINT_TRY(coarse.run(q->coarse, q->coarse_steps, U + n * sd, Gold.p + n * sd, 1, s, false));
       PINT_HIP(hipMemcpyAsync(U + (n + 1) * sd, Gold.p + n * sd, sb, hipMemcpyDeviceToDevice, s));
       r->coarse_steps += q->coarse_steps;
     }
@@ -302,19 +357,19 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
         r->fine_slice_steps += (long long)N * q->fine_steps;
       }
       // coarse values of the relaxed C-points, Phi_1(v_i)
-      PINT_TRY(propagate(p, q->coarse, U, Gold.p, N, q->coarse_steps, s));
+      PINT_TRY(coarse.run(q->coarse, q->coarse_steps, U, Gold.p, N, s, false));
       r->coarse_steps += (long long)N * q->coarse_steps;
     }
     if (three) {
       // three levels: Phi_1(v_i) of the (relaxed) C-points, F_i of every
       // interval, then the level-1 problem by cycles on levels (1, 2)
       if (nrelax == 0) {
-        PINT_TRY(propagate(p, q->coarse, U, Gold.p, N, q->coarse_steps, s));
+        PINT_TRY(coarse.run(q->coarse, q->coarse_steps, U, Gold.p, N, s, false));
         r->coarse_steps += (long long)N * q->coarse_steps;
       }
       PINT_TRY(propagate(p, q->fine, U, Fv.p, N, q->fine_steps, s));
       r->fine_slice_steps += (long long)N * q->fine_steps;
-      PINT_TRY(level1_cycles(p, q, l1, U, Fv.p, Gold.p, r, s));
+      PINT_TRY(level1_cycles(p, q, l1, coarse, U, Fv.p, Gold.p, r, s));
     } else {
       // fine propagation of every active slice (the parallel part), in chunks
       // of cs slices; chunk c's event releases the sweep steps that need it
@@ -333,7 +388,6 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
       // reads F(U_n^old) (chunk (n-first)/cs) and overwrites U_{n+1}, the start
       // of chunk (n+1-first)/cs when it begins one: it waits for both.
       {
-        SideWork side(p);
         hipStream_t ss = p.side_stream;
         int waited = -1;
         for (int n = first; n < N; ++n) {
@@ -342,7 +396,7 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
           while (waited < need) PINT_HIP(hipStreamWaitEvent(ss, p.chunk_ev[++waited], 0));
           const double* gnew = Gold.p + n * sd;        // unchanged input at n == first
           if (n > first) {
-            PINT_TRY(propagate(p, q->coarse, U + n * sd, Gtmp.p, 1, q->coarse_steps, ss));
+            PINT_TRY(coarse.run(q->coarse, q->coarse_steps, U + n * sd, Gtmp.p, 1, ss, true));
             r->coarse_steps += q->coarse_steps;
             gnew = Gtmp.p;
           }

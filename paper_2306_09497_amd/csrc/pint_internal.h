@@ -193,6 +193,8 @@ pint_status imex_steps(Plan& p, const pint_stepper& st, const double* in, double
 
 // transforms on the GEMM workspace
 // prec: PINT_FP64 (also used by the public scalar transforms) or PINT_LEG_FP32
+pint_status spec_truncate(const double* in, int Mf, double* out, int Mc, int B, hipStream_t s);
+pint_status spec_pad(const double* in, int Mc, double* out, int Mf, int B, hipStream_t s);
 pint_status legendre_synth(Plan& p, int B, int nf, int prec, hipStream_t s);
 pint_status legendre_anal(Plan& p, int B, int nf, int prec, hipStream_t s);
 pint_status ring_tendency(Plan& p, int B, hipStream_t s);

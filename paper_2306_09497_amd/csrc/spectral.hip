@@ -739,4 +739,45 @@ pint_status scalar_post(Plan& p, double* spec, int B, hipStream_t s) {
   return PINT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Spectral restriction / prolongation between truncations Mf >= Mc (spatial
+// coarsening of the coarse levels, Sec. 5): truncate keeps the coefficients
+// (m, n) with n <= Mc; pad puts a truncation-Mc state into the
+// truncation-Mf packing with zeros above Mc.  One thread per output
+// coefficient: x = n - m, y = m, z = state * 3 + field; public layout
+// [B][3][ncoef][2].
+// ---------------------------------------------------------------------------
+__global__ void k_truncate(const double* __restrict__ in, double* __restrict__ out, int Mf,
+                           int Mc) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x, m = blockIdx.y, bf = blockIdx.z;
+  if (k > Mc - m) return;
+  const size_t ncf = (size_t)(Mf + 1) * (Mf + 2) / 2, ncc = (size_t)(Mc + 1) * (Mc + 2) / 2;
+  st2(out, bf * ncc + coef_idx(Mc, m, m) + k, ld2(in, bf * ncf + coef_idx(Mf, m, m) + k));
+}
+
+__global__ void k_pad(const double* __restrict__ in, double* __restrict__ out, int Mc, int Mf) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x, m = blockIdx.y, bf = blockIdx.z;
+  if (k > Mf - m) return;
+  const size_t ncf = (size_t)(Mf + 1) * (Mf + 2) / 2, ncc = (size_t)(Mc + 1) * (Mc + 2) / 2;
+  const double2 v = (m <= Mc && k <= Mc - m) ? ld2(in, bf * ncc + coef_idx(Mc, m, m) + k)
+                                             : make_double2(0.0, 0.0);
+  st2(out, bf * ncf + coef_idx(Mf, m, m) + k, v);
+}
+
+pint_status spec_truncate(const double* in, int Mf, double* out, int Mc, int B, hipStream_t s) {
+  if (B <= 0) return PINT_OK;
+  const dim3 grid((unsigned)((Mc + 64) / 64), (unsigned)(Mc + 1), (unsigned)(3 * B));
+  hipLaunchKernelGGL(k_truncate, grid, dim3(64), 0, s, in, out, Mf, Mc);
+  PINT_HIP(hipGetLastError());
+  return PINT_OK;
+}
+
+pint_status spec_pad(const double* in, int Mc, double* out, int Mf, int B, hipStream_t s) {
+  if (B <= 0) return PINT_OK;
+  const dim3 grid((unsigned)((Mf + 64) / 64), (unsigned)(Mf + 1), (unsigned)(3 * B));
+  hipLaunchKernelGGL(k_pad, grid, dim3(64), 0, s, in, out, Mc, Mf);
+  PINT_HIP(hipGetLastError());
+  return PINT_OK;
+}
+
 }  // namespace pint

@@ -276,3 +276,83 @@ def test_mgrit3_invalid_params(setup):
     bad.method = pint.PARAREAL
     st, _, msg = pl.solve_status(bad, u0, out)
     assert st == -1 and "MGRIT" in msg
+
+
+@pytest.fixture(scope="module")
+def coarse_t10():
+    """Coarse-level plan at truncation 10 (spatial coarsening of a T21 run)."""
+    pc = pint.Plan(10, 64, 32, phibar=PHIBAR, max_batch=8)
+    mdc = Model(10, 64, 32, phibar=PHIBAR)
+    yield pc, mdc
+    pc.close()
+
+
+@pytest.mark.parametrize("method,nrelax,k", [(pint.PARAREAL, 0, 1), (pint.PARAREAL, 0, 2),
+                                             (pint.MGRIT, 1, 1)])
+def test_spatial_coarsening_vs_oracle(setup, coarse_t10, method, nrelax, k):
+    """NEXT-2 spatial coarsening: coarse levels at T10 for a T21 run (coarse
+    propagator pad(step_T10(truncate(u)))) against the oracle."""
+    from oracle import sht
+    md, pl = setup
+    pc, mdc = coarse_t10
+    U0 = workloads.solid_body(M, noise=1e-3, seed=9)
+    f = pint.stepper(300.0, 2, 0.0, T_ALL)
+    c = pint.stepper(600.0, 4, 1e13, T_ALL)
+    coarse = lambda u: sht.pad(mdc.propagate(sht.truncate(u, M, 10), 600.0, 2, 1e13, 4, T_ALL),
+                               10, M)
+    if method == pint.PARAREAL:
+        ref, _ = opint.parareal(U0, 8, lambda u: md.propagate(u, 300.0, 4), coarse, k)
+        prm = pint.params(method, 8, f, 4, c, 2, max_iter=k, coarse_plan=pc)
+    else:
+        ref, _ = opint.mgrit2(U0, 8, 4, lambda u: md.propagate(u, 300.0, 1), coarse, 1, k)
+        prm = pint.params(method, 8, f, 4, c, 2, nrelax=1, max_iter=k, coarse_plan=pc)
+    got, _ = run_solve(pl, prm, U0, 8)
+    for i in range(9):
+        assert_parity(got[i], ref[i], M)
+
+
+def test_spatial_coarsening_same_truncation_bitwise(setup):
+    """A coarse plan at the plan's own truncation gives bitwise the iterates
+    of no coarse plan (truncation and padding are then copies)."""
+    md, pl = setup
+    p2 = pint.Plan(M, NLON, NLAT, phibar=PHIBAR, max_batch=8)
+    U0 = workloads.solid_body(M, noise=1e-3, seed=10)
+    f = pint.stepper(300.0, 2, 0.0, T_ALL)
+    c = pint.stepper(1200.0, 4, 1e15, T_ALL)
+    for kw in (dict(), dict(levels=3, cfactor1=2, coarse2=pint.stepper(2400.0, 4, 1e15, T_ALL))):
+        a, _ = run_solve(pl, pint.params(pint.MGRIT, 8, f, 4, c, 1, nrelax=1, max_iter=2, **kw),
+                         U0, 8)
+        b, _ = run_solve(pl, pint.params(pint.MGRIT, 8, f, 4, c, 1, nrelax=1, max_iter=2,
+                                         coarse_plan=p2, **kw), U0, 8)
+        assert np.array_equal(a, b)
+    p2.close()
+
+
+def test_spatial_coarsening_exact_and_checks(setup, coarse_t10):
+    """Parareal with a T10 coarse level still reproduces serial fine bitwise
+    at k = N; a coarse plan of higher truncation or another Phibar is
+    rejected."""
+    md, pl = setup
+    pc, _ = coarse_t10
+    U0 = workloads.solid_body(M, noise=1e-4, seed=11)
+    f = pint.stepper(300.0, 2, 0.0, T_ALL)
+    c = pint.stepper(600.0, 4, 1e13, T_ALL)
+    got, _ = run_solve(pl, pint.params(pint.PARAREAL, 4, f, 4, c, 2, max_iter=4,
+                                       coarse_plan=pc), U0, 4)
+    u = to_dev(U0, torch)
+    for n in range(1, 5):
+        pl.step(f, u, u, 1, 4)
+        torch.cuda.synchronize()
+        assert np.array_equal(from_dev(u)[0], got[n])
+    u0 = to_dev(U0, torch)
+    out = torch.zeros((5, 3, pl.ncoef, 2), dtype=torch.float64, device="cuda")
+    pbig = pint.Plan(42, 128, 64, phibar=PHIBAR, max_batch=2)
+    st, _, msg = pl.solve_status(pint.params(pint.PARAREAL, 4, f, 4, c, 2, max_iter=1,
+                                             coarse_plan=pbig), u0, out)
+    assert st == -1 and "coarse_plan" in msg
+    pbig.close()
+    pphi = pint.Plan(10, 64, 32, phibar=3.0e4, max_batch=2)
+    st, _, msg = pl.solve_status(pint.params(pint.PARAREAL, 4, f, 4, c, 2, max_iter=1,
+                                             coarse_plan=pphi), u0, out)
+    assert st == -1 and "coarse_plan" in msg
+    pphi.close()
