@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // even rows, the others the odd rows.  Per output element the matrix cores
 // consume k in steps of 4 in increasing order, as in every other shape.
 template <typename E, int TC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_legendre_anal(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_legendre_anal(
     const E* __restrict__ Tt, const int* __restrict__ rowoff, const int* __restrict__ tiles,
     const E* __restrict__ G, E* __restrict__ Q, int nlat, int nlat2, int ncol, int nrows) {
   using MM = Mma<E>;
@@ -200,8 +200,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   constexpr int WR = 4 / WC;                         // waves across rows
   constexpr int BI = TR / WR / 16, BJ = TC / WC / 16;
   static_assert(BI >= 1 && BJ >= 1 && NA >= 1 && NB >= 1 && (TR / WR) <= TR2, "tile shape");
-  __shared__ E As[2][TK * LDA];
-  __shared__ E Bs[2][2][TK * LDB];                   // [buffer][parity]
+  // one LDS slab (the next one is held in registers while the current one
+  // is consumed): four workgroups per CU instead of three
+  __shared__ E As[TK * LDA];
+  __shared__ E Bs[2][TK * LDB];                      // [parity]
 
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int nct = (ncol + TC - 1) / TC;
@@ -254,32 +256,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       rbo[e4] = vo;
     }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&]() {
 #pragma unroll
     for (int e4 = 0; e4 < NA; ++e4) {
       const int e = tid + e4 * 256;
-      As[buf][(e / TR) * LDA + (e % TR)] = ra[e4];
+      As[(e / TR) * LDA + (e % TR)] = ra[e4];
     }
 #pragma unroll
     for (int e4 = 0; e4 < NB; ++e4) {
       const int e = tid + e4 * 256;
-      Bs[buf][0][(e / TC) * LDB + (e % TC)] = rbe[e4];
-      Bs[buf][1][(e / TC) * LDB + (e % TC)] = rbo[e4];
+      Bs[0][(e / TC) * LDB + (e % TC)] = rbe[e4];
+      Bs[1][(e / TC) * LDB + (e % TC)] = rbo[e4];
     }
   };
   const int nslab = (nlat2 + TK - 1) / TK;
   fetch(0);
-  stash(0);
+  stash();
   __syncthreads();
   for (int sl = 0; sl < nslab; ++sl) {
-    const int cur = sl & 1;
     if (sl + 1 < nslab) fetch((sl + 1) * TK);
-    const E* bs = Bs[cur][par];
+    const E* bs = Bs[par];
 #pragma unroll
     for (int ks = 0; ks < TK; ks += 4) {
       E a[BI], b[BJ];
 #pragma unroll
-      for (int i = 0; i < BI; ++i) a[i] = As[cur][(ks + lk) * LDA + wr + 16 * i + li];
+      for (int i = 0; i < BI; ++i) a[i] = As[(ks + lk) * LDA + wr + 16 * i + li];
 #pragma unroll
       for (int j = 0; j < BJ; ++j) b[j] = bs[(ks + lk) * LDB + wc + 16 * j + li];
 #pragma unroll
@@ -287,7 +288,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
         for (int j = 0; j < BJ; ++j) acc[i][j] = MM::mma(a[i], b[j], acc[i][j]);
     }
-    if (sl + 1 < nslab) stash(cur ^ 1);
+    if (sl + 1 < nslab) {
+      __syncthreads();                               // every wave has read the slab
+      stash();
+    }
     __syncthreads();
   }
   const int roff = par ? roffO : roffE, cnt = par ? cntO : cntE;
