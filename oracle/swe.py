@@ -162,20 +162,21 @@ class Model:
             out[0, sl], out[1, sl], out[2, sl] = r[:K], r[K:2 * K], r[2 * K:]
         return out
 
-    def cn_half(self, U, dt, terms=T_ALL):
-        """Crank-Nicolson half step: (I - dt/4 L) x = (I + dt/4 L) U."""
+    def cn_half(self, U, dt, terms=T_ALL, ms=None):
+        """Crank-Nicolson half step: (I - dt/4 L) x = (I + dt/4 L) U.
+
+        ``ms`` restricts the solve to the listed zonal wavenumbers (the
+        others are left zero), for sampled checks at large M."""
         alpha = dt / 4.0
         key = (alpha, terms & (T_LG | T_LC))
-        if key not in self._lu_cache:
-            facs = []
-            for m in range(self.M + 1):
+        ms = range(self.M + 1) if ms is None else ms
+        facs = self._lu_cache.setdefault(key, {})
+        out = np.zeros_like(U)
+        for m in ms:
+            if m not in facs:
                 L = self.linear_matrix(m, terms)
                 Id = np.eye(L.shape[0])
-                facs.append((Id + alpha * L, scipy.linalg.lu_factor(Id - alpha * L)))
-            self._lu_cache[key] = facs
-        facs = self._lu_cache[key]
-        out = np.zeros_like(U)
-        for m in range(self.M + 1):
+                facs[m] = (Id + alpha * L, scipy.linalg.lu_factor(Id - alpha * L))
             sl = m_slice(self.M, m)
             K = self.M - m + 1
             v = np.concatenate([U[0, sl], U[1, sl], U[2, sl]])

@@ -1,0 +1,151 @@
+"""GPU edge cases through the C ABI: empty batches and zero step counts, the
+smallest truncation, a zero state, a single time slice, and the largest
+supported sizes (1024-point rings, 512-coefficient implicit chains)."""
+
+import numpy as np
+import pytest
+
+from gpu_util import assert_parity, from_dev, to_dev
+from oracle.sht import m_slice
+from oracle.swe import Model, T_ALL
+from paper_2306_09497_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2306_09497_amd import pint  # noqa: E402
+
+JET_PHIBAR = 9.80616e4
+
+
+def jet_state(md, amp=120.0, lam_c=1.0):
+    G = workloads.jet_bump_grid(md.grid.mu, md.grid.nlon, phibar=JET_PHIBAR, amp=amp,
+                                lam_c=lam_c)
+    return np.stack([md.grid.anal(G[f]) for f in range(3)])
+
+
+def test_empty_batches_and_zero_steps():
+    """B = 0 calls return without touching memory; nsteps = 0 copies the
+    input (and is a no-op in place)."""
+    pl = pint.Plan(21, 64, 32, phibar=2.94e4, max_batch=4)
+    U = workloads.solid_body(21, noise=1e-3, seed=1)
+    u = to_dev(U, torch)
+    sentinel = torch.full_like(u, 7.0)
+    out = sentinel.clone()
+    pl.tendency(u, out, 0)
+    pl.implicit(pint.stepper(600.0), u, out, 0)
+    pl.step(pint.stepper(600.0), u, out, 0, 3)
+    grid = torch.full((1, 32, 64), 7.0, dtype=torch.float64, device="cuda")
+    pl.synthesis(u[:, 0].contiguous(), grid, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(out, sentinel) and bool((grid == 7.0).all())
+    pl.step(pint.stepper(600.0), u, out, 1, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(out, u)
+    v = u.clone()
+    pl.step(pint.stepper(600.0), v, v, 1, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(v, u)
+    pl.close()
+
+
+def test_smallest_truncation():
+    """M = 1 (modes (0,0), (0,1), (1,1)): tendencies and IMEX steps against
+    the oracle."""
+    md = Model(1, 64, 32, phibar=2.94e4)
+    pl = pint.Plan(1, 64, 32, phibar=2.94e4, max_batch=2)
+    rng = np.random.default_rng(3)
+    U = (rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))) * np.array(
+        [[1e3], [1e-5], [1e-6]])
+    U[:, :2] = U[:, :2].real                       # m = 0 coefficients real
+    U[0, 0] += 2.94e4                              # Phi about its mean
+    u = to_dev(U, torch)
+    out = torch.zeros_like(u)
+    pl.tendency(u, out, 1)
+    pl.step(pint.stepper(600.0, 2, 1e5, T_ALL), u, u, 1, 5)
+    torch.cuda.synchronize()
+    assert_parity(from_dev(out)[0], md.tendencies(U), 1)
+    assert_parity(from_dev(u)[0], md.propagate(U, 600.0, 5, 1e5, 2, T_ALL), 1)
+    pl.close()
+
+
+def test_rest_state_is_fixed():
+    """The state at rest (Phi = Phibar, xi = delta = 0) has zero tendencies
+    and is a fixed point of the IMEX step: every coefficient but the mean
+    stays exactly zero, the mean to rounding."""
+    M, phibar = 21, 2.94e4
+    pl = pint.Plan(M, 64, 32, phibar=phibar, max_batch=2)
+    U = np.zeros((3, (M + 1) * (M + 2) // 2), dtype=complex)
+    U[0, 0] = phibar
+    u = to_dev(U, torch)
+    out = torch.full_like(u, 1.0)
+    pl.tendency(u, out, 1)
+    pl.step(pint.stepper(600.0, 4, 1e15, T_ALL), u, u, 1, 4)
+    torch.cuda.synchronize()
+    assert float(out.abs().max()) == 0.0
+    got = from_dev(u)[0]
+    assert abs(got[0, 0] - phibar) <= 1e-15 * phibar
+    got[0, 0] = 0.0
+    assert float(np.abs(got).max()) == 0.0
+    pl.close()
+
+
+def test_single_slice_pint():
+    """One time slice: one Parareal or MGRIT iteration is the fine solve."""
+    M = 21
+    pl = pint.Plan(M, 64, 32, phibar=2.94e4, max_batch=2)
+    U0 = workloads.solid_body(M, noise=1e-3, seed=2)
+    f = pint.stepper(300.0, 2, 0.0, T_ALL)
+    c = pint.stepper(1200.0, 2, 0.0, T_ALL)
+    ref = to_dev(U0, torch)
+    pl.step(f, ref, ref, 1, 4)
+    for method, nrelax in ((pint.PARAREAL, 0), (pint.MGRIT, 1)):
+        out = torch.zeros((2, 3, pl.ncoef, 2), dtype=torch.float64, device="cuda")
+        rep = pl.solve(pint.params(method, 1, f, 4, c, 1, nrelax=nrelax, max_iter=1),
+                       to_dev(U0, torch), out)
+        torch.cuda.synchronize()
+        assert rep.iters == 1
+        assert torch.equal(out[1], ref[0])
+    pl.close()
+
+
+def test_largest_ring_tendency():
+    """The largest ring (nlon 1024, T340 on the 3/2-rule grid 1024 x 512):
+    one N-eval against the oracle."""
+    md = Model(340, 1024, 512, phibar=JET_PHIBAR)
+    pl = pint.Plan(340, 1024, 512, phibar=JET_PHIBAR, max_batch=1)
+    U = jet_state(md)
+    u = to_dev(U, torch)
+    out = torch.zeros_like(u)
+    pl.tendency(u, out, 1)
+    torch.cuda.synchronize()
+    assert_parity(from_dev(out)[0], md.tendencies(U), 340)
+    pl.close()
+
+
+def test_longest_implicit_chains():
+    """The longest implicit chains (M = 511: 512 coefficients per field at
+    m = 0, eight per lane): Crank-Nicolson half step with viscosity against
+    the oracle on sampled zonal wavenumbers (each m is an independent solve)."""
+    M = 511
+    md = Model(M, 1024, 514, phibar=JET_PHIBAR)
+    pl = pint.Plan(M, 1024, 514, phibar=JET_PHIBAR, max_batch=1)
+    U = workloads.white_noise(M, jet_state(md), 1e-2, 4)
+    dt, nu, q = 300.0, 1e14, 4
+    u = to_dev(U, torch)
+    x = torch.zeros_like(u)
+    pl.implicit(pint.stepper(dt, q, nu, T_ALL), u, x, 1)
+    torch.cuda.synchronize()
+    got = from_dev(x)[0]
+    ms = (0, 1, 2, 7, 8, 63, 255, 384, 509, 510, 511)
+    ref = md.viscosity(md.cn_half(U, dt, T_ALL, ms=ms), dt, nu, q)
+    for m in ms:
+        sl = m_slice(M, m)
+        for f in range(3):
+            den = np.linalg.norm(ref[f, sl])
+            err = np.linalg.norm(got[f, sl] - ref[f, sl]) / den
+            assert den > 0 and err < 1e-12, (m, f, err)
+    pl.close()
