@@ -19,6 +19,11 @@ Y_{0,2} = sqrt(5) (3 mu^2 - 1) / 2.
   returns grid-point (Phi, xi, delta) at caller-given Gauss latitudes.  This is
   a synthetic stand-in with the shape of the unstable-jet test (Sec. 5.3), not
   its published profile.
+* ``gaussian_bumps_grid``: the Gaussian-bumps test case (Sec. 6): a fluid at
+  rest with mean depth hbar and three Gaussian height bumps of amplitude A at
+  the printed centres and widths; geopotential Phi = g (hbar + A sum_i
+  exp(-a_i d_i^2)), d_i the great-circle angle to centre i.  Grid-point
+  (Phi, xi, delta) at caller-given Gauss latitudes.
 """
 
 import math
@@ -160,3 +165,26 @@ def jet_bump_params(seed, amp=120.0):
     """Seeded bump longitude (and the given amplitude)."""
     rng = np.random.default_rng(seed)
     return dict(lam_c=float(rng.uniform(0.0, 2.0 * math.pi)), amp=float(amp))
+
+
+# centres (longitude, latitude) and sharpness a_i of the three bumps (Sec. 6)
+GAUSSIAN_BUMPS = ((math.pi / 5, math.pi / 3, 20.0),
+                  (6 * math.pi / 5, math.pi / 5, 80.0),
+                  (8 * math.pi / 5, -math.pi / 4, 360.0))
+
+
+def gaussian_bumps_grid(mu, nlon, g=G_EARTH, hbar=29400.0, amp=6000.0, bumps=GAUSSIAN_BUMPS):
+    """Grid-point (Phi, xi, delta), shape (3, nlat, nlon): Phi = g (hbar + amp
+    sum_i exp(-a_i d_i^2)), zero wind.  The mean geopotential parameter of the
+    model is g * hbar."""
+    mu = np.asarray(mu, dtype=np.float64)
+    theta = np.arcsin(mu)[:, None]
+    lam = 2.0 * np.pi * np.arange(nlon)[None, :] / nlon
+    h = np.zeros((mu.size, nlon))
+    for lam_i, th_i, a_i in bumps:
+        c = np.sin(theta) * math.sin(th_i) + np.cos(theta) * math.cos(th_i) * np.cos(lam - lam_i)
+        d = np.arccos(np.clip(c, -1.0, 1.0))
+        h += np.exp(-a_i * d * d)
+    Phi = g * (hbar + amp * h)
+    zero = np.zeros_like(Phi)
+    return np.stack([Phi, zero, zero.copy()])
