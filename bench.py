@@ -290,6 +290,144 @@ def measure(precision, steps, warmup, levels=2, coarse_grid=None):
             "prof": prof, "incr": incr, "slices": slices}
 
 
+def measure_diagnostics(slices, reps=20):
+    """Time the device diagnostics over the GROUP slice states (the states of
+    slices 1..GROUP against those of 0..GROUP-1): KE spectrum, E_{psi,R} for
+    every R, physical-space L2 errors.  Algorithmic bytes: every coefficient
+    read once (complex128)."""
+    import torch
+    from paper_2306_09497_amd import pint
+
+    plan = pint.Plan(M, NLON, NLAT, phibar=PHIBAR, max_batch=GROUP)
+    u = slices[1:].contiguous()
+    ref = slices[:-1].contiguous()
+    B = u.shape[0]
+    e = torch.zeros((B, M + 1), dtype=torch.float64, device="cuda")
+    es = torch.zeros((B, 3, M + 1), dtype=torch.float64, device="cuda")
+    calls = {
+        "ke_spectrum": (lambda: plan.ke_spectrum(u, e, B), B * 2 * plan.ncoef * 16),
+        "spectral_errors": (lambda: plan.spectral_errors(u, ref, es, B),
+                            B * 2 * 3 * plan.ncoef * 16),
+        "grid_l2_errors": (lambda: plan.grid_l2_errors(u, ref, B), None),
+    }
+    out = {}
+    for name, (fn, byts) in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            fn()
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / reps
+        out[name] = {"states": B, "ms_per_call": ms}
+        if byts is not None:
+            out[name]["gbps_algorithmic"] = byts / (ms * 1e-3) / 1e9
+            out[name]["hbm_frac"] = byts / (ms * 1e-3) / 1e9 / PEAK_HBM
+    out["grid_l2_errors"]["note"] = ("scalar synthesis of 6 fields per state (difference and "
+                                     "reference) and per-ring sums of squares; synchronises")
+    plan.close()
+    return out
+
+
+def serve_bench(seconds, rate, max_iter=2, seed=0, steps_per_tick=8, arena_gb=96.0):
+    """Serving with continuous batching: Poisson arrivals (rate per second for
+    `seconds`) of Parareal or two-level MGRIT (FCF) requests, uniform over
+    T63 192x96 / T127 384x192 / T255 768x384, 16/32/64/128 slices and 1-4 day
+    horizons; fine IMEX 45 s, coarse IMEX 675 s with q = 4 and nu fixed per
+    truncation (T63 1.6e16, T127 1e15, T255 6.2e13 m^4/s), max_iter
+    iterations each; jet + bump initial states (amplitude U[60, 160] m, seeded
+    bump longitude).  Requests are submitted at the tick after their arrival
+    time; latency = completion - arrival."""
+    import numpy as np
+    import torch
+    from paper_2306_09497_amd import pint, workloads
+
+    grids = [(63, 192, 96, 1.6e16), (127, 384, 192, 1.0e15), (255, 768, 384, 6.2e13)]
+    plans = [pint.Plan(Mg, nl, nt, phibar=PHIBAR, max_batch=GROUP) for Mg, nl, nt, _ in grids]
+    rng = np.random.default_rng(seed)
+    # a few analysed initial states per truncation, made before timing
+    init = []
+    for pl, (Mg, nl, nt, _) in zip(plans, grids):
+        mu, _ = pl.grid_coords()
+        us = []
+        for v in range(3):
+            G = workloads.jet_bump_grid(mu, nl, phibar=PHIBAR, amp=float(rng.uniform(60, 160)),
+                                        lam_c=float(rng.uniform(0, 2 * math.pi)))
+            g = torch.from_numpy(np.ascontiguousarray(G)).cuda()
+            u = torch.zeros((1, 3, pl.ncoef, 2), dtype=torch.float64, device="cuda")
+            pl.analysis(g, u, 3)
+            us.append(u)
+        init.append(us)
+    reqs = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > seconds:
+            break
+        gi = int(rng.integers(3))
+        S = int(rng.choice([16, 32, 64, 128]))
+        days = int(rng.integers(1, 5))
+        span = days * 86400.0 / S
+        fs, cs = int(round(span / 45.0)), int(round(span / 675.0))
+        if cs < 1 or abs(fs * 45.0 - span) > 1e-6 or abs(cs * 675.0 - span) > 1e-6:
+            continue                       # (every combination divides exactly)
+        method = int(rng.integers(2))
+        prm = pint.params(method, S, pint.stepper(45.0, 2, 0.0, pint.T_ALL), fs,
+                          pint.stepper(675.0, 4, grids[gi][3], pint.T_ALL), cs,
+                          nrelax=method, max_iter=max_iter)
+        reqs.append((t, gi, prm, int(rng.integers(3))))
+    srv = pint.Server(plans, int(arena_gb * 2**30), steps_per_tick=steps_per_tick,
+                      stage_states=2 * GROUP)
+    torch.cuda.synchronize()
+    ids, outs = [], []
+    t0 = srv.clock()
+    nxt, pending = 0, 1
+    while nxt < len(reqs) or pending:
+        now = srv.clock() - t0
+        while nxt < len(reqs) and reqs[nxt][0] <= now:
+            _, gi, prm, v = reqs[nxt]
+            out = torch.empty((prm.n_intervals + 1, 3, plans[gi].ncoef, 2), dtype=torch.float64,
+                              device="cuda")
+            ids.append(srv.submit(gi, prm, init[gi][v][0], out))
+            outs.append(out)
+            nxt += 1
+        pending = srv.tick()
+        if nxt < len(reqs) and not pending:
+            time.sleep(max(0.0, min(0.01, reqs[nxt][0] - (srv.clock() - t0))))
+    makespan = srv.clock() - t0
+    st = [srv.status(i) for i in ids]
+    srv.close()
+    for pl in plans:
+        pl.close()
+    lat = np.array([s.t_done - t0 - r[0] for s, r in zip(st, reqs)])
+    queue = np.array([s.t_start - t0 - r[0] for s, r in zip(st, reqs)])
+    service = np.array([s.t_done - s.t_start for s in st])
+    work = sum(s.fine_slice_steps for s in st)
+    per = {}
+    for (_, gi, _, _), l in zip(reqs, lat):
+        per.setdefault(grids[gi][0], []).append(l)
+    return {
+        "metric": "served fine slice-steps/s (continuous batching)",
+        "value": work / makespan, "unit": "slice-steps/s", "n_gpus": 1,
+        "requests": len(reqs), "completed": sum(s.state == pint.REQ_DONE for s in st),
+        "arrival_window_s": seconds, "rate_per_s": rate, "makespan_s": makespan,
+        "offered_fine_slice_steps_per_s": work / seconds,
+        "achieved_fine_slice_steps_per_s": work / makespan,
+        "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "queue_mean_s": float(queue.mean()), "service_mean_s": float(service.mean()),
+        "latency_p50_by_truncation_s": {f"T{k}": float(np.percentile(v, 50))
+                                        for k, v in sorted(per.items())},
+        "config": {"workload": "Poisson arrivals, uniform T63/T127/T255, S in {16,32,64,128}, "
+                               "1-4 days, fine 45 s, coarse 675 s, Parareal or MGRIT FCF, "
+                               f"{max_iter} iterations", "steps_per_tick": steps_per_tick},
+        "data": "synthetic", "dtype": "f64",
+    }
+
+
 def field_errors(a, b):
     """Per-field relative L2 difference (Phi', xi, delta) of two (N, 3, ncoef, 2)
     device tensors over all slices."""
@@ -321,12 +459,18 @@ def main():
                     help="skip the three-level MGRIT side measurement of the default run")
     ap.add_argument("--time-to-tol", action="store_true",
                     help="print the T127 Parareal time-to-tolerance measurement instead")
+    ap.add_argument("--serve", type=float, nargs=2, metavar=("SECONDS", "RATE"),
+                    help="print the continuous-batching serving measurement instead "
+                         "(Poisson arrivals at RATE per second for SECONDS)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the whole PinT problem on a "
               "single MI355X (time slices are the batch dimension); --gpus must be 1.",
               file=sys.stderr)
         return 2
+    if args.serve:
+        print(json.dumps(serve_bench(args.serve[0], args.serve[1])), flush=True)
+        return 0
     if args.time_to_tol:
         print(json.dumps({"metric": "PinT time-to-tol vs serial fine", **time_to_tol()}),
               flush=True)
@@ -454,6 +598,11 @@ def main():
             }
         except Exception as e:
             out["mgrit3_coarse_t127"] = {"error": str(e)}
+    if prec == pint.FP64:
+        try:
+            out["diagnostics"] = measure_diagnostics(res["slices"])
+        except Exception as e:                      # reported, not fatal
+            out["diagnostics"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

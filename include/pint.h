@@ -227,6 +227,97 @@ pint_status pint_solve(pint_plan* plan, const pint_pint_params* p, const double*
 pint_status pint_rel_diff(pint_plan* plan, const double* a, const double* c, double* out_host,
                           int B, void* stream);
 
+/* Kinetic-energy spectrum of a triangular truncation (Sec. 6, Gaussian bumps
+ * test case, after Koshyk and Hamilton): for each of B states
+ *   e[b][n] = a^2 / (4 n (n+1)) * sum_{m=-n..n} (|xi_{m,n}|^2 + |delta_{m,n}|^2),
+ * n = 0..M, e[b][0] = 0; the m < 0 coefficients of a real field are the
+ * conjugates of the stored m > 0 ones.  u: device [B][3][ncoef][2]; e: device
+ * [B][M+1].  Asynchronous on `stream`.  */
+pint_status pint_ke_spectrum(pint_plan* plan, const double* u, double* e, int B, void* stream);
+
+/* Spectral max-norm errors (Sec. 5, eq. error_definition) of B states u
+ * against B references ref, for psi = Phi' (Phi - phibar), xi, delta and
+ * every resolution R = 0..M at once:
+ *   e[b][f][R] = max_{0<=m<=n<=R} |u - ref| / max_{0<=m<=n<=R} |ref|,
+ * 0 where difference and reference are both zero, +inf for a nonzero
+ * difference on a zero reference.  u, ref: device [B][3][ncoef][2]; e: device
+ * [B][3][M+1].  Needs M <= 511 (PINT_E_INVAL otherwise).  Asynchronous.  */
+pint_status pint_spectral_errors(pint_plan* plan, const double* u, const double* ref, double* e,
+                                 int B, void* stream);
+
+/* Physical-space relative L2 errors (Sec. 5, the equation after
+ * error_definition): for psi = Phi' (Phi - phibar), xi, delta,
+ *   out[b][f] = sqrt( sum_nodes (psi - psi_ref)^2 / sum_nodes psi_ref^2 ),
+ * the unweighted sums over the nodes of the plan's Gauss grid (the grid
+ * means of the printed formula, whose 1/(nlat nlon) cancels); 0 / 0 gives 0
+ * and x / 0 gives +inf.  u, ref: device [B][3][ncoef][2]; out: HOST [B][3].
+ * Uses the plan's transform workspace (do not overlap with other calls on
+ * the plan); synchronises `stream`.  */
+pint_status pint_grid_l2_errors(pint_plan* plan, const double* u, const double* ref,
+                                double* out_host, int B, void* stream);
+
+/* ---- Serving with continuous batching ------------------------------------
+ * A server runs many Parareal / two-level MGRIT solves (Sec. 3, the
+ * iteration of pint_solve) at once on one stream.  Each tick advances every
+ * running request's pending propagation by one chunk of at most
+ * steps_per_tick IMEX steps, and all chunks of one plan with the same
+ * stepper and length run as one batched propagation: fine propagations of
+ * different requests share launches, and so do the serial coarse sweeps of
+ * different requests.  A request's chunks depend only on its own step
+ * counts and the propagator is batch invariant, so its result is bitwise
+ * the same alone and in any mix.  Request state (4 n_intervals + 3 states)
+ * lives in a device arena of arena_bytes allocated at creation; requests are
+ * admitted first in first out when their state fits, and nothing is
+ * allocated while serving.  The plans are borrowed: they must outlive the
+ * server and must not be used by other calls while it runs.  Not thread
+ * safe.  Errors as for the other entry points; a request larger than the
+ * arena is refused at submission with PINT_E_NOMEM.  */
+typedef struct pint_server pint_server;
+
+typedef struct {
+  int n_plans;               /* plans (truncations) requests may use          */
+  pint_plan* const* plans;   /* [n_plans], borrowed                           */
+  size_t arena_bytes;        /* device bytes for request state                */
+  int steps_per_tick;        /* >= 1: IMEX steps per chunk                    */
+  int stage_states;          /* >= 1: per-plan staging buffer (states) for
+                                merged launches                               */
+} pint_server_config;
+
+typedef struct {
+  int plan;                  /* index into pint_server_config.plans           */
+  pint_pint_params params;   /* method 0 or 1, levels 2, no coarse_plan,
+                                resume 0                                       */
+  const double* u0;          /* device [3][ncoef][2]; read at admission, so it
+                                must stay valid until the request runs        */
+  double* u_slices;          /* device [(n_intervals+1)][3][ncoef][2], written
+                                when the request completes                    */
+} pint_request;
+
+enum { PINT_REQ_QUEUED = 0, PINT_REQ_RUNNING = 1, PINT_REQ_DONE = 2, PINT_REQ_FAILED = 3 };
+
+typedef struct {
+  int state;                 /* PINT_REQ_*                                    */
+  int status;                /* PINT_OK, PINT_E_NOTCONV (tol not reached: the
+                                result is still written), PINT_E_DIVERGED
+                                (state FAILED)                                 */
+  int iters;                 /* iterations performed                          */
+  double incr;               /* last stopping increment (as pint_report)      */
+  double t_submit, t_start, t_done;  /* seconds on the server clock           */
+  long long fine_slice_steps, coarse_steps;
+} pint_request_status;
+
+pint_status pint_server_create(const pint_server_config* cfg, void* stream, pint_server** out);
+pint_status pint_server_destroy(pint_server* server);
+/* Queue a request (validated as pint_solve's parameters); *id identifies it. */
+pint_status pint_server_submit(pint_server* server, const pint_request* req, long long* id);
+/* Admit what fits, advance every running request by one chunk, finish what
+ * completed; *pending = requests queued or running afterwards.  Synchronises
+ * the stream once (and once per completed iteration, for the increments). */
+pint_status pint_server_tick(pint_server* server, int* pending);
+pint_status pint_server_status(pint_server* server, long long id, pint_request_status* st);
+/* Seconds since the server was created (the clock of the time stamps). */
+pint_status pint_server_clock(pint_server* server, double* t);
+
 /* Kernel timing for measurement.  While enabled, every kernel launch of the
  * plan whose kind is in kind_mask (bit 1 << kind) and that processes at least
  * min_batch states is bracketed by HIP events on its stream (kind_mask = 0

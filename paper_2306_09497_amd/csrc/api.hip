@@ -7,13 +7,7 @@
 
 namespace pint {
 
-#define PINT_TRY(x)                  \
-  do {                               \
-    pint_status st_ = (x);           \
-    if (st_ != PINT_OK) return st_;  \
-  } while (0)
-
-static pint_status check_stepper(const Plan& p, const pint_stepper* st) {
+pint_status check_stepper(const Plan& p, const pint_stepper* st) {
   if (!st) {
     set_error("null stepper");
     return PINT_E_INVAL;
@@ -105,7 +99,7 @@ static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-static pint_status check_params(const Plan& p, const pint_pint_params* q) {
+pint_status check_params(const Plan& p, const pint_pint_params* q) {
   if (!q) {
     set_error("null params");
     return PINT_E_INVAL;
@@ -581,6 +575,31 @@ pint_status pint_rel_diff(pint_plan* plan, const double* a, const double* c, dou
     return PINT_E_INVAL;
   }
   return rel_diff(plan->p, a, c, out_host, B, (hipStream_t)stream);
+}
+
+pint_status pint_ke_spectrum(pint_plan* plan, const double* u, double* e, int B, void* stream) {
+  API_GUARD(plan);
+  PINT_TRY(check_batch(B, u, e));
+  return ke_spectrum(plan->p, u, e, B, (hipStream_t)stream);
+}
+
+pint_status pint_spectral_errors(pint_plan* plan, const double* u, const double* ref, double* e,
+                                 int B, void* stream) {
+  API_GUARD(plan);
+  PINT_TRY(check_batch(B, u, ref));
+  PINT_TRY(check_batch(B, u, e));
+  return spectral_errors(plan->p, u, ref, e, B, (hipStream_t)stream);
+}
+
+pint_status pint_grid_l2_errors(pint_plan* plan, const double* u, const double* ref,
+                                double* out_host, int B, void* stream) {
+  API_GUARD(plan);
+  PINT_TRY(check_batch(B, u, ref));
+  if (!out_host && B > 0) {
+    set_error("null output");
+    return PINT_E_INVAL;
+  }
+  return grid_l2_errors(plan->p, u, ref, out_host, B, (hipStream_t)stream);
 }
 
 pint_status pint_profile_enable(pint_plan* plan, unsigned kind_mask, int min_batch) {

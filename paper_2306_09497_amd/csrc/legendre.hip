@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int wave = tid >> 6, lane = tid & 63;
   const int wr = (wave / WC) * (TR / WR), wc = (wave % WC) * (TC / WC);
   const int li = lane & 15, lk = lane >> 4;
-  const size_t gbase = (size_t)m * nlat;
+  const size_t gbase = (size_t)m * fourier_pitch<E>(nlat, ncol);
 
   typename MM::acc_t acc[2][BI][BJ];
 #pragma unroll
@@ -173,8 +173,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int r = row0 + wr + bi * 16 + MM::row(lk, i);
         if (r < nlat2 && c < ncol) {
           const E e = acc[0][bi][bj][i], o = acc[1][bi][bj][i];
-          F[(gbase + r) * ncol + c] = e + o;
-          F[(gbase + (nlat - 1 - r)) * ncol + c] = e - o;
+          F[gbase + (size_t)r * ncol + c] = e + o;
+          F[gbase + (size_t)(nlat - 1 - r) * ncol + c] = e - o;
         }
       }
     }
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int wr = (wave / WC) * (TR / WR), wc = (wave % WC) * (TC / WC);
   const int par = wr >= TR2;                         // uniform per wave
   const int li = lane & 15, lk = lane >> 4;
-  const size_t gbase = (size_t)m * nlat;
+  const size_t gbase = (size_t)m * fourier_pitch<E>(nlat, ncol);
 
   typename MM::acc_t acc[BI][BJ];
 #pragma unroll
@@ -247,8 +247,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       const int k = k0 + kk, c = col0 + cc;
       E ve = E(0), vo = E(0);
       if (k < nlat2 && c < ncol) {
-        const E gn = G[(gbase + k) * ncol + c];
-        const E gs = G[(gbase + (nlat - 1 - k)) * ncol + c];
+        const E gn = G[gbase + (size_t)k * ncol + c];
+        const E gs = G[gbase + (size_t)(nlat - 1 - k) * ncol + c];
         ve = gn + gs;
         vo = gn + E(-1) * gs;
       }
@@ -368,7 +368,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int wave = tid >> 6, lane = tid & 63;
   const int wr = (wave / WC) * (TR / WR), wc = (wave % WC) * (TC / WC);
   const int li = lane & 15, lk = lane >> 4;
-  const size_t gbase = (size_t)m * nlat;
+  const size_t gbase = (size_t)m * fourier_pitch<float>(nlat, ncol);
 
   v4f acc[2][BI][BJ];
 #pragma unroll
@@ -466,8 +466,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int r = row0 + wr + bi * 16 + 4 * lk + i;
         if (r < nlat2 && c < ncol) {
           const float e = acc[0][bi][bj][i], o = acc[1][bi][bj][i];
-          F[(gbase + r) * ncol + c] = e + o;
-          F[(gbase + (nlat - 1 - r)) * ncol + c] = e - o;
+          F[gbase + (size_t)r * ncol + c] = e + o;
+          F[gbase + (size_t)(nlat - 1 - r) * ncol + c] = e - o;
         }
       }
     }
@@ -505,7 +505,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int wr = (wave / WC) * (TR / WR), wc = (wave % WC) * (TC / WC);
   const int par = wr >= TR2;                         // uniform per wave
   const int li = lane & 15, lk = lane >> 4;
-  const size_t gbase = (size_t)m * nlat;
+  const size_t gbase = (size_t)m * fourier_pitch<float>(nlat, ncol);
 
   v4f acc[BI][BJ];
 #pragma unroll
@@ -534,8 +534,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int k = k0 + 8 * rb_g + e;
         float ve = 0.0f, vo = 0.0f;
         if (k < nlat2 && c < ncol) {
-          const float gn = G[(gbase + k) * ncol + c];
-          const float gs = G[(gbase + (nlat - 1 - k)) * ncol + c];
+          const float gn = G[gbase + (size_t)k * ncol + c];
+          const float gs = G[gbase + (size_t)(nlat - 1 - k) * ncol + c];
           ve = gn + gs;
           vo = gn - gs;
         }

@@ -49,6 +49,13 @@ void set_error(const char* fmt, ...);
     }                                                                         \
   } while (0)
 
+// Return the status of a library call that failed.
+#define PINT_TRY(x)                  \
+  do {                               \
+    pint_status st_ = (x);           \
+    if (st_ != PINT_OK) return st_;  \
+  } while (0)
+
 // LU factors of the two tridiagonal chains of (I - dt/4 L) per m, for one
 // (dt, terms), as the coefficients of the two first-order recurrences
 //   y_i = alph_i y_{i-1} + invpiv_i r_i,   x_i = gam_i x_{i+1} + y_i
@@ -113,6 +120,7 @@ struct Plan {
   hipEvent_t join_ev = nullptr;      // end of a sweep on side_stream
   int sweep_chunks = 4;
   double* red = nullptr;       // reduction scratch
+  double* diag = nullptr;      // L2-error partial sums [3 max_batch][nlat][2]
   double* h_red = nullptr;     // pinned host mirror
   size_t ws_bytes = 0;
   std::map<std::pair<double, unsigned>, CnFactors> cn_cache;
@@ -188,6 +196,9 @@ pint_status sp_tend(Plan& p, double* out, int B, hipStream_t s);
 pint_status sp_cn(Plan& p, const CnFactors& f, const pint_stepper& st0, const pint_stepper* st1,
                   const double* in, double* out, int B, hipStream_t s);
 // nsteps IMEX steps of B <= max_batch public-layout states (out may alias in)
+// argument checks of the public entry points (PINT_E_INVAL with a message)
+pint_status check_stepper(const Plan& p, const pint_stepper* st);
+pint_status check_params(const Plan& p, const pint_pint_params* q);
 pint_status imex_steps(Plan& p, const pint_stepper& st, const double* in, double* out, int B,
                        int nsteps, hipStream_t s);
 
@@ -212,8 +223,31 @@ pint_status pr_update(Plan& p, const double* gnew, const double* gold, const dou
 pint_status rel_diff(Plan& p, const double* a, const double* c, double* out_host, int B,
                      hipStream_t s);
 
+// diagnostics (Sec. 5, Sec. 6): KE spectrum [B][M+1] and spectral max-norm
+// errors [B][3][M+1] on the device, physical-space L2 errors [B][3] to the host
+pint_status ke_spectrum(Plan& p, const double* u, double* e, int B, hipStream_t s);
+pint_status spectral_errors(Plan& p, const double* u, const double* ref, double* e, int B,
+                            hipStream_t s);
+pint_status grid_l2_errors(Plan& p, const double* u, const double* ref, double* out_host, int B,
+                           hipStream_t s);
+// sums of squares over each ring of nspec / 2 synthesised pairs held in F:
+// part[pair][latitude][2]
+pint_status ring_sumsq(Plan& p, int nspec, double* part, hipStream_t s);
+
 inline __host__ __device__ int coef_idx(int M, int m, int n) {
   return m * (2 * M + 3 - m) / 2 + (n - m);
+}
+
+// Pitch, in elements of type E, between the rows of wavenumbers m and m + 1
+// of the Fourier arrays F[m][latitude][column] and G (ncol columns per
+// latitude).  nlat * ncol alone is a multiple of 256 KiB at batched sizes
+// (T255, 64 states: 9 x 256 KiB), which puts every wavenumber row that one
+// ring reads at the same L2 set and channel; 256 bytes of padding spread
+// them over the channels.
+constexpr int kFourierPadBytes = 256;
+template <typename E>
+__host__ __device__ inline size_t fourier_pitch(int nlat, int ncol) {
+  return (size_t)nlat * ncol + kFourierPadBytes / sizeof(E);
 }
 
 // ---- small device helpers shared by the kernels ----

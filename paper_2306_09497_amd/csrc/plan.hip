@@ -151,16 +151,10 @@ static pint_status dalloc(T** ptr, size_t count, size_t* total) {
   return PINT_OK;
 }
 
-#define PINT_TRY(x)                  \
-  do {                               \
-    pint_status st_ = (x);           \
-    if (st_ != PINT_OK) return st_;  \
-  } while (0)
-
 static void free_plan(Plan& p) {
   void* ptrs[] = {p.mu, p.w, p.c2, p.ptab, p.ptabT, p.ptab32, p.ptabT32, p.twid32,
                   p.rowoff, p.rowinfo, p.coefmn, p.twid, p.cnco, p.syn_tiles.dev,
-                  p.ana_tiles.dev, p.S, p.F, p.G, p.Q, p.Ua, p.N1, p.red,
+                  p.ana_tiles.dev, p.S, p.F, p.G, p.Q, p.Ua, p.N1, p.red, p.diag,
                   p.side.S, p.side.F, p.side.G, p.side.Q, p.side.Ua, p.side.N1};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -317,19 +311,20 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
   PLAN_TRY(build_tiles(p.h_rowoff, M, p.nlat2, false, kGemmTRAnal, &p.ana_tiles, &tot));
   const size_t B = p.max_batch;
   PLAN_TRY(dalloc(&p.S, (size_t)p.nrows * 12 * B, &tot));
-  PLAN_TRY(dalloc(&p.F, (size_t)2 * (M + 1) * p.nlat2 * 12 * B, &tot));
-  PLAN_TRY(dalloc(&p.G, (size_t)(M + 1) * nlat * 8 * B, &tot));
+  PLAN_TRY(dalloc(&p.F, (M + 1) * fourier_pitch<double>(nlat, 12 * B), &tot));
+  PLAN_TRY(dalloc(&p.G, (M + 1) * fourier_pitch<double>(nlat, 8 * B), &tot));
   PLAN_TRY(dalloc(&p.Q, (size_t)p.nrows * 8 * B, &tot));
   const size_t sw = (size_t)p.ncoef * B * 3 * 2;
   PLAN_TRY(dalloc(&p.Ua, sw, &tot));
   PLAN_TRY(dalloc(&p.N1, sw, &tot));
   PLAN_TRY(dalloc(&p.side.S, (size_t)p.nrows * 12, &tot));
-  PLAN_TRY(dalloc(&p.side.F, (size_t)2 * (M + 1) * p.nlat2 * 12, &tot));
-  PLAN_TRY(dalloc(&p.side.G, (size_t)(M + 1) * nlat * 8, &tot));
+  PLAN_TRY(dalloc(&p.side.F, (M + 1) * fourier_pitch<double>(nlat, 12), &tot));
+  PLAN_TRY(dalloc(&p.side.G, (M + 1) * fourier_pitch<double>(nlat, 8), &tot));
   PLAN_TRY(dalloc(&p.side.Q, (size_t)p.nrows * 8, &tot));
   PLAN_TRY(dalloc(&p.side.Ua, (size_t)p.ncoef * 3 * 2, &tot));
   PLAN_TRY(dalloc(&p.side.N1, (size_t)p.ncoef * 3 * 2, &tot));
   PLAN_TRY(dalloc(&p.red, (size_t)8 * B + 64, &tot));
+  PLAN_TRY(dalloc(&p.diag, (size_t)6 * B * nlat, &tot));
   if (hipHostMalloc((void**)&p.h_red, (8 * B + 64) * sizeof(double), 0) != hipSuccess) {
     free_plan(p);
     delete pp;

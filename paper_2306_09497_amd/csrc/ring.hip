@@ -586,7 +586,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
   // Fourier coefficients of this ring: record (m, j, b) holds the six
   // synthesised fields contiguously
   const T* frow = F + (size_t)j * ncs + b * 12;
-  const size_t fstride = (size_t)nlat * ncs;         // between m and m + 1
+  const size_t fstride = fourier_pitch<T>(nlat, ncs);   // between m and m + 1
   // Stage NS fields' coefficients in LDS, slot s at point m for m <= M.
   // Lanes run over the fields of a record (a few cache lines per wave
   // access); a thread's loads are all issued before its first LDS store.
@@ -754,7 +754,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
   // results (N_Phi, K, A, B) = slots (0, 3, 1, 2) to G, lanes over the four
   // fields of a record
   T* grow = Gout + (size_t)j * ncg + b * 8;
-  const size_t gstride = (size_t)nlat * ncg;
+  const size_t gstride = fourier_pitch<T>(nlat, ncg);
   for (int it = tid; it < (M + 1) * 4; it += NT) {
     const int m = it >> 2, f = it & 3;
     const int sl = f == 0 ? 0 : (f == 1 ? 3 : f - 1);
@@ -767,7 +767,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
 // synthesis: Fourier rows F[m][j][b] (nf = 1) -> grid[b][j][k]
 // analysis:  grid[b][j][k] -> G[m][j][b*2] scaled by w_j / nlon
 // ---------------------------------------------------------------------------
-template <int N>
+// SQ: instead of storing the grid, sum the squares of the pair over the
+// ring into grid[pair][latitude][2] (physical-space L2 norms).
+template <int N, bool SQ>
 __global__ __launch_bounds__(kRingThreads) void k_ring_synth(const double* __restrict__ F,
                                                              double* __restrict__ grid,
                                                              const double2* __restrict__ tw,
@@ -780,7 +782,8 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_synth(const double* __res
   const bool two = b0 + 1 < B;
   const int ncs = 2 * B;
   auto fourier = [&](int m, double2* x, double2* y) {
-    const double2* f = reinterpret_cast<const double2*>(F + ((size_t)m * nlat + j) * ncs);
+    const double2* f = reinterpret_cast<const double2*>(F + m * fourier_pitch<double>(nlat, ncs) +
+                                                        (size_t)j * ncs);
     *x = f[b0];
     *y = two ? f[b0 + 1] : make_double2(0.0, 0.0);
   };
@@ -803,10 +806,27 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_synth(const double* __res
   __syncthreads();
   fft_lds<N, 1>(zb, 1.0, tw, threadIdx.x);
   const double isc = 1.0 / sc;
-  for (int k = threadIdx.x; k < nlon; k += kRingThreads) {
-    const double2 z = zb[L::at(0, k)];
-    grid[((size_t)b0 * nlat + j) * nlon + k] = z.x;
-    if (two) grid[((size_t)(b0 + 1) * nlat + j) * nlon + k] = z.y * isc;
+  if constexpr (SQ) {
+    double acc[2] = {0.0, 0.0};
+    for (int k = threadIdx.x; k < nlon; k += kRingThreads) {
+      const double2 z = zb[L::at(0, k)];
+      const double y = z.y * isc;
+      acc[0] += z.x * z.x;
+      acc[1] += y * y;
+    }
+    block_sum<2>(acc, red, threadIdx.x);
+    // a signal whose Fourier coefficients on this ring are all zero is zero
+    // on the ring: drop the rounding its partner leaks into it
+    if (threadIdx.x == 0) {
+      grid[((size_t)blockIdx.y * nlat + j) * 2] = nrm[0] > 0.0 ? acc[0] : 0.0;
+      grid[((size_t)blockIdx.y * nlat + j) * 2 + 1] = two && nrm[1] > 0.0 ? acc[1] : 0.0;
+    }
+  } else {
+    for (int k = threadIdx.x; k < nlon; k += kRingThreads) {
+      const double2 z = zb[L::at(0, k)];
+      grid[((size_t)b0 * nlat + j) * nlon + k] = z.x;
+      if (two) grid[((size_t)(b0 + 1) * nlat + j) * nlon + k] = z.y * isc;
+    }
   }
 }
 
@@ -844,7 +864,8 @@ __global__ __launch_bounds__(kRingThreads) void k_ring_anal(const double* __rest
   for (int m = threadIdx.x; m <= M; m += kRingThreads) {
     double2 X, Y;
     get_pair<N>(zb, 0, m, &X, &Y);
-    double2* g = reinterpret_cast<double2*>(Gout + ((size_t)m * nlat + j) * ncg);
+    double2* g = reinterpret_cast<double2*>(Gout + m * fourier_pitch<double>(nlat, ncg) +
+                                              (size_t)j * ncg);
     g[b0] = X;
     if (two) g[b0 + 1] = c_scl(Y, is);
   }
@@ -951,7 +972,7 @@ pint_status scalar_synthesis(Plan& p, const double* spec, double* grid, int B, h
       switch (p.nlon) {
 #define PINT_CASE(n)                                                                             \
   case n:                                                                                        \
-    hipLaunchKernelGGL(k_ring_synth<n>, dim3(p.nlat, (nb + 1) / 2), dim3(kRingThreads),          \
+    hipLaunchKernelGGL((k_ring_synth<n, false>), dim3(p.nlat, (nb + 1) / 2), dim3(kRingThreads), \
                        (size_t)RingLds<n>::SP * sizeof(double2), s, p.F, gout, p.twid, p.M,      \
                        p.nlat, p.nlat2, nb);                                                     \
     break;
@@ -964,6 +985,25 @@ pint_status scalar_synthesis(Plan& p, const double* spec, double* grid, int B, h
       PINT_HIP(hipGetLastError());
     }
   }
+  return PINT_OK;
+}
+
+pint_status ring_sumsq(Plan& p, int nspec, double* part, hipStream_t s) {
+  ProfScope ps(p, PK_SRING, nspec, s);
+  switch (p.nlon) {
+#define PINT_CASE(n)                                                                             \
+  case n:                                                                                        \
+    hipLaunchKernelGGL((k_ring_synth<n, true>), dim3(p.nlat, (nspec + 1) / 2),                   \
+                       dim3(kRingThreads), (size_t)RingLds<n>::SP * sizeof(double2), s, p.F,     \
+                       part, p.twid, p.M, p.nlat, p.nlat2, nspec);                               \
+    break;
+    PINT_FOR_EACH_NLON(PINT_CASE)
+#undef PINT_CASE
+    default:
+      set_error("no ring FFT for nlon=%d", p.nlon);
+      return PINT_E_INVAL;
+  }
+  PINT_HIP(hipGetLastError());
   return PINT_OK;
 }
 

@@ -24,8 +24,12 @@ STATUS = {0: "PINT_OK", -1: "PINT_E_INVAL", -2: "PINT_E_NOMEM", -3: "PINT_E_HIP"
 
 EXPORTS = ["pint_plan_create", "pint_plan_destroy", "pint_plan_info", "pint_grid_coords",
            "pint_synthesis", "pint_analysis", "pint_tendency", "pint_implicit", "pint_step",
-           "pint_solve", "pint_rel_diff", "pint_profile_enable", "pint_profile_read",
-           "pint_last_error"]
+           "pint_solve", "pint_rel_diff", "pint_ke_spectrum", "pint_spectral_errors",
+           "pint_grid_l2_errors", "pint_server_create", "pint_server_destroy",
+           "pint_server_submit", "pint_server_tick", "pint_server_status", "pint_server_clock",
+           "pint_profile_enable", "pint_profile_read", "pint_last_error"]
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
 PROF_KINDS = ["prep", "legendre_synth", "ring_tendency", "legendre_anal", "assemble_rk",
               "cn_solve", "layout", "pint_ops", "scalar_ring"]
@@ -62,6 +66,24 @@ class PintParams(ctypes.Structure):
 class ProfEntry(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("batch", ctypes.c_int),
                 ("launches", ctypes.c_longlong), ("total_ms", ctypes.c_double)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("n_plans", ctypes.c_int), ("plans", ctypes.POINTER(ctypes.c_void_p)),
+                ("arena_bytes", ctypes.c_size_t), ("steps_per_tick", ctypes.c_int),
+                ("stage_states", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_int), ("params", PintParams), ("u0", ctypes.c_void_p),
+                ("u_slices", ctypes.c_void_p)]
+
+
+class RequestStatus(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int), ("status", ctypes.c_int), ("iters", ctypes.c_int),
+                ("incr", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("fine_slice_steps", ctypes.c_longlong), ("coarse_steps", ctypes.c_longlong)]
 
 
 class Report(ctypes.Structure):
@@ -102,6 +124,16 @@ def load(path=LIB_PATH):
     lib.pint_step.argtypes = [vp, ctypes.POINTER(Stepper), vp, vp, ip, ip, vp]
     lib.pint_solve.argtypes = [vp, ctypes.POINTER(PintParams), vp, vp, ctypes.POINTER(Report), vp]
     lib.pint_rel_diff.argtypes = [vp, vp, vp, dp, ip, vp]
+    lib.pint_ke_spectrum.argtypes = [vp, vp, vp, ip, vp]
+    lib.pint_spectral_errors.argtypes = [vp, vp, vp, vp, ip, vp]
+    lib.pint_grid_l2_errors.argtypes = [vp, vp, vp, dp, ip, vp]
+    lib.pint_server_create.argtypes = [ctypes.POINTER(ServerConfig), vp, ctypes.POINTER(vp)]
+    lib.pint_server_destroy.argtypes = [vp]
+    lib.pint_server_submit.argtypes = [vp, ctypes.POINTER(Request),
+                                       ctypes.POINTER(ctypes.c_longlong)]
+    lib.pint_server_tick.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    lib.pint_server_status.argtypes = [vp, ctypes.c_longlong, ctypes.POINTER(RequestStatus)]
+    lib.pint_server_clock.argtypes = [vp, dp]
     lib.pint_profile_enable.argtypes = [vp, ctypes.c_uint, ip]
     lib.pint_profile_read.argtypes = [vp, ctypes.POINTER(ProfEntry), ip,
                                       ctypes.POINTER(ctypes.c_int), vp]
@@ -243,6 +275,25 @@ class Plan:
                                     _stream(stream)))
         return out
 
+    # ---- diagnostics (Sec. 5, Sec. 6) ---------------------------------
+    def ke_spectrum(self, u, e, B, stream=None):
+        """e (device [B][M+1]) <- kinetic-energy spectrum of the B states u."""
+        _check(load().pint_ke_spectrum(self._h, _ptr(u), _ptr(e), int(B), _stream(stream)))
+
+    def spectral_errors(self, u, ref, e, B, stream=None):
+        """e (device [B][3][M+1]) <- E_{psi,R} of (Phi', xi, delta), R = 0..M."""
+        _check(load().pint_spectral_errors(self._h, _ptr(u), _ptr(ref), _ptr(e), int(B),
+                                           _stream(stream)))
+
+    def grid_l2_errors(self, u, ref, B, stream=None):
+        """Host [B][3] physical-space relative L2 errors of (Phi', xi, delta)."""
+        import numpy as np
+        out = np.zeros((B, 3))
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(load().pint_grid_l2_errors(self._h, _ptr(u), _ptr(ref), out.ctypes.data_as(dp),
+                                          int(B), _stream(stream)))
+        return out
+
 
 def params(method, n_intervals, fine, fine_steps, coarse, coarse_steps, nrelax=0, max_iter=1,
            tol=0.0, resume=False, levels=2, cfactor1=0, coarse2=None, coarse2_steps=1,
@@ -254,3 +305,62 @@ def params(method, n_intervals, fine, fine_steps, coarse, coarse_steps, nrelax=0
     return PintParams(int(method), int(n_intervals), fine, int(fine_steps), coarse,
                       int(coarse_steps), int(nrelax), int(max_iter), float(tol), int(resume),
                       int(levels), int(cfactor1), c2, int(coarse2_steps), int(cycles1), cp)
+
+
+class Server:
+    """Continuous-batching server over borrowed plans (see pint_server_create).
+
+    submit() queues a solve and returns its id; tick() runs one scheduling
+    step and returns the number of requests still queued or running."""
+
+    def __init__(self, plans, arena_bytes, steps_per_tick=8, stage_states=64, stream=None):
+        lib = load()
+        self._plans = list(plans)           # keep the plans alive
+        arr = (ctypes.c_void_p * len(self._plans))(*[p._h.value for p in self._plans])
+        self._arr = arr
+        cfg = ServerConfig(len(self._plans), ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)),
+                           int(arena_bytes), int(steps_per_tick), int(stage_states))
+        h = ctypes.c_void_p()
+        _check(lib.pint_server_create(ctypes.byref(cfg), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pint_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, plan_index, params, u0, u_slices):
+        req = Request(int(plan_index), params, _ptr(u0), _ptr(u_slices))
+        rid = ctypes.c_longlong()
+        _check(load().pint_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)))
+        self._keep[rid.value] = (u0, u_slices)      # device buffers outlive the request
+        return rid.value
+
+    def tick(self):
+        n = ctypes.c_int()
+        _check(load().pint_server_tick(self._h, ctypes.byref(n)))
+        return n.value
+
+    def status(self, rid):
+        st = RequestStatus()
+        _check(load().pint_server_status(self._h, int(rid), ctypes.byref(st)))
+        return st
+
+    def clock(self):
+        t = ctypes.c_double()
+        _check(load().pint_server_clock(self._h, ctypes.byref(t)))
+        return t.value
+
+    def run(self, max_ticks=1 << 30):
+        """Tick until nothing is queued or running; returns the tick count."""
+        for i in range(max_ticks):
+            if self.tick() == 0:
+                return i + 1
+        raise RuntimeError("server did not drain")

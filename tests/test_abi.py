@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def header_functions():
     text = open(os.path.join(ROOT, "include", "pint.h")).read()
-    return sorted(set(re.findall(r"\b(pint_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(pint_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_binding_exports():
@@ -50,3 +50,26 @@ def test_null_arguments():
     assert lib.pint_plan_destroy(None) == -1
     assert b"null plan" in lib.pint_last_error()
     assert lib.pint_plan_create(None, None, None) == -1
+
+
+def test_server_and_diagnostics_argument_checks():
+    """Entry points added for serving and diagnostics refuse bad arguments
+    before touching a device."""
+    from paper_2306_09497_amd import pint
+    lib = pint.load()
+    h = ctypes.c_void_p()
+    assert lib.pint_server_create(None, None, ctypes.byref(h)) == -1
+    cfg = pint.ServerConfig(0, None, 1 << 20, 1, 1)
+    assert lib.pint_server_create(ctypes.byref(cfg), None, ctypes.byref(h)) == -1
+    assert b"n_plans >= 1" in lib.pint_last_error()
+    arr = (ctypes.c_void_p * 1)(None)
+    cfg = pint.ServerConfig(1, ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)), 1 << 20, 1, 1)
+    assert lib.pint_server_create(ctypes.byref(cfg), None, ctypes.byref(h)) == -1
+    assert b"plan 0 is null" in lib.pint_last_error()
+    assert lib.pint_server_destroy(None) == -1
+    assert lib.pint_server_tick(None, None) == -1
+    st = pint.RequestStatus()
+    assert lib.pint_server_status(None, 1, ctypes.byref(st)) == -1
+    assert lib.pint_ke_spectrum(None, None, None, 1, None) == -1
+    assert lib.pint_spectral_errors(None, None, None, None, 1, None) == -1
+    assert lib.pint_grid_l2_errors(None, None, None, None, 1, None) == -1

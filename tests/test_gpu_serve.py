@@ -1,0 +1,153 @@
+"""GPU tests of the continuous-batching server (NEXT-1): a request served
+alone equals pint_solve bitwise; every request's result is bitwise the same
+alone and in a mix (merged fine launches and merged coarse sweeps);
+admission by arena footprint; argument checks; parity with the oracle."""
+
+import numpy as np
+import pytest
+
+from gpu_util import assert_parity, from_dev, to_dev
+from oracle import pint as opint
+from oracle.swe import Model, T_ALL
+from paper_2306_09497_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2306_09497_amd import pint  # noqa: E402
+
+PHIBAR = 2.94e4
+GRIDS = [(21, 64, 32), (42, 128, 64)]
+
+
+@pytest.fixture(scope="module")
+def plans():
+    return [pint.Plan(M, nlon, nlat, phibar=PHIBAR, max_batch=8) for M, nlon, nlat in GRIDS]
+
+
+def state_bytes(pl):
+    return 3 * pl.ncoef * 2 * 8
+
+
+def request(pi, method, N, fdt, fs, cs, k, nrelax=0, tol=0.0, seed=0):
+    """Plan index, params and initial state of one solve."""
+    f = pint.stepper(fdt, 2, 0.0, T_ALL)
+    c = pint.stepper(fdt * fs / cs, 4, 1e15, T_ALL)
+    prm = pint.params(method, N, f, fs, c, cs, nrelax=nrelax, max_iter=k, tol=tol)
+    U0 = workloads.solid_body(GRIDS[pi][0], noise=1e-4, seed=seed)
+    return pi, prm, U0
+
+
+MIX = [request(0, pint.PARAREAL, 4, 300.0, 6, 2, 3, seed=1),
+       request(0, pint.MGRIT, 6, 300.0, 4, 1, 2, nrelax=1, seed=2),
+       request(1, pint.PARAREAL, 3, 200.0, 5, 1, 2, seed=3),
+       request(0, pint.PARAREAL, 5, 150.0, 12, 3, 2, seed=4),
+       request(1, pint.MGRIT, 4, 200.0, 4, 2, 3, nrelax=1, tol=1e-12, seed=5)]
+
+
+def serve(plans, reqs, steps_per_tick, arrivals=None, arena_states=4096, stage_states=8):
+    """Serve reqs (request i submitted before tick arrivals[i]); return the
+    results, the statuses and the tick count."""
+    srv = pint.Server(plans, arena_states * max(state_bytes(p) for p in plans),
+                      steps_per_tick=steps_per_tick, stage_states=stage_states)
+    arrivals = arrivals or [0] * len(reqs)
+    outs, ids = [None] * len(reqs), [None] * len(reqs)
+    tick, pending = 0, 1
+    while pending or any(i is None for i in ids):
+        for i, (pi, prm, U0) in enumerate(reqs):
+            if ids[i] is None and arrivals[i] <= tick:
+                outs[i] = torch.zeros((prm.n_intervals + 1, 3, plans[pi].ncoef, 2),
+                                      dtype=torch.float64, device="cuda")
+                ids[i] = srv.submit(pi, prm, to_dev(U0, torch), outs[i])
+        pending = srv.tick()
+        tick += 1
+        assert tick < 100000
+    torch.cuda.synchronize()
+    st = [srv.status(i) for i in ids]
+    srv.close()
+    return outs, st, tick
+
+
+def test_alone_equals_pint_solve_bitwise(plans):
+    """One request at a time, chunks longer than any step count: the server
+    issues pint_solve's propagations, so the iterates agree bitwise."""
+    for pi, prm, U0 in MIX:
+        outs, st, _ = serve(plans, [(pi, prm, U0)], steps_per_tick=1000)
+        ref = torch.zeros_like(outs[0])
+        status, rep, _ = plans[pi].solve_status(prm, to_dev(U0, torch), ref)
+        torch.cuda.synchronize()
+        assert status in (0, -5) and st[0].status == status          # -5: tol not reached
+        assert st[0].state == pint.REQ_DONE and st[0].iters == rep.iters
+        assert st[0].fine_slice_steps == rep.fine_slice_steps
+        assert torch.equal(outs[0], ref)
+
+
+@pytest.mark.parametrize("steps_per_tick", [1, 3])
+def test_mix_equals_alone_bitwise(plans, steps_per_tick):
+    """Five requests on two truncations, Parareal and MGRIT, arriving at
+    different ticks: each result is bitwise the result of serving it alone."""
+    mixed, st, ticks = serve(plans, MIX, steps_per_tick, arrivals=[0, 0, 2, 5, 9])
+    for i, r in enumerate(MIX):
+        alone, st1, ticks1 = serve(plans, [r], steps_per_tick)
+        assert st[i].state == pint.REQ_DONE and st[i].iters == st1[0].iters
+        assert torch.equal(mixed[i], alone[0]), i
+    assert all(s.t_submit <= s.t_start <= s.t_done for s in st)
+
+
+def test_admission_by_footprint(plans):
+    """An arena that holds the largest request but not all of them: requests
+    are admitted in arrival order as memory frees up, and give the same
+    results."""
+    big = max((4 * prm.n_intervals + 3) * state_bytes(plans[pi]) for pi, prm, _ in MIX)
+    srv_states = (big + 255) // max(state_bytes(p) for p in plans) + 1
+    seq, st, _ = serve(plans, MIX, 3, arena_states=srv_states)
+    par, _, _ = serve(plans, MIX, 3)
+    for i in range(len(MIX)):
+        assert torch.equal(seq[i], par[i])
+    starts = [s.t_start for s in st]
+    dones = [s.t_done for s in st]
+    assert starts == sorted(starts)                  # first in, first out
+    assert any(starts[i] >= min(dones[:i]) for i in range(1, len(MIX)))   # someone waited
+
+
+def test_server_argument_checks(plans):
+    srv = pint.Server(plans, 64 * state_bytes(plans[1]), steps_per_tick=2, stage_states=4)
+    pi, prm, U0 = MIX[0]
+    u0 = to_dev(U0, torch)
+    out = torch.zeros((prm.n_intervals + 1, 3, plans[0].ncoef, 2), dtype=torch.float64,
+                      device="cuda")
+    with pytest.raises(pint.PintError) as e:
+        srv.submit(2, prm, u0, out)
+    assert e.value.status == -1
+    bad = pint.params(pint.MGRIT, 4, prm.fine, prm.fine_steps, prm.coarse, prm.coarse_steps,
+                      nrelax=1, max_iter=1, levels=3, cfactor1=2,
+                      coarse2=prm.coarse, coarse2_steps=prm.coarse_steps * 2)
+    with pytest.raises(pint.PintError) as e:
+        srv.submit(0, bad, u0, out)
+    assert "two-level" in str(e.value)
+    huge = pint.params(pint.PARAREAL, 40, prm.fine, prm.fine_steps, prm.coarse,
+                       prm.coarse_steps, max_iter=1)
+    with pytest.raises(pint.PintError) as e:
+        srv.submit(1, huge, u0, out)
+    assert e.value.status == -2
+    assert srv.tick() == 0                           # nothing was queued
+    srv.close()
+
+
+def test_served_parareal_vs_oracle(plans):
+    """Row a10-a12 through the server: a Parareal request in a mix matches
+    the oracle's iterate."""
+    M, nlon, nlat = GRIDS[0]
+    md = Model(M, nlon, nlat, phibar=PHIBAR)
+    pi, prm, U0 = MIX[0]
+    outs, st, _ = serve(plans, MIX, 3, arrivals=[1, 0, 0, 2, 3])
+    fine = lambda u: md.propagate(u, 300.0, 6)
+    coarse = lambda u: md.propagate(u, 900.0, 2, 1e15, 4)
+    ref = opint.parareal(U0, 4, fine, coarse, 3)
+    ref = ref[0] if isinstance(ref, tuple) else ref
+    got = from_dev(outs[0])
+    for n in range(1, 5):
+        assert_parity(got[n], ref[n], M)
