@@ -74,18 +74,18 @@ def algorithmic_work(kind, B, prec=0):
 # (FETCH x 2.0, WRITE x 1.0), keyed by (kernel, precision), together with the
 # SHA-256 prefixes of the kernel sources the counters were taken on: a changed
 # kernel reports traffic null until measured again.
-_RING = {"ring.hip": "333320f910e02662", "pint_internal.h": "be9df7675699bcaa"}
-_LEG = {"legendre.hip": "3cf7e882174167f7", "pint_internal.h": "be9df7675699bcaa"}
+_RING = {"ring.hip": "3610c43efa925128", "pint_internal.h": "d617c8a956e268cc"}
+_LEG = {"legendre.hip": "a9fce86c23f688ce", "pint_internal.h": "d617c8a956e268cc"}
 MEASURED_TRAFFIC = {
-    ("ring_tendency", 0): (518922 * 1024 * 2.0 + 482283 * 1024 * 1.0, _RING),
-    ("legendre_synth", 0): (141042 * 1024 * 2.0 + 589824 * 1024 * 1.0, _LEG),
-    ("legendre_anal", 0): (241454 * 1024 * 2.0 + 132608 * 1024 * 1.0, _LEG),
-    ("ring_tendency", 1): (183621 * 1024 * 2.0 + 230154 * 1024 * 1.0, _RING),
-    ("legendre_synth", 1): (63824 * 1024 * 2.0 + 296281 * 1024 * 1.0, _LEG),
-    ("legendre_anal", 1): (120040 * 1024 * 2.0 + 66304 * 1024 * 1.0, _LEG),
-    ("ring_tendency", 2): (183186 * 1024 * 2.0 + 230264 * 1024 * 1.0, _RING),
-    ("legendre_synth", 2): (64595 * 1024 * 2.0 + 295284 * 1024 * 1.0, _LEG),
-    ("legendre_anal", 2): (121194 * 1024 * 2.0 + 66304 * 1024 * 1.0, _LEG),
+    ("ring_tendency", 0): (532608 * 1024 * 2.0 + 465520 * 1024 * 1.0, _RING),
+    ("legendre_synth", 0): (141419 * 1024 * 2.0 + 589824 * 1024 * 1.0, _LEG),
+    ("legendre_anal", 0): (242536 * 1024 * 2.0 + 132608 * 1024 * 1.0, _LEG),
+    ("ring_tendency", 1): (180599 * 1024 * 2.0 + 201946 * 1024 * 1.0, _RING),
+    ("legendre_synth", 1): (63776 * 1024 * 2.0 + 296043 * 1024 * 1.0, _LEG),
+    ("legendre_anal", 1): (120221 * 1024 * 2.0 + 66304 * 1024 * 1.0, _LEG),
+    ("ring_tendency", 2): (180993 * 1024 * 2.0 + 202162 * 1024 * 1.0, _RING),
+    ("legendre_synth", 2): (64557 * 1024 * 2.0 + 295372 * 1024 * 1.0, _LEG),
+    ("legendre_anal", 2): (122609 * 1024 * 2.0 + 66304 * 1024 * 1.0, _LEG),
 }
 
 
@@ -325,10 +325,28 @@ def measure_diagnostics(slices, reps=20):
         out[name] = {"states": B, "ms_per_call": ms}
         if byts is not None:
             out[name]["gbps_algorithmic"] = byts / (ms * 1e-3) / 1e9
-            out[name]["hbm_frac"] = byts / (ms * 1e-3) / 1e9 / PEAK_HBM
+            out[name]["hbm_frac"] = byts / (ms * 1e-3) / PEAK_HBM
     out["grid_l2_errors"]["note"] = ("scalar synthesis of 6 fields per state (difference and "
                                      "reference) and per-ring sums of squares; synchronises")
     plan.close()
+    # stability map (Sec. 4): two-level MGRIT (nu = 1) with an SL-SI-SETTLS
+    # coarse scheme, 21 phases x 2 roots per point, on a 2048 x 2048 grid
+    smap = torch.zeros((2048, 2048), dtype=torch.float64, device="cuda")
+    run = lambda: pint.stability_map(smap, "mgrit", "settls", 0.248j, (-2.0, 0.5), (-3.0, 3.0),
+                                     n=100, k=5, cfactor=2, n_c=1, nrelax=1, n_ks=20)
+    run()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(5):
+        run()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / 5
+    out["stability_map"] = {"points": smap.numel(), "ms_per_call": ms,
+                            "points_per_s": smap.numel() / (ms * 1e-3),
+                            "stable_fraction": float((smap <= 1.0).double().mean())}
     return out
 
 
@@ -336,16 +354,17 @@ def serve_bench(seconds, rate, max_iter=2, seed=0, steps_per_tick=8, arena_gb=96
     """Serving with continuous batching: Poisson arrivals (rate per second for
     `seconds`) of Parareal or two-level MGRIT (FCF) requests, uniform over
     T63 192x96 / T127 384x192 / T255 768x384, 16/32/64/128 slices and 1-4 day
-    horizons; fine IMEX 45 s, coarse IMEX 675 s with q = 4 and nu fixed per
-    truncation (T63 1.6e16, T127 1e15, T255 6.2e13 m^4/s), max_iter
-    iterations each; jet + bump initial states (amplitude U[60, 160] m, seeded
+    horizons; fine IMEX 45 s, coarse IMEX 675 s with q = 4 and nu scaled
+    with (n(n+1))^-2 from the paper's 1e17 m^4/s for IMEX coarse levels at
+    T127 (T63 1.6e18, T127 1e17, T255 6.25e15; weaker values leave the 675 s
+    coarse step unstable for the jet), max_iter iterations each; jet + bump initial states (amplitude U[60, 160] m, seeded
     bump longitude).  Requests are submitted at the tick after their arrival
     time; latency = completion - arrival."""
     import numpy as np
     import torch
     from paper_2306_09497_amd import pint, workloads
 
-    grids = [(63, 192, 96, 1.6e16), (127, 384, 192, 1.0e15), (255, 768, 384, 6.2e13)]
+    grids = [(63, 192, 96, 1.6e18), (127, 384, 192, 1.0e17), (255, 768, 384, 6.25e15)]
     plans = [pint.Plan(Mg, nl, nt, phibar=PHIBAR, max_batch=GROUP) for Mg, nl, nt, _ in grids]
     rng = np.random.default_rng(seed)
     # a few analysed initial states per truncation, made before timing
@@ -413,6 +432,7 @@ def serve_bench(seconds, rate, max_iter=2, seed=0, steps_per_tick=8, arena_gb=96
         "metric": "served fine slice-steps/s (continuous batching)",
         "value": work / makespan, "unit": "slice-steps/s", "n_gpus": 1,
         "requests": len(reqs), "completed": sum(s.state == pint.REQ_DONE for s in st),
+        "diverged": sum(s.state == pint.REQ_FAILED for s in st),
         "arrival_window_s": seconds, "rate_per_s": rate, "makespan_s": makespan,
         "offered_fine_slice_steps_per_s": work / seconds,
         "achieved_fine_slice_steps_per_s": work / makespan,
@@ -457,6 +477,8 @@ def main():
                     help="skip the FP32-Legendre side measurement of the default run")
     ap.add_argument("--no-mgrit3", action="store_true",
                     help="skip the three-level MGRIT side measurement of the default run")
+    ap.add_argument("--no-diagnostics", action="store_true",
+                    help="skip the diagnostics and stability-map timings of the default run")
     ap.add_argument("--time-to-tol", action="store_true",
                     help="print the T127 Parareal time-to-tolerance measurement instead")
     ap.add_argument("--serve", type=float, nargs=2, metavar=("SECONDS", "RATE"),
@@ -598,7 +620,7 @@ def main():
             }
         except Exception as e:
             out["mgrit3_coarse_t127"] = {"error": str(e)}
-    if prec == pint.FP64:
+    if prec == pint.FP64 and not args.no_diagnostics:
         try:
             out["diagnostics"] = measure_diagnostics(res["slices"])
         except Exception as e:                      # reported, not fatal

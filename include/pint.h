@@ -256,6 +256,37 @@ pint_status pint_spectral_errors(pint_plan* plan, const double* u, const double*
 pint_status pint_grid_l2_errors(pint_plan* plan, const double* u, const double* ref,
                                 double* out_host, int B, void* stream);
 
+/* Stability maps (Sec. 4): max |A| over a grid of xi_N = lambda_N dt for the
+ * scalar test equation u' = (lambda_L + lambda_N) u, written to out (device,
+ * [nim][nre], row r at Im xi_N = im0 + r (im1 - im0)/(nim - 1), column c at
+ * Re xi_N = re0 + c (re1 - re0)/(nre - 1)).
+ *   kind 0: the coarse scheme alone, one step: IMEX (Sec. 4.1.1, Heun
+ *     keeping U*), or SL-SI-SETTLS: both roots of eq.
+ *     stability_SL_SI_SETTLS for ks = 2 pi j / n_ks, j = 0..n_ks;
+ *   kind 1: two-level MGRIT with F(CF)^nrelax relaxation (nrelax = 0 is
+ *     Parareal) after k iterations at slice n: the closed form of the
+ *     recurrence eq. parareal_FCF_nrelax_B, sum_{i<=k} C(n - i nu, i) S^i
+ *     R^(n - i(nu+1)), S = F^nu (F - R), with an IMEX fine propagator
+ *     F = A_IMEX(xi/cfactor)^(cfactor n_c) and the coarse scheme
+ *     R = A_c^(n_c); for SL-SI-SETTLS the maximum over both roots and all
+ *     ks.
+ * xi_L and xi_N are on the coarse step.  Asynchronous; no plan needed.  */
+typedef struct {
+  int kind;                  /* 0 scheme alone, 1 two-level MGRIT / Parareal   */
+  int coarse;                /* 0 IMEX, 1 SL-SI-SETTLS                         */
+  double xl_re, xl_im;       /* xi_L                                           */
+  double re0, re1;           /* Re xi_N range                                  */
+  int nre;                   /* >= 1 columns                                   */
+  double im0, im1;           /* Im xi_N range                                  */
+  int nim;                   /* 1..65535 rows; nre nim <= 2^28                 */
+  int n, k;                  /* slice n >= 0, iterations 0 <= k <= 64         */
+  int cfactor, n_c;          /* >= 1: fine steps per coarse step, coarse steps */
+  int nrelax;                /* 0..8                                           */
+  int n_ks;                  /* >= 1 phases for SL-SI-SETTLS                   */
+} pint_stability_cfg;
+
+pint_status pint_stability_map(const pint_stability_cfg* cfg, double* out, void* stream);
+
 /* ---- Serving with continuous batching ------------------------------------
  * A server runs many Parareal / two-level MGRIT solves (Sec. 3, the
  * iteration of pint_solve) at once on one stream.  Each tick advances every

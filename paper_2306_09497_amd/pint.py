@@ -25,7 +25,7 @@ STATUS = {0: "PINT_OK", -1: "PINT_E_INVAL", -2: "PINT_E_NOMEM", -3: "PINT_E_HIP"
 EXPORTS = ["pint_plan_create", "pint_plan_destroy", "pint_plan_info", "pint_grid_coords",
            "pint_synthesis", "pint_analysis", "pint_tendency", "pint_implicit", "pint_step",
            "pint_solve", "pint_rel_diff", "pint_ke_spectrum", "pint_spectral_errors",
-           "pint_grid_l2_errors", "pint_server_create", "pint_server_destroy",
+           "pint_grid_l2_errors", "pint_stability_map", "pint_server_create", "pint_server_destroy",
            "pint_server_submit", "pint_server_tick", "pint_server_status", "pint_server_clock",
            "pint_profile_enable", "pint_profile_read", "pint_last_error"]
 
@@ -66,6 +66,15 @@ class PintParams(ctypes.Structure):
 class ProfEntry(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("batch", ctypes.c_int),
                 ("launches", ctypes.c_longlong), ("total_ms", ctypes.c_double)]
+
+
+class StabilityCfg(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("coarse", ctypes.c_int), ("xl_re", ctypes.c_double),
+                ("xl_im", ctypes.c_double), ("re0", ctypes.c_double), ("re1", ctypes.c_double),
+                ("nre", ctypes.c_int), ("im0", ctypes.c_double), ("im1", ctypes.c_double),
+                ("nim", ctypes.c_int), ("n", ctypes.c_int), ("k", ctypes.c_int),
+                ("cfactor", ctypes.c_int), ("n_c", ctypes.c_int), ("nrelax", ctypes.c_int),
+                ("n_ks", ctypes.c_int)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -127,6 +136,7 @@ def load(path=LIB_PATH):
     lib.pint_ke_spectrum.argtypes = [vp, vp, vp, ip, vp]
     lib.pint_spectral_errors.argtypes = [vp, vp, vp, vp, ip, vp]
     lib.pint_grid_l2_errors.argtypes = [vp, vp, vp, dp, ip, vp]
+    lib.pint_stability_map.argtypes = [ctypes.POINTER(StabilityCfg), vp, vp]
     lib.pint_server_create.argtypes = [ctypes.POINTER(ServerConfig), vp, ctypes.POINTER(vp)]
     lib.pint_server_destroy.argtypes = [vp]
     lib.pint_server_submit.argtypes = [vp, ctypes.POINTER(Request),
@@ -364,3 +374,15 @@ class Server:
             if self.tick() == 0:
                 return i + 1
         raise RuntimeError("server did not drain")
+
+
+def stability_map(out, kind, coarse, xl, re_range, im_range, n=100, k=5, cfactor=2, n_c=1,
+                  nrelax=0, n_ks=20, stream=None):
+    """out (device [nim][nre] float64) <- max |A| on the xi_N grid (see
+    pint_stability_map); kind "scheme" or "mgrit", coarse "imex" or "settls";
+    re_range / im_range = (first, last)."""
+    nim, nre = out.shape
+    cfg = StabilityCfg({"scheme": 0, "mgrit": 1}[kind], {"imex": 0, "settls": 1}[coarse],
+                       complex(xl).real, complex(xl).imag, re_range[0], re_range[1], nre,
+                       im_range[0], im_range[1], nim, n, k, cfactor, n_c, nrelax, n_ks)
+    _check(load().pint_stability_map(ctypes.byref(cfg), _ptr(out), _stream(stream)))
