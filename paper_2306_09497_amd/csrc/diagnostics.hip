@@ -23,22 +23,35 @@ __device__ inline double2 load_c(const double* p, size_t i) {
   return *reinterpret_cast<const double2*>(p + 2 * i);
 }
 
-// One thread per (n, state): threads of consecutive n read consecutive
-// coefficients of each m; the sum runs over m in increasing order.
-__global__ void k_ke_spectrum(const double* __restrict__ u, double* __restrict__ e, int M,
-                              int ncoef, double a2) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
-  if (n > M) return;
+// 64 n of one state per workgroup, four waves splitting m by m mod 4:
+// threads of consecutive n read consecutive coefficients of each m; each
+// wave sums its m in increasing order, then the four partial sums are added
+// in wave order.
+constexpr int kKeWaves = 4;
+__global__ __launch_bounds__(64 * kKeWaves) void k_ke_spectrum(const double* __restrict__ u,
+                                                               double* __restrict__ e, int M,
+                                                               int ncoef, double a2) {
+  __shared__ double part[kKeWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + lane, b = blockIdx.y;
   const double* xi = u + ((size_t)b * 3 + 1) * ncoef * 2;
   const double* de = xi + (size_t)ncoef * 2;
   double s = 0.0;
-  for (int m = 0; m <= n; ++m) {
-    const int k = coef_idx(M, m, n);
-    const double2 x = load_c(xi, k), d = load_c(de, k);
-    const double v = (x.x * x.x + x.y * x.y) + (d.x * d.x + d.y * d.y);
-    s += m == 0 ? v : 2.0 * v;
+  if (n <= M) {
+    for (int m = w; m <= n; m += kKeWaves) {
+      const int k = coef_idx(M, m, n);
+      const double2 x = load_c(xi, k), d = load_c(de, k);
+      const double v = (x.x * x.x + x.y * x.y) + (d.x * d.x + d.y * d.y);
+      s += m == 0 ? v : 2.0 * v;
+    }
   }
-  e[(size_t)b * (M + 1) + n] = n == 0 ? 0.0 : 0.25 * a2 / (n * (n + 1.0)) * s;
+  part[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && n <= M) {
+    double t = part[0][lane];
+    for (int q = 1; q < kKeWaves; ++q) t += part[q][lane];
+    e[(size_t)b * (M + 1) + n] = n == 0 ? 0.0 : 0.25 * a2 / (n * (n + 1.0)) * t;
+  }
 }
 
 constexpr int kErrThreads = 256;
@@ -127,8 +140,8 @@ __global__ void k_l2_pairs(const double* __restrict__ u, const double* __restric
 
 pint_status ke_spectrum(Plan& p, const double* u, double* e, int B, hipStream_t s) {
   if (B == 0) return PINT_OK;
-  hipLaunchKernelGGL(k_ke_spectrum, dim3((p.M + 64) / 64, B), dim3(64), 0, s, u, e, p.M, p.ncoef,
-                     p.a * p.a);
+  hipLaunchKernelGGL(k_ke_spectrum, dim3((p.M + 64) / 64, B), dim3(64 * kKeWaves), 0, s, u, e,
+                     p.M, p.ncoef, p.a * p.a);
   PINT_HIP(hipGetLastError());
   return PINT_OK;
 }
