@@ -173,7 +173,9 @@ pint_status pint_step(pint_plan* plan, const pint_stepper* st, const double* u_i
  * mean) and of the wind (vorticity and divergence through the velocity they
  * induce), both area-weighted L2 norms (see pint_rel_diff).  u_slices[(n_intervals+1)][3][ncoef][2] receives the
  * states at the slice (C-point) boundaries; u0 is its initial state.
- * Synchronises `stream` once per iteration (to read the increment).  */
+ * Synchronises `stream` once per iteration (to read the increment).  The
+ * plan keeps the drivers' scratch (about 3 n_intervals + 2 states, more with
+ * three levels) between calls and grows it only when a call needs more.  */
 typedef struct {
   int method;             /* 0 Parareal, 1 MGRIT two-level                    */
   int n_intervals;        /* N slices / C-intervals                           */

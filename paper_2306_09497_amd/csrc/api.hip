@@ -81,19 +81,35 @@ static pint_status propagate(Plan& p, const pint_stepper& st, const double* in, 
 // ---------------------------------------------------------------------------
 // PinT drivers.  States are public layout, one per slice boundary.
 // ---------------------------------------------------------------------------
+// Device scratch of the drivers: slot `slot` of the plan's pool, kept
+// between calls and grown (free, then allocate) only when a call needs more
+// than any before it, so repeated solves neither allocate nor synchronise on
+// frees.  Calls on one plan are ordered on their stream; a plan is not
+// shared between concurrent calls.
 struct DevBuf {
+  Plan& pl;
+  int slot;
   double* p = nullptr;
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
-  }
+  DevBuf(Plan& plan, int s) : pl(plan), slot(s) {}
   pint_status alloc(size_t n) {
-    if (hipMalloc(&p, n * sizeof(double)) != hipSuccess) {
-      set_error("hipMalloc(%zu bytes) failed in pint_solve", n * sizeof(double));
-      return PINT_E_NOMEM;
+    if (pl.pool.size() <= (size_t)slot) pl.pool.resize(slot + 1, {nullptr, 0});
+    auto& b = pl.pool[slot];
+    if (b.second < n) {
+      if (b.first) (void)hipFree(b.first);
+      b = {nullptr, 0};
+      if (hipMalloc(&b.first, n * sizeof(double)) != hipSuccess) {
+        b.first = nullptr;
+        set_error("hipMalloc(%zu bytes) failed in pint_solve", n * sizeof(double));
+        return PINT_E_NOMEM;
+      }
+      b.second = n;
     }
+    p = b.first;
     return PINT_OK;
   }
 };
+enum PoolSlot { kSlotGold, kSlotFv, kSlotUprev, kSlotGtmp, kSlotCin, kSlotCinSide, kSlotW,
+                kSlotFl, kSlotGl, kSlotTmp, kSlotF2, kSlotG2, kSlotGz };
 
 static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -173,7 +189,8 @@ struct CoarseProp {
   Plan* pc = nullptr;
   DevBuf cin, cin_side;   // truncation-Mc states
   int cap = 0;            // states cin holds
-  explicit CoarseProp(Plan& fine) : p(fine) {}
+  explicit CoarseProp(Plan& fine)
+      : p(fine), cin(fine, kSlotCin), cin_side(fine, kSlotCinSide) {}
   pint_status init(const pint_pint_params* q, int cap_states) {
     if (!q->coarse_plan) return PINT_OK;
     pc = &q->coarse_plan->p;
@@ -220,6 +237,9 @@ struct CoarseProp {
 // return U[1..N1] = w.
 struct Level1Bufs {
   DevBuf W, Fl, Gl, tmp, F2, G2, gz;
+  explicit Level1Bufs(Plan& p)
+      : W(p, kSlotW), Fl(p, kSlotFl), Gl(p, kSlotGl), tmp(p, kSlotTmp), F2(p, kSlotF2),
+        G2(p, kSlotG2), gz(p, kSlotGz) {}
   pint_status alloc(size_t sd, int m1, int N2) {
     const size_t rows = (size_t)m1 * (N2 + 1);
     PINT_TRY(W.alloc(sd * rows));
@@ -299,7 +319,7 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
   pint_report local;
   pint_report* r = rep ? rep : &local;
   memset(r, 0, sizeof *r);
-  DevBuf Gold, Fv, Uprev, Gtmp;
+  DevBuf Gold(p, kSlotGold), Fv(p, kSlotFv), Uprev(p, kSlotUprev), Gtmp(p, kSlotGtmp);
   PINT_TRY(Gold.alloc(sd * N));
   PINT_TRY(Fv.alloc(sd * N));
   PINT_TRY(Uprev.alloc(sd * (N + 1)));
@@ -309,7 +329,7 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
   const bool mgrit = q->method == 1;
   const int nrelax = mgrit ? q->nrelax : 0;
   const bool three = mgrit && q->levels == 3;
-  Level1Bufs l1;
+  Level1Bufs l1(p);
   if (three) PINT_TRY(l1.alloc(sd, q->cfactor1, N / q->cfactor1));
   CoarseProp coarse(p);
   PINT_TRY(coarse.init(q, N));

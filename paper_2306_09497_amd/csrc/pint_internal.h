@@ -123,6 +123,9 @@ struct Plan {
   double* diag = nullptr;      // L2-error partial sums [3 max_batch][nlat][2]
   double* h_red = nullptr;     // pinned host mirror
   size_t ws_bytes = 0;
+  // device scratch of the PinT drivers, kept between calls and grown on
+  // demand (slot -> buffer, doubles)
+  std::vector<std::pair<double*, size_t>> pool;
   std::map<std::pair<double, unsigned>, CnFactors> cn_cache;
   // kernel timing (pint_profile_enable)
   bool prof_on = false;

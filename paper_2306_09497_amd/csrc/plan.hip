@@ -158,6 +158,9 @@ static void free_plan(Plan& p) {
                   p.side.S, p.side.F, p.side.G, p.side.Q, p.side.Ua, p.side.N1};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
+  for (auto& b : p.pool)
+    if (b.first) (void)hipFree(b.first);
+  p.pool.clear();
   for (hipEvent_t e : p.chunk_ev) (void)hipEventDestroy(e);
   p.chunk_ev.clear();
   if (p.join_ev) (void)hipEventDestroy(p.join_ev);
