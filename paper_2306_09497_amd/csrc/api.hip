@@ -40,7 +40,11 @@ pint_status check_stepper(const Plan& p, const pint_stepper* st) {
 // the next step's first half step.  Without the nonlinear term a step is the
 // two half steps alone.  out may alias in.
 pint_status imex_steps(Plan& p, const pint_stepper& st, const double* in, double* out, int B,
-                       int nsteps, hipStream_t s) {
+                       int nsteps, hipStream_t s, const double* cf, double* corr) {
+  if (corr && (nsteps < 1 || !(st.terms & PINT_T_NL))) {
+    set_error("internal: a fused correction needs a nonlinear step");
+    return PINT_E_INVAL;
+  }
   if (nsteps == 0) {
     if (in != out)
       PINT_HIP(hipMemcpyAsync(out, in, (size_t)B * 3 * p.ncoef * 2 * sizeof(double),
@@ -62,7 +66,8 @@ pint_status imex_steps(Plan& p, const pint_stepper& st, const double* in, double
     PINT_TRY(legendre_synth(p, B, kSynFields, p.prec, s));
     PINT_TRY(ring_tendency(p, B, s));
     PINT_TRY(legendre_anal(p, B, kAnaFields, p.prec, s));
-    PINT_TRY(sp_stage2(p, *f, st, out, k + 1 < nsteps, B, s));
+    const bool last = k + 1 == nsteps;
+    PINT_TRY(sp_stage2(p, *f, st, out, !last, B, s, last ? cf : nullptr, last ? corr : nullptr));
   }
   return PINT_OK;
 }
@@ -200,6 +205,22 @@ struct CoarseProp {
     return cin_side.alloc(sdc);
   }
   Plan& stepping() { return pc ? *pc : p; }
+  // One sweep step on the sweep stream: gold (G_old in, G out) and
+  // out = (G - G_old) + f, with G = Phi_c(in).  Fused into the last
+  // propagation kernel when the coarse level is on the plan itself;
+  // otherwise propagation, pr_update and a copy.
+  pint_status sweep_step(const pint_stepper& st, int nsteps, const double* in, double* gold,
+                         const double* f, double* out, double* tmp, hipStream_t s) {
+    const size_t sd = (size_t)3 * p.ncoef * 2;
+    if (!pc && nsteps >= 1 && (st.terms & PINT_T_NL)) {
+      SideWork sw(p);
+      return imex_steps(p, st, in, gold, 1, nsteps, s, f, out);
+    }
+    PINT_TRY(run(st, nsteps, in, tmp, 1, s, true));
+    PINT_TRY(pr_update(p, tmp, gold, f, out, sd, s));
+    PINT_HIP(hipMemcpyAsync(gold, tmp, sd * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return PINT_OK;
+  }
   pint_status run(const pint_stepper& st, int nsteps, const double* in, double* out, int B,
                   hipStream_t s, bool side) {
     if (!pc) {
@@ -408,15 +429,14 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
           int need = (n + 1 - first) / cs;
           if (need > nchunk - 1) need = nchunk - 1;
           while (waited < need) PINT_HIP(hipStreamWaitEvent(ss, p.chunk_ev[++waited], 0));
-          const double* gnew = Gold.p + n * sd;        // unchanged input at n == first
-          if (n > first) {
-            PINT_TRY(coarse.run(q->coarse, q->coarse_steps, U + n * sd, Gtmp.p, 1, ss, true));
+          if (n == first) {   // unchanged input: G_new = G_old
+            PINT_TRY(pr_update(p, Gold.p + n * sd, Gold.p + n * sd, Fv.p + n * sd,
+                               U + (n + 1) * sd, sd, ss));
+          } else {
+            PINT_TRY(coarse.sweep_step(q->coarse, q->coarse_steps, U + n * sd, Gold.p + n * sd,
+                                       Fv.p + n * sd, U + (n + 1) * sd, Gtmp.p, ss));
             r->coarse_steps += q->coarse_steps;
-            gnew = Gtmp.p;
           }
-          PINT_TRY(pr_update(p, gnew, Gold.p + n * sd, Fv.p + n * sd, U + (n + 1) * sd, sd, ss));
-          if (n > first)
-            PINT_HIP(hipMemcpyAsync(Gold.p + n * sd, Gtmp.p, sb, hipMemcpyDeviceToDevice, ss));
         }
         PINT_HIP(hipEventRecord(p.join_ev, ss));
       }

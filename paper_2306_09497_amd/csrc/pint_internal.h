@@ -193,7 +193,8 @@ pint_status sp_cn_prep(Plan& p, const CnFactors& f, const pint_stepper& st, cons
                        int B, hipStream_t s);
 pint_status sp_stage1(Plan& p, double dt, int B, hipStream_t s);
 pint_status sp_stage2(Plan& p, const CnFactors& f, const pint_stepper& st, double* out,
-                      bool chain, int B, hipStream_t s);
+                      bool chain, int B, hipStream_t s, const double* cf = nullptr,
+                      double* corr = nullptr);
 pint_status sp_prep(Plan& p, const double* in, int B, hipStream_t s);
 pint_status sp_tend(Plan& p, double* out, int B, hipStream_t s);
 pint_status sp_cn(Plan& p, const CnFactors& f, const pint_stepper& st0, const pint_stepper* st1,
@@ -202,8 +203,12 @@ pint_status sp_cn(Plan& p, const CnFactors& f, const pint_stepper& st0, const pi
 // argument checks of the public entry points (PINT_E_INVAL with a message)
 pint_status check_stepper(const Plan& p, const pint_stepper* st);
 pint_status check_params(const Plan& p, const pint_pint_params* q);
+// With corr (needs nsteps >= 1 and the nonlinear term): out holds G_old on
+// entry and receives the result G, and corr = (G - G_old) + cf (a PinT
+// correction fused into the last step).
 pint_status imex_steps(Plan& p, const pint_stepper& st, const double* in, double* out, int B,
-                       int nsteps, hipStream_t s);
+                       int nsteps, hipStream_t s, const double* cf = nullptr,
+                       double* corr = nullptr);
 
 // transforms on the GEMM workspace
 // prec: PINT_FP64 (also used by the public scalar transforms) or PINT_LEG_FP32

@@ -397,12 +397,17 @@ __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_stage1(const SE* __restr
 // K_C (second explicit stage and the closing half step):
 // U = D_nu CN(Ua + dt/2 (N1 + N(Q))); chain = 0: out = U; chain = 1: the next
 // step's first half step follows at once: ua = CN(U), S = its synthesis input.
+// With a correction (corr != null, one state, chain = 0) the step is the
+// coarse propagation of a PinT sweep: out holds G_old on entry and receives
+// U, and corr = (U - G_old) + f, the update pr_update makes (bitwise).
 template <int SEG, typename SE>
 __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_stage2(const SE* __restrict__ Q,
                                                   double* __restrict__ ua,
                                                   const double* __restrict__ n1,
                                                   double* __restrict__ out,
                                                   SE* __restrict__ S, double dt, int chain,
+                                                  const double* __restrict__ cf,
+                                                  double* __restrict__ corr,
                                                   SpecArgs sa, CnArgs c) {
   const WaveAt w = wave_at<SEG>(sa.M, sa.B);
   if (w.b >= sa.B) return;                            // uniform per wave
@@ -426,6 +431,20 @@ __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_stage2(const SE* __restr
     cn_lane<SEG>(V, w, sa.ncoef, c1);
     store_state<SEG>(ua, w, sa.ncoef, V);
     prep_lane<SEG>(V, w, sa.B, S, sa.rowoff, sa.a, sa.phibar);
+  } else if (corr) {
+#pragma unroll
+    for (int k = 0; k < SEG; ++k) {
+      const int i = w.p0 + k;
+      if (i < w.K) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+          const size_t at = ((size_t)w.b * 3 + f) * sa.ncoef + w.i0 + i;
+          const double2 go = ld2(out, at), fv = ld2(cf, at);
+          st2(corr, at, cadd(csub(V[k][f], go), fv));
+          st2(out, at, V[k][f]);
+        }
+      }
+    }
   } else {
     store_state<SEG>(out, w, sa.ncoef, V);
   }
@@ -550,7 +569,7 @@ pint_status sp_stage1(Plan& p, double dt, int B, hipStream_t s) {
 }
 
 pint_status sp_stage2(Plan& p, const CnFactors& f, const pint_stepper& st, double* out,
-                      bool chain, int B, hipStream_t s) {
+                      bool chain, int B, hipStream_t s, const double* cf, double* corr) {
   ProfScope ps(p, PK_ASSEMBLE, B, s);
   const SpecArgs sa = spec_args(p, B);
   const CnArgs c = cn_args(p, f, st, true);
@@ -558,7 +577,7 @@ pint_status sp_stage2(Plan& p, const CnFactors& f, const pint_stepper& st, doubl
 #define L(SEG, SE)                                                                    \
   hipLaunchKernelGGL((k_sp_stage2<SEG, SE>), grid, dim3(64 * kSpecWaves), 0, s,          \
                      reinterpret_cast<const SE*>(p.Q), p.Ua, p.N1, out,                  \
-                     reinterpret_cast<SE*>(p.S), st.dt, chain ? 1 : 0, sa, c)
+                     reinterpret_cast<SE*>(p.S), st.dt, chain ? 1 : 0, cf, corr, sa, c)
   PINT_SEG_DISPATCH(L)
 #undef L
   PINT_HIP(hipGetLastError());
