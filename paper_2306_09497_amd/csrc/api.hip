@@ -391,9 +391,13 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
         PINT_HIP(hipMemcpyAsync(U + sd, Fv.p, sb * N, hipMemcpyDeviceToDevice, s));
         r->fine_slice_steps += (long long)N * q->fine_steps;
       }
-      // coarse values of the relaxed C-points, Phi_1(v_i)
-      PINT_TRY(coarse.run(q->coarse, q->coarse_steps, U, Gold.p, N, s, false));
-      r->coarse_steps += (long long)N * q->coarse_steps;
+      // coarse values of the relaxed C-points, Phi_1(v_i): all of them now
+      // for three levels; with two levels chunk by chunk below, so that the
+      // sweep can start after the first chunk
+      if (three) {
+        PINT_TRY(coarse.run(q->coarse, q->coarse_steps, U, Gold.p, N, s, false));
+        r->coarse_steps += (long long)N * q->coarse_steps;
+      }
     }
     if (three) {
       // three levels: Phi_1(v_i) of the (relaxed) C-points, F_i of every
@@ -414,6 +418,11 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
       for (int c = 0; c < nchunk; ++c) {
         const int n0 = first + c * cs;
         const int nb = cs < N - n0 ? cs : N - n0;
+        if (nrelax > 0) {
+          PINT_TRY(coarse.run(q->coarse, q->coarse_steps, src + n0 * sd, Gold.p + n0 * sd, nb, s,
+                              false));
+          r->coarse_steps += (long long)nb * q->coarse_steps;
+        }
         PINT_TRY(propagate(p, q->fine, src + n0 * sd, Fv.p + n0 * sd, nb, q->fine_steps, s));
         PINT_HIP(hipEventRecord(p.chunk_ev[c], s));
       }
