@@ -291,7 +291,8 @@ pint_status pint_stability_map(const pint_stability_cfg* cfg, double* out, void*
 
 /* ---- Serving with continuous batching ------------------------------------
  * A server runs many Parareal / two-level MGRIT solves (Sec. 3, the
- * iteration of pint_solve) at once on one stream.  Each tick advances every
+ * iteration of pint_solve) at once: plan 0's work on the stream given at
+ * creation, each other plan's on a stream the server creates.  Each tick advances every
  * running request's pending propagation by one chunk of at most
  * steps_per_tick IMEX steps, and all chunks of one plan with the same
  * stepper and length run as one batched propagation: fine propagations of
@@ -345,7 +346,8 @@ pint_status pint_server_destroy(pint_server* server);
 pint_status pint_server_submit(pint_server* server, const pint_request* req, long long* id);
 /* Admit what fits, advance every running request by one chunk, finish what
  * completed; *pending = requests queued or running afterwards.  Synchronises
- * the stream once (and once per completed iteration, for the increments). */
+ * the server's streams once (and a plan's stream once per completed
+ * iteration, for the increments). */
 pint_status pint_server_tick(pint_server* server, int* pending);
 pint_status pint_server_status(pint_server* server, long long id, pint_request_status* st);
 /* Seconds since the server was created (the clock of the time stamps). */

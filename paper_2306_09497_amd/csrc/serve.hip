@@ -16,7 +16,10 @@
 //
 // Request state lives in one device arena allocated when the server is
 // created (first-fit with coalescing); admission is by footprint, first in
-// first out, so nothing is allocated in the serving loop.
+// first out, so nothing is allocated in the serving loop.  Each plan's work
+// goes to a stream of its own (plan 0: the caller's), so launches of
+// different truncations overlap; a plan's workspace is only touched from its
+// stream.
 #include <algorithm>
 #include <chrono>
 #include <deque>
@@ -140,7 +143,8 @@ using namespace pint;
 
 struct pint_server {
   std::vector<Plan*> plans;
-  hipStream_t s = nullptr;
+  std::vector<hipStream_t> streams;      // per plan: the caller's for plan 0
+  std::vector<hipStream_t> owned;        // streams the server created
   Arena arena;
   int steps_per_tick = 1;
   int stage_states = 0;
@@ -152,8 +156,10 @@ struct pint_server {
   double t0 = 0;
   std::vector<double> incr;
   ~pint_server() {
+    for (hipStream_t st : streams) (void)hipStreamSynchronize(st);
     for (double* p : staging)
       if (p) (void)hipFree(p);
+    for (hipStream_t st : owned) (void)hipStreamDestroy(st);
   }
   double now() const { return clock_s() - t0; }
 };
@@ -193,7 +199,7 @@ pint_status run_machine(pint_server& S, Request& r) {
   const int N = q.n_intervals;
   const size_t sd = state_doubles(p);
   const bool mgrit = q.method == 1;
-  hipStream_t s = S.s;
+  hipStream_t s = S.streams[r.plan];
   auto finish = [&]() -> pint_status {
     PINT_TRY(copy(r.out, r.U, sd * (N + 1), s));
     r.finishing = true;
@@ -324,7 +330,7 @@ pint_status admit(pint_server& S) {
     r.Fv = r.Uprev + sd * (N + 1);
     r.Gold = r.Fv + sd * N;
     r.Gtmp = r.Gold + sd * N;
-    PINT_TRY(copy(r.U, r.u0, sd, S.s));
+    PINT_TRY(copy(r.U, r.u0, sd, S.streams[r.plan]));
     r.t_start = S.now();
     r.state = PINT_REQ_RUNNING;
     enter(r, kInitSweep);
@@ -338,10 +344,11 @@ pint_status run_group(pint_server& S, int pi, const std::vector<Job*>& jobs, int
   Plan& p = *S.plans[pi];
   const size_t sd = state_doubles(p);
   const pint_stepper& st = jobs.front()->st;
+  hipStream_t s = S.streams[pi];
   auto launch = [&](const double* in, double* out, int count) -> pint_status {
     for (int b0 = 0; b0 < count; b0 += p.max_batch) {
       const int nb = count - b0 < p.max_batch ? count - b0 : p.max_batch;
-      PINT_TRY(imex_steps(p, st, in + b0 * sd, out + b0 * sd, nb, chunk, S.s));
+      PINT_TRY(imex_steps(p, st, in + b0 * sd, out + b0 * sd, nb, chunk, s));
     }
     return PINT_OK;
   };
@@ -361,11 +368,11 @@ pint_status run_group(pint_server& S, int pi, const std::vector<Job*>& jobs, int
     double* stg = S.staging[pi];
     for (const Piece& c : seg) {
       const double* src = (c.j->done ? c.j->out : c.j->in) + (size_t)c.off * sd;
-      PINT_TRY(copy(stg + (size_t)c.slot * sd, src, sd * c.cnt, S.s));
+      PINT_TRY(copy(stg + (size_t)c.slot * sd, src, sd * c.cnt, s));
     }
     PINT_TRY(launch(stg, stg, used));
     for (const Piece& c : seg)
-      PINT_TRY(copy(c.j->out + (size_t)c.off * sd, stg + (size_t)c.slot * sd, sd * c.cnt, S.s));
+      PINT_TRY(copy(c.j->out + (size_t)c.off * sd, stg + (size_t)c.slot * sd, sd * c.cnt, s));
     seg.clear();
     used = 0;
     return PINT_OK;
@@ -401,7 +408,7 @@ pint_status tick(pint_server& S, int* pending) {
       for (Job* j : g.second) ran.push_back({j, g.first.chunk});
     }
   }
-  PINT_HIP(hipStreamSynchronize(S.s));
+  for (hipStream_t st : S.streams) PINT_HIP(hipStreamSynchronize(st));
   for (auto& jr : ran) jr.first->done += jr.second;
   const double t = S.now();
   std::vector<Request*> still;
@@ -439,7 +446,17 @@ pint_status pint_server_create(const pint_server_config* cfg, void* stream, pint
       return PINT_E_INVAL;
     }
   std::unique_ptr<pint_server> S(new pint_server);
-  S->s = (hipStream_t)stream;
+  for (int i = 0; i < cfg->n_plans; ++i) {
+    hipStream_t st = (hipStream_t)stream;
+    if (i > 0) {
+      if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        set_error("pint_server_create: hipStreamCreateWithFlags failed");
+        return PINT_E_HIP;
+      }
+      S->owned.push_back(st);
+    }
+    S->streams.push_back(st);
+  }
   S->steps_per_tick = cfg->steps_per_tick;
   S->stage_states = cfg->stage_states;
   S->t0 = clock_s();
@@ -464,7 +481,6 @@ pint_status pint_server_destroy(pint_server* S) {
     set_error("null server");
     return PINT_E_INVAL;
   }
-  (void)hipStreamSynchronize(S->s);
   delete S;
   return PINT_OK;
 }
@@ -499,8 +515,8 @@ pint_status pint_server_submit(pint_server* S, const pint_request* req, long lon
   }
   // Crank-Nicolson factors of both steppers now, not in the serving loop
   const CnFactors* f = nullptr;
-  PINT_TRY(cn_factors(p, q.fine.dt, q.fine.terms, S->s, &f));
-  PINT_TRY(cn_factors(p, q.coarse.dt, q.coarse.terms, S->s, &f));
+  PINT_TRY(cn_factors(p, q.fine.dt, q.fine.terms, S->streams[req->plan], &f));
+  PINT_TRY(cn_factors(p, q.coarse.dt, q.coarse.terms, S->streams[req->plan], &f));
   std::unique_ptr<Request> r(new Request);
   r->id = S->next_id++;
   r->plan = req->plan;

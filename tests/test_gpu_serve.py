@@ -151,3 +151,27 @@ def test_served_parareal_vs_oracle(plans):
     got = from_dev(outs[0])
     for n in range(1, 5):
         assert_parity(got[n], ref[n], M)
+
+
+def test_mixed_precision_plan_mix_equals_alone():
+    """A server over an FP32-Legendre plan and a split-BF16 plan: results are
+    bitwise the same alone and in the mix (the mixed modes are batch
+    invariant too) and differ from the FP64 plan's only at reduced-precision
+    level."""
+    M, nlon, nlat = GRIDS[0]
+    pls = [pint.Plan(M, nlon, nlat, phibar=PHIBAR, max_batch=8, precision=pint.LEG_FP32),
+           pint.Plan(M, nlon, nlat, phibar=PHIBAR, max_batch=8, precision=pint.LEG_BF16X3)]
+    reqs = [(0, MIX[0][1], MIX[0][2]), (1, MIX[1][1], MIX[1][2]), (0, MIX[3][1], MIX[3][2]),
+            (1, MIX[0][1], MIX[0][2])]
+    mixed, st, _ = serve(pls, reqs, 3, arrivals=[0, 1, 1, 4])
+    for i, r in enumerate(reqs):
+        alone, _, _ = serve(pls, [r], 3)
+        assert st[i].state == pint.REQ_DONE
+        assert torch.equal(mixed[i], alone[0]), i
+    # the same Parareal request on the FP32 and BF16x3 plans vs the FP64 plan
+    ref, _, _ = serve([pint.Plan(M, nlon, nlat, phibar=PHIBAR, max_batch=8)], [reqs[0]], 3)
+    d32 = float((mixed[0] - ref[0]).abs().max() / ref[0].abs().max())
+    d16 = float((mixed[3] - ref[0]).abs().max() / ref[0].abs().max())
+    assert 0.0 < d32 < d16 < 1e-3, (d32, d16)
+    for p in pls:
+        p.close()
