@@ -229,14 +229,15 @@ def time_to_tol():
     return out
 
 
-def measure(precision, steps, warmup, levels=2, coarse_grid=None):
+def measure(precision, steps, warmup, levels=2, coarse_grid=None, coarse_precision=None):
     """Time `steps` MGRIT iterations at the given Legendre precision (levels 2,
     or 3 with level-2 points every CFACTOR level-1 points, one level-2 step of
     CFACTOR * DT_COARSE, two cycles on levels 1 and 2 per iteration); return
     the throughput, the per-kernel profile of the batched transform kernels,
     the increments and the slice states after warmup + steps iterations.
     coarse_grid = (Mc, nlon, nlat): coarse level on a plan of that truncation
-    (spatial coarsening)."""
+    (spatial coarsening); coarse_precision: the coarse plan's transform
+    precision (default: the fine plan's)."""
     import numpy as np
     import torch
     from paper_2306_09497_amd import pint, workloads
@@ -254,7 +255,8 @@ def measure(precision, steps, warmup, levels=2, coarse_grid=None):
     extra = {}
     cplan = None
     if coarse_grid is not None:
-        cplan = pint.Plan(*coarse_grid, phibar=PHIBAR, max_batch=GROUP, precision=precision)
+        cplan = pint.Plan(*coarse_grid, phibar=PHIBAR, max_batch=GROUP,
+                          precision=precision if coarse_precision is None else coarse_precision)
         extra["coarse_plan"] = cplan
     if levels == 3:
         extra.update(levels=3, cfactor1=CFACTOR, coarse2_steps=1, cycles1=2,
@@ -620,6 +622,22 @@ def main():
             }
         except Exception as e:
             out["mgrit3_coarse_t127"] = {"error": str(e)}
+        # two levels, coarse level at the fine truncation with FP32 transforms
+        # (the fine propagator stays FP64, so the iteration converges to the
+        # same FP64 fine solution)
+        try:
+            rf = measure(pint.FP64, args.steps, args.warmup, coarse_grid=(M, NLON, NLAT),
+                         coarse_precision=pint.LEG_FP32)
+            out["mgrit2_coarse_fp32"] = {
+                "value": rf["value"], "unit": "slice-steps/s",
+                "ms_per_step": rf["elapsed"] / args.steps * 1e3,
+                "increment": rf["incr"],
+                "rel_l2_vs_fp64_coarse": field_errors(rf["slices"], res["slices"]),
+                "config": "two levels, coarse level at T255 with FP32 Legendre GEMMs and ring "
+                          "(reduced precision on the coarse level only)",
+            }
+        except Exception as e:
+            out["mgrit2_coarse_fp32"] = {"error": str(e)}
     if prec == pint.FP64 and not args.no_diagnostics:
         try:
             out["diagnostics"] = measure_diagnostics(res["slices"])

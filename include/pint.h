@@ -203,6 +203,11 @@ typedef struct {
                              n > Mc are dropped before and zero after it.
                              The difference-first updates then keep the
                              fine values of those coefficients exactly.
+                             A coarse plan at the fine truncation (Mc = M)
+                             runs the coarse levels directly on it, e.g. in
+                             a reduced transform precision while the fine
+                             propagator stays FP64 (the converged iterate
+                             is still the FP64 fine solution).
                              Not thread-safe with other calls on either
                              plan.                                         */
 } pint_pint_params;

@@ -199,22 +199,26 @@ struct CoarseProp {
   pint_status init(const pint_pint_params* q, int cap_states) {
     if (!q->coarse_plan) return PINT_OK;
     pc = &q->coarse_plan->p;
+    if (same()) return PINT_OK;
     cap = cap_states;
     const size_t sdc = (size_t)3 * pc->ncoef * 2;
     PINT_TRY(cin.alloc(sdc * cap));
     return cin_side.alloc(sdc);
   }
   Plan& stepping() { return pc ? *pc : p; }
+  // the coarse level has the fine truncation (no coarse plan, or one that
+  // differs only in its transform precision): no truncation or padding
+  bool same() const { return !pc || pc->M == p.M; }
   // One sweep step on the sweep stream: gold (G_old in, G out) and
   // out = (G - G_old) + f, with G = Phi_c(in).  Fused into the last
-  // propagation kernel when the coarse level is on the plan itself;
+  // propagation kernel when the coarse level has the fine truncation;
   // otherwise propagation, pr_update and a copy.
   pint_status sweep_step(const pint_stepper& st, int nsteps, const double* in, double* gold,
                          const double* f, double* out, double* tmp, hipStream_t s) {
     const size_t sd = (size_t)3 * p.ncoef * 2;
-    if (!pc && nsteps >= 1 && (st.terms & PINT_T_NL)) {
-      SideWork sw(p);
-      return imex_steps(p, st, in, gold, 1, nsteps, s, f, out);
+    if (same() && nsteps >= 1 && (st.terms & PINT_T_NL)) {
+      SideWork sw(stepping());
+      return imex_steps(stepping(), st, in, gold, 1, nsteps, s, f, out);
     }
     PINT_TRY(run(st, nsteps, in, tmp, 1, s, true));
     PINT_TRY(pr_update(p, tmp, gold, f, out, sd, s));
@@ -223,12 +227,13 @@ struct CoarseProp {
   }
   pint_status run(const pint_stepper& st, int nsteps, const double* in, double* out, int B,
                   hipStream_t s, bool side) {
-    if (!pc) {
+    if (same()) {
+      Plan& sp = stepping();
       if (side) {
-        SideWork sw(p);
-        return propagate(p, st, in, out, B, nsteps, s);
+        SideWork sw(sp);
+        return propagate(sp, st, in, out, B, nsteps, s);
       }
-      return propagate(p, st, in, out, B, nsteps, s);
+      return propagate(sp, st, in, out, B, nsteps, s);
     }
     const size_t sdf = (size_t)3 * p.ncoef * 2;
     const int chunk = side ? 1 : cap;

@@ -356,3 +356,36 @@ def test_spatial_coarsening_exact_and_checks(setup, coarse_t10):
                                              coarse_plan=pphi), u0, out)
     assert st == -1 and "coarse_plan" in msg
     pphi.close()
+
+
+@pytest.mark.parametrize("prec", [pint.LEG_FP32, pint.LEG_BF16X3])
+def test_reduced_precision_coarse_level(setup, prec):
+    """A coarse plan at the fine truncation in a reduced transform precision:
+    the coarse levels change (iterates differ from the FP64-coarse ones at
+    reduced-precision level), the fine propagator does not, so Parareal at
+    k = N and MGRIT at its termination bound still give the serial fine
+    states bitwise."""
+    _, pl = setup
+    cp = pint.Plan(M, NLON, NLAT, phibar=PHIBAR, max_batch=8, precision=prec)
+    U0 = workloads.solid_body(M, noise=1e-3, seed=11)
+    f = pint.stepper(300.0, 2, 0.0, T_ALL)
+    c = pint.stepper(1200.0, 4, 1e15, T_ALL)
+    N = 4
+    ser = [U0]
+    u = to_dev(U0, torch)
+    for n in range(N):
+        pl.step(f, u, u, 1, 4)
+        torch.cuda.synchronize()
+        ser.append(from_dev(u)[0])
+    for method, nrelax, k in ((pint.PARAREAL, 0, N), (pint.MGRIT, 1, 2)):
+        got, _ = run_solve(pl, pint.params(method, N, f, 4, c, 1, nrelax=nrelax, max_iter=k,
+                                           coarse_plan=cp), U0, N)
+        for n in range(N + 1):
+            assert np.array_equal(got[n], ser[n]), (method, n)
+        early, _ = run_solve(pl, pint.params(method, N, f, 4, c, 1, nrelax=nrelax, max_iter=1,
+                                             coarse_plan=cp), U0, N)
+        ref64, _ = run_solve(pl, pint.params(method, N, f, 4, c, 1, nrelax=nrelax, max_iter=1),
+                             U0, N)
+        d = np.abs(early[N] - ref64[N]).max() / np.abs(ref64[N]).max()
+        assert 0.0 < d < 1e-3, (method, d)
+    cp.close()
