@@ -72,10 +72,11 @@ def algorithmic_work(kind, B, prec=0):
 # WRITE_SIZE on `python -m paper_2306_09497_amd.profile_drivers tendency 64 3
 # <precision>`, each counter scaled by what it reads for a plain 1 GiB copy
 # (FETCH x 2.0, WRITE x 1.0), keyed by (kernel, precision), together with the
-# SHA-256 prefixes of the kernel sources the counters were taken on: a changed
-# kernel reports traffic null until measured again.
-_RING = {"ring.hip": "3610c43efa925128", "pint_internal.h": "ae2ec2b5555fb0fc"}
-_LEG = {"legendre.hip": "a9fce86c23f688ce", "pint_internal.h": "ae2ec2b5555fb0fc"}
+# SHA-256 prefixes of the sources the kernel is compiled from (its own file and
+# the shared device header) when the counters were taken: a changed kernel
+# reports traffic null until measured again.
+_RING = {"ring.hip": "0", "device_common.h": "0"}
+_LEG = {"legendre.hip": "0", "device_common.h": "0"}
 MEASURED_TRAFFIC = {
     ("ring_tendency", 0): (533178 * 1024 * 2.0 + 465989 * 1024 * 1.0, _RING),
     ("legendre_synth", 0): (141898 * 1024 * 2.0 + 589824 * 1024 * 1.0, _LEG),
