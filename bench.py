@@ -125,10 +125,30 @@ def cpu_baseline(seconds):
             break
     dt = time.perf_counter() - t0
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    # median time per fine step at the smaller truncations (5 steps each after
+    # one untimed step that builds the LU factors)
+    per = {"T255": 1e3 * dt / n}
+    for Mt, nl, nt in ((21, 64, 32), (127, 384, 192)):
+        mt = Model(Mt, nl, nt, phibar=PHIBAR)
+        Gt = workloads.jet_bump_grid(mt.grid.mu, nl, phibar=PHIBAR, **workloads.jet_bump_params(0))
+        Ut = mt.imex_step(np.stack([mt.grid.anal(Gt[f]) for f in range(3)]), DT_FINE)
+        ts = []
+        for _ in range(5):
+            a = time.perf_counter()
+            Ut = mt.imex_step(Ut, DT_FINE)
+            ts.append(time.perf_counter() - a)
+        per[f"T{Mt}"] = 1e3 * float(np.median(ts))
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": n / dt, "unit": "fine slice-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} fine IMEX steps (dt {DT_FINE:g} s) of one T255 768x384 jet+bump "
                       f"slice after LU setup, {dt:.1f} s; host has "
-                      f"{len(os.sched_getaffinity(0))} cores available"}
+                      f"{len(os.sched_getaffinity(0))} cores available",
+            "ms_per_fine_step": per, "cpu": cpu}
 
 
 def e_phi_r(phi, ref, mmax, R=32):
@@ -353,7 +373,8 @@ def measure_diagnostics(slices, reps=20):
     return out
 
 
-def serve_bench(seconds, rate, max_iter=2, seed=0, steps_per_tick=8, arena_gb=96.0):
+def serve_bench(seconds, rate, max_iter=2, seed=0, steps_per_tick=8, arena_gb=96.0,
+                precision=0, tol=0.0):
     """Serving with continuous batching: Poisson arrivals (rate per second for
     `seconds`) of Parareal or two-level MGRIT (FCF) requests, uniform over
     T63 192x96 / T127 384x192 / T255 768x384, 16/32/64/128 slices and 1-4 day
@@ -362,13 +383,16 @@ def serve_bench(seconds, rate, max_iter=2, seed=0, steps_per_tick=8, arena_gb=96
     T127 (T63 1.6e18, T127 1e17, T255 6.25e15; weaker values leave the 675 s
     coarse step unstable for the jet), max_iter iterations each; jet + bump initial states (amplitude U[60, 160] m, seeded
     bump longitude).  Requests are submitted at the tick after their arrival
-    time; latency = completion - arrival."""
+    time; latency = completion - arrival.  precision: the plans' transform
+    precision (0 FP64, 1 FP32 Legendre); tol > 0: each request stops at that
+    increment (at most max_iter iterations)."""
     import numpy as np
     import torch
     from paper_2306_09497_amd import pint, workloads
 
     grids = [(63, 192, 96, 1.6e18), (127, 384, 192, 1.0e17), (255, 768, 384, 6.25e15)]
-    plans = [pint.Plan(Mg, nl, nt, phibar=PHIBAR, max_batch=GROUP) for Mg, nl, nt, _ in grids]
+    plans = [pint.Plan(Mg, nl, nt, phibar=PHIBAR, max_batch=GROUP, precision=precision)
+             for Mg, nl, nt, _ in grids]
     rng = np.random.default_rng(seed)
     # a few analysed initial states per truncation, made before timing
     init = []
@@ -399,7 +423,7 @@ def serve_bench(seconds, rate, max_iter=2, seed=0, steps_per_tick=8, arena_gb=96
         method = int(rng.integers(2))
         prm = pint.params(method, S, pint.stepper(45.0, 2, 0.0, pint.T_ALL), fs,
                           pint.stepper(675.0, 4, grids[gi][3], pint.T_ALL), cs,
-                          nrelax=method, max_iter=max_iter)
+                          nrelax=method, max_iter=max_iter, tol=tol)
         reqs.append((t, gi, prm, int(rng.integers(3))))
     srv = pint.Server(plans, int(arena_gb * 2**30), steps_per_tick=steps_per_tick,
                       stage_states=2 * GROUP)
@@ -444,10 +468,15 @@ def serve_bench(seconds, rate, max_iter=2, seed=0, steps_per_tick=8, arena_gb=96
         "queue_mean_s": float(queue.mean()), "service_mean_s": float(service.mean()),
         "latency_p50_by_truncation_s": {f"T{k}": float(np.percentile(v, 50))
                                         for k, v in sorted(per.items())},
+        "iterations_mean": float(np.mean([s.iters for s in st])),
+        "not_converged": sum(s.status == -5 for s in st),
         "config": {"workload": "Poisson arrivals, uniform T63/T127/T255, S in {16,32,64,128}, "
                                "1-4 days, fine 45 s, coarse 675 s, Parareal or MGRIT FCF, "
-                               f"{max_iter} iterations", "steps_per_tick": steps_per_tick},
-        "data": "synthetic", "dtype": "f64",
+                               + (f"stop at increment {tol:g} (at most {max_iter} iterations)"
+                                  if tol > 0 else f"{max_iter} iterations"),
+                   "steps_per_tick": steps_per_tick,
+                   "legendre_precision": ["fp64", "fp32"][precision]},
+        "data": "synthetic", "dtype": "f64" if precision == 0 else "f64 state, f32 transforms",
     }
 
 
@@ -487,6 +516,9 @@ def main():
     ap.add_argument("--serve", type=float, nargs=2, metavar=("SECONDS", "RATE"),
                     help="print the continuous-batching serving measurement instead "
                          "(Poisson arrivals at RATE per second for SECONDS)")
+    ap.add_argument("--serve-fp32", action="store_true",
+                    help="serving with FP32-Legendre plans, each request stopping at an "
+                         "increment of 1e-6 (at most 8 iterations)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the whole PinT problem on a "
@@ -494,7 +526,8 @@ def main():
               file=sys.stderr)
         return 2
     if args.serve:
-        print(json.dumps(serve_bench(args.serve[0], args.serve[1])), flush=True)
+        kw = dict(precision=1, tol=1e-6, max_iter=8) if args.serve_fp32 else {}
+        print(json.dumps(serve_bench(args.serve[0], args.serve[1], **kw)), flush=True)
         return 0
     if args.time_to_tol:
         print(json.dumps({"metric": "PinT time-to-tol vs serial fine", **time_to_tol()}),
