@@ -493,6 +493,10 @@ static int seg_of(int M) {
   return K <= 64 ? 1 : K <= 128 ? 2 : K <= 256 ? 4 : K <= 512 ? 8 : 0;
 }
 
+// A single state (the serial sweep) runs one wave per workgroup: the other
+// three waves of a four-state workgroup would have nothing to do.
+static unsigned spec_threads(int B) { return B == 1 ? 64u : 64u * kSpecWaves; }
+
 static SpecArgs spec_args(const Plan& p, int B) {
   SpecArgs sa;
   sa.rowoff = p.rowoff;
@@ -546,7 +550,7 @@ pint_status sp_cn_prep(Plan& p, const CnFactors& f, const pint_stepper& st, cons
   const CnArgs c = cn_args(p, f, st, false);
   const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
 #define L(SEG, SE)                                                                      \
-  hipLaunchKernelGGL((k_sp_cn_prep<SEG, SE>), grid, dim3(64 * kSpecWaves), 0, s, in, p.Ua, \
+  hipLaunchKernelGGL((k_sp_cn_prep<SEG, SE>), grid, dim3(spec_threads(B)), 0, s, in, p.Ua, \
                      reinterpret_cast<SE*>(p.S), sa, c)
   PINT_SEG_DISPATCH(L)
 #undef L
@@ -559,7 +563,7 @@ pint_status sp_stage1(Plan& p, double dt, int B, hipStream_t s) {
   const SpecArgs sa = spec_args(p, B);
   const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
 #define L(SEG, SE)                                                                    \
-  hipLaunchKernelGGL((k_sp_stage1<SEG, SE>), grid, dim3(64 * kSpecWaves), 0, s,          \
+  hipLaunchKernelGGL((k_sp_stage1<SEG, SE>), grid, dim3(spec_threads(B)), 0, s,          \
                      reinterpret_cast<const SE*>(p.Q), p.Ua, p.N1, reinterpret_cast<SE*>(p.S), \
                      dt, sa)
   PINT_SEG_DISPATCH(L)
@@ -575,7 +579,7 @@ pint_status sp_stage2(Plan& p, const CnFactors& f, const pint_stepper& st, doubl
   const CnArgs c = cn_args(p, f, st, true);
   const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
 #define L(SEG, SE)                                                                    \
-  hipLaunchKernelGGL((k_sp_stage2<SEG, SE>), grid, dim3(64 * kSpecWaves), 0, s,          \
+  hipLaunchKernelGGL((k_sp_stage2<SEG, SE>), grid, dim3(spec_threads(B)), 0, s,          \
                      reinterpret_cast<const SE*>(p.Q), p.Ua, p.N1, out,                  \
                      reinterpret_cast<SE*>(p.S), st.dt, chain ? 1 : 0, cf, corr, sa, c)
   PINT_SEG_DISPATCH(L)
@@ -589,7 +593,7 @@ pint_status sp_prep(Plan& p, const double* in, int B, hipStream_t s) {
   const SpecArgs sa = spec_args(p, B);
   const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
 #define L(SEG, SE)                                                                 \
-  hipLaunchKernelGGL((k_sp_prep<SEG, SE>), grid, dim3(64 * kSpecWaves), 0, s, in,      \
+  hipLaunchKernelGGL((k_sp_prep<SEG, SE>), grid, dim3(spec_threads(B)), 0, s, in,      \
                      reinterpret_cast<SE*>(p.S), sa)
   PINT_SEG_DISPATCH(L)
 #undef L
@@ -602,7 +606,7 @@ pint_status sp_tend(Plan& p, double* out, int B, hipStream_t s) {
   const SpecArgs sa = spec_args(p, B);
   const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
 #define L(SEG, SE)                                                                 \
-  hipLaunchKernelGGL((k_sp_tend<SEG, SE>), grid, dim3(64 * kSpecWaves), 0, s,          \
+  hipLaunchKernelGGL((k_sp_tend<SEG, SE>), grid, dim3(spec_threads(B)), 0, s,          \
                      reinterpret_cast<const SE*>(p.Q), out, sa)
   PINT_SEG_DISPATCH(L)
 #undef L
@@ -619,7 +623,7 @@ pint_status sp_cn(Plan& p, const CnFactors& f, const pint_stepper& st0, const pi
   const int two = st1 ? 1 : 0;
   const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
 #define L(SEG, SE)                                                                           \
-  hipLaunchKernelGGL(k_sp_cn<SEG>, grid, dim3(64 * kSpecWaves), 0, s, in, out, two, sa, c0, c1)
+  hipLaunchKernelGGL(k_sp_cn<SEG>, grid, dim3(spec_threads(B)), 0, s, in, out, two, sa, c0, c1)
   PINT_SEG_DISPATCH(L)
 #undef L
   PINT_HIP(hipGetLastError());
