@@ -6,8 +6,10 @@
  * step of the rotating shallow-water equations in vorticity/divergence/
  * geopotential form (Sec. 2.1, eq. swe_sphere), discretised with spherical
  * harmonics under triangular truncation on a Gauss grid (Sec. 2.2), and runs
- * it batched over many time slices inside Parareal (Sec. 3.1) and two-level
- * MGRIT (Sec. 3.2).
+ * it batched over many time slices inside Parareal (Sec. 3.1) and two- and
+ * three-level MGRIT (Sec. 3.2).  Around that path: a server that runs many
+ * such solves at once, the error norms and kinetic-energy spectrum of
+ * Sec. 5-6 and the stability maps of Sec. 4, all on the device.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -143,7 +145,8 @@ pint_status pint_implicit(pint_plan* plan, const pint_stepper* st, const double*
  * CN half step, Heun explicit stage, CN half step, viscosity) applied
  * independently to each of B states (time slices).  u_in and u_out are
  * [B][3][ncoef][2]; u_out may alias u_in.  Results for a state do not depend
- * on B or on the other states (bitwise).  */
+ * on B, on the other states or on how the steps are split between calls
+ * (n steps in one call equal n one-step calls), bitwise.  */
 pint_status pint_step(pint_plan* plan, const pint_stepper* st, const double* u_in, double* u_out,
                       int B, int nsteps, void* stream);
 

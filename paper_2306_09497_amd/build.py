@@ -21,6 +21,13 @@ FLAGS = [
 ]
 
 
+# Per-source flags.  The spectral kernels round every operation on its own
+# (no multiply-add contraction), so that the same step computed in different
+# kernels (a Crank-Nicolson half step fused into the previous step's last
+# kernel, or in a kernel of its own) gives bitwise the same result.
+EXTRA = {"spectral.hip": ["-ffp-contract=off"]}
+
+
 def hipcc():
     exe = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(exe):
@@ -37,7 +44,7 @@ def build(verbose=False, jobs=None):
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = [hipcc()] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc()] + FLAGS + EXTRA.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -40,9 +40,14 @@ pint_status check_stepper(const Plan& p, const pint_stepper* st) {
 // the next step's first half step.  Without the nonlinear term a step is the
 // two half steps alone.  out may alias in.
 pint_status imex_steps(Plan& p, const pint_stepper& st, const double* in, double* out, int B,
-                       int nsteps, hipStream_t s, const double* cf, double* corr) {
-  if (corr && (nsteps < 1 || !(st.terms & PINT_T_NL))) {
+                       int nsteps, hipStream_t s, const double* cf, double* corr, bool prepped,
+                       bool chain_out) {
+  if ((corr || prepped) && (nsteps < 1 || !(st.terms & PINT_T_NL))) {
     set_error("internal: a fused correction needs a nonlinear step");
+    return PINT_E_INVAL;
+  }
+  if (chain_out && !corr) {
+    set_error("internal: chaining a sweep step needs its correction");
     return PINT_E_INVAL;
   }
   if (nsteps == 0) {
@@ -57,7 +62,7 @@ pint_status imex_steps(Plan& p, const pint_stepper& st, const double* in, double
     for (int k = 0; k < nsteps; ++k) PINT_TRY(sp_cn(p, *f, st, &st, k ? out : in, out, B, s));
     return PINT_OK;
   }
-  PINT_TRY(sp_cn_prep(p, *f, st, in, B, s));
+  if (!prepped) PINT_TRY(sp_cn_prep(p, *f, st, in, B, s));
   for (int k = 0; k < nsteps; ++k) {
     PINT_TRY(legendre_synth(p, B, kSynFields, p.prec, s));
     PINT_TRY(ring_tendency(p, B, s));
@@ -67,7 +72,8 @@ pint_status imex_steps(Plan& p, const pint_stepper& st, const double* in, double
     PINT_TRY(ring_tendency(p, B, s));
     PINT_TRY(legendre_anal(p, B, kAnaFields, p.prec, s));
     const bool last = k + 1 == nsteps;
-    PINT_TRY(sp_stage2(p, *f, st, out, !last, B, s, last ? cf : nullptr, last ? corr : nullptr));
+    PINT_TRY(sp_stage2(p, *f, st, out, !last || chain_out, B, s, last ? cf : nullptr,
+                       last ? corr : nullptr));
   }
   return PINT_OK;
 }
@@ -213,12 +219,21 @@ struct CoarseProp {
   // out = (G - G_old) + f, with G = Phi_c(in).  Fused into the last
   // propagation kernel when the coarse level has the fine truncation;
   // otherwise propagation, pr_update and a copy.
+  // prepped: the previous step already made this step's first half step
+  // (it chained); chain_next: make the next step's.  *chained tells whether
+  // this step did.
+  bool fusable(const pint_stepper& st, int nsteps) const {
+    return same() && nsteps >= 1 && (st.terms & PINT_T_NL);
+  }
   pint_status sweep_step(const pint_stepper& st, int nsteps, const double* in, double* gold,
-                         const double* f, double* out, double* tmp, hipStream_t s) {
+                         const double* f, double* out, double* tmp, hipStream_t s,
+                         bool prepped = false, bool chain_next = false, bool* chained = nullptr) {
     const size_t sd = (size_t)3 * p.ncoef * 2;
-    if (same() && nsteps >= 1 && (st.terms & PINT_T_NL)) {
+    if (chained) *chained = false;
+    if (fusable(st, nsteps)) {
       SideWork sw(stepping());
-      return imex_steps(stepping(), st, in, gold, 1, nsteps, s, f, out);
+      if (chained) *chained = chain_next;
+      return imex_steps(stepping(), st, in, gold, 1, nsteps, s, f, out, prepped, chain_next);
     }
     PINT_TRY(run(st, nsteps, in, tmp, 1, s, true));
     PINT_TRY(pr_update(p, tmp, gold, f, out, sd, s));
@@ -439,6 +454,7 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
       {
         hipStream_t ss = p.side_stream;
         int waited = -1;
+        bool prepped = false;   // this step's first half step was made by the previous one
         for (int n = first; n < N; ++n) {
           int need = (n + 1 - first) / cs;
           if (need > nchunk - 1) need = nchunk - 1;
@@ -447,8 +463,11 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
             PINT_TRY(pr_update(p, Gold.p + n * sd, Gold.p + n * sd, Fv.p + n * sd,
                                U + (n + 1) * sd, sd, ss));
           } else {
+            bool chained = false;
             PINT_TRY(coarse.sweep_step(q->coarse, q->coarse_steps, U + n * sd, Gold.p + n * sd,
-                                       Fv.p + n * sd, U + (n + 1) * sd, Gtmp.p, ss));
+                                       Fv.p + n * sd, U + (n + 1) * sd, Gtmp.p, ss, prepped,
+                                       n + 1 < N, &chained));
+            prepped = chained;
             r->coarse_steps += q->coarse_steps;
           }
         }

@@ -198,10 +198,12 @@ pint_status check_stepper(const Plan& p, const pint_stepper* st);
 pint_status check_params(const Plan& p, const pint_pint_params* q);
 // With corr (needs nsteps >= 1 and the nonlinear term): out holds G_old on
 // entry and receives the result G, and corr = (G - G_old) + cf (a PinT
-// correction fused into the last step).
+// correction fused into the last step); chain_out: the last kernel also
+// makes the first half step of corr (the next sweep step), which a call
+// with prepped = true then starts from instead of `in`.
 pint_status imex_steps(Plan& p, const pint_stepper& st, const double* in, double* out, int B,
                        int nsteps, hipStream_t s, const double* cf = nullptr,
-                       double* corr = nullptr);
+                       double* corr = nullptr, bool prepped = false, bool chain_out = false);
 
 // transforms on the GEMM workspace
 // prec: PINT_FP64 (also used by the public scalar transforms) or PINT_LEG_FP32

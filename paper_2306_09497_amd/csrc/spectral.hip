@@ -397,9 +397,10 @@ __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_stage1(const SE* __restr
 // K_C (second explicit stage and the closing half step):
 // U = D_nu CN(Ua + dt/2 (N1 + N(Q))); chain = 0: out = U; chain = 1: the next
 // step's first half step follows at once: ua = CN(U), S = its synthesis input.
-// With a correction (corr != null, one state, chain = 0) the step is the
-// coarse propagation of a PinT sweep: out holds G_old on entry and receives
-// U, and corr = (U - G_old) + f, the update pr_update makes (bitwise).
+// With a correction (corr != null) the step is the coarse propagation of a
+// PinT sweep: out holds G_old on entry and receives U, and
+// corr = (U - G_old) + f, the update pr_update makes (bitwise); chain then
+// starts the next sweep step from corr.
 template <int SEG, typename SE>
 __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_stage2(const SE* __restrict__ Q,
                                                   double* __restrict__ ua,
@@ -425,13 +426,7 @@ __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_stage2(const SE* __restr
 #pragma unroll
     for (int f = 0; f < 3; ++f) V[k][f] = cadd(V[k][f], cscale(N[k][f], hdt));
   cn_lane<SEG>(V, w, sa.ncoef, c);                    // with the stepper's viscosity
-  if (chain) {
-    CnArgs c1 = c;
-    c1.nu = 0.0;
-    cn_lane<SEG>(V, w, sa.ncoef, c1);
-    store_state<SEG>(ua, w, sa.ncoef, V);
-    prep_lane<SEG>(V, w, sa.B, S, sa.rowoff, sa.a, sa.phibar);
-  } else if (corr) {
+  if (corr) {
 #pragma unroll
     for (int k = 0; k < SEG; ++k) {
       const int i = w.p0 + k;
@@ -440,12 +435,21 @@ __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_stage2(const SE* __restr
         for (int f = 0; f < 3; ++f) {
           const size_t at = ((size_t)w.b * 3 + f) * sa.ncoef + w.i0 + i;
           const double2 go = ld2(out, at), fv = ld2(cf, at);
-          st2(corr, at, cadd(csub(V[k][f], go), fv));
+          const double2 cv = cadd(csub(V[k][f], go), fv);
+          st2(corr, at, cv);
           st2(out, at, V[k][f]);
+          V[k][f] = cv;                 // a chained step continues from corr
         }
       }
     }
-  } else {
+  }
+  if (chain) {
+    CnArgs c1 = c;
+    c1.nu = 0.0;
+    cn_lane<SEG>(V, w, sa.ncoef, c1);
+    store_state<SEG>(ua, w, sa.ncoef, V);
+    prep_lane<SEG>(V, w, sa.B, S, sa.rowoff, sa.a, sa.phibar);
+  } else if (!corr) {
     store_state<SEG>(out, w, sa.ncoef, V);
   }
 }

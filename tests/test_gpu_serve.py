@@ -71,11 +71,14 @@ def serve(plans, reqs, steps_per_tick, arrivals=None, arena_states=4096, stage_s
     return outs, st, tick
 
 
-def test_alone_equals_pint_solve_bitwise(plans):
-    """One request at a time, chunks longer than any step count: the server
-    issues pint_solve's propagations, so the iterates agree bitwise."""
+@pytest.mark.parametrize("steps_per_tick", [1000, 3])
+def test_alone_equals_pint_solve_bitwise(plans, steps_per_tick):
+    """One request at a time: the iterates agree bitwise with pint_solve's,
+    with chunks longer than any step count (the same propagations) and with
+    chunks of 3 steps (a step chained into the previous one's last kernel
+    rounds exactly as a step of its own)."""
     for pi, prm, U0 in MIX:
-        outs, st, _ = serve(plans, [(pi, prm, U0)], steps_per_tick=1000)
+        outs, st, _ = serve(plans, [(pi, prm, U0)], steps_per_tick=steps_per_tick)
         ref = torch.zeros_like(outs[0])
         status, rep, _ = plans[pi].solve_status(prm, to_dev(U0, torch), ref)
         torch.cuda.synchronize()
