@@ -17,6 +17,9 @@ Gauss-Legendre nodes, dense LU) as the only building blocks:
                App. A).
 * ``pint``  -- Parareal (Sec. 3.1) and two-level MGRIT with F(CF)^nu
                relaxation and FAS coarse correction (Sec. 3.2).
+* ``sl``    -- the SL-SI-SETTLS step (Sec. 2.3.2) and its one-step variant
+               (Sec. 3.3): trajectories, bicubic interpolation, the
+               semi-implicit solve.
 * ``norms`` -- spectral (area-weighted) L2 norms and the paper's spectral
                max-norm error (Sec. 5).
 
@@ -25,4 +28,4 @@ not pinned by a test against closed forms, library routines or invariants says
 "parity unpinned" there.
 """
 
-from . import sht, swe, pint, norms  # noqa: F401
+from . import sht, swe, pint, norms, sl  # noqa: F401
