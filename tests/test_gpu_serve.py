@@ -178,3 +178,19 @@ def test_mixed_precision_plan_mix_equals_alone():
     assert 0.0 < d32 < d16 < 1e-3, (d32, d16)
     for p in pls:
         p.close()
+
+
+def test_diverging_request_fails_alone(plans):
+    """A request whose state holds a NaN is marked FAILED (PINT_E_DIVERGED)
+    after its first iteration; the requests served beside it, whose states
+    share its merged launches, finish with bitwise their results alone."""
+    pi, prm, U0 = MIX[0]
+    Ubad = U0.copy()
+    Ubad[1, 5] = np.nan
+    reqs = [MIX[0], (pi, prm, Ubad), MIX[3]]
+    mixed, st, _ = serve(plans, reqs, 3)
+    assert st[1].state == pint.REQ_FAILED and st[1].status == -4 and st[1].iters == 1
+    for i in (0, 2):
+        alone, _, _ = serve(plans, [reqs[i]], 3)
+        assert st[i].state == pint.REQ_DONE
+        assert torch.equal(mixed[i], alone[0]), i
