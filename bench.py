@@ -373,6 +373,66 @@ def measure_diagnostics(slices, reps=20):
     return out
 
 
+def measure_sl(reps=10):
+    """SL-SI-SETTLS coarse steps (Sec. 2.3.2) at T127 (384 x 192), dt = 1800 s,
+    second-order viscosity 1e5, two trajectory iterations: the coarse
+    configuration of the paper's SL runs.  Three steps per call (one slice),
+    the first in the one-step variant; batches of 5 instances and of 1 (the
+    serial sweep).  Grid-point kernels: algorithmic bytes per arrival point
+    and state = 17 doubles for the right-hand-side fields (10 read, 7
+    written) + 14 for the trajectories (4 arrival values, 7 gathered fields
+    once, 3 written)."""
+    import numpy as np
+    import torch
+    from paper_2306_09497_amd import pint, workloads
+
+    Mc, nlon, nlat = 127, 384, 192
+    plan = pint.Plan(Mc, nlon, nlat, phibar=PHIBAR, max_batch=10)
+    mu, _ = plan.grid_coords()
+    grids = [workloads.jet_bump_grid(mu, nlon, phibar=PHIBAR, **workloads.jet_bump_params(i))
+             for i in range(5)]
+    grid = torch.from_numpy(np.ascontiguousarray(np.stack(grids))).cuda()
+    u = torch.zeros((5, 3, plan.ncoef, 2), dtype=torch.float64, device="cuda")
+    plan.analysis(grid, u, 15)                       # 5 states x 3 fields
+    st = pint.sl_stepper(1800.0, 2, 2, 1.0e5)
+    imex = pint.stepper(1800.0, 2, 1.0e5, pint.T_ALL)
+    out = {}
+    o = torch.empty_like(u)
+    for B in (5, 1):
+        plan.sl_steps(st, u[:B], o[:B], B, 3)
+        torch.cuda.synchronize()
+        plan.profile(["sl_points"], min_batch=B)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            plan.sl_steps(st, u[:B], o[:B], B, 3)
+        t1.record()
+        torch.cuda.synchronize()
+        prof = plan.profile_read()
+        plan.profile([])
+        ms = t0.elapsed_time(t1) / (3 * reps)
+        rec = {"ms_per_step": ms, "state_steps_per_s": B / (ms * 1e-3)}
+        pk = prof.get(("sl_points", B))
+        if pk:
+            pms = pk[1] / pk[0]
+            byts = (17 + 14) * 8.0 * nlat * nlon * B
+            rec["grid_point_kernels_ms"] = pms
+            rec["grid_point_gbps_algorithmic"] = byts / (pms * 1e-3) / 1e9
+        plan.step(imex, u[:B], o[:B], B, 3)
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(reps):
+            plan.step(imex, u[:B], o[:B], B, 3)
+        t1.record()
+        torch.cuda.synchronize()
+        rec["imex_ms_per_step_same_dt"] = t0.elapsed_time(t1) / (3 * reps)
+        out["B%d" % B] = rec
+    out["config"] = "T127 384x192, dt 1800 s, q 2, nu 1e5, 2 trajectory iterations"
+    plan.close()
+    return out
+
+
 def serve_bench(seconds, rate, max_iter=2, seed=0, steps_per_tick=8, arena_gb=96.0,
                 precision=0, tol=0.0):
     """Serving with continuous batching: Poisson arrivals (rate per second for
@@ -511,6 +571,8 @@ def main():
                     help="skip the three-level MGRIT side measurement of the default run")
     ap.add_argument("--no-diagnostics", action="store_true",
                     help="skip the diagnostics and stability-map timings of the default run")
+    ap.add_argument("--no-sl", action="store_true",
+                    help="skip the SL-SI-SETTLS coarse-step timing of the default run")
     ap.add_argument("--time-to-tol", action="store_true",
                     help="print the T127 Parareal time-to-tolerance measurement instead")
     ap.add_argument("--serve", type=float, nargs=2, metavar=("SECONDS", "RATE"),
@@ -677,6 +739,11 @@ def main():
             out["diagnostics"] = measure_diagnostics(res["slices"])
         except Exception as e:                      # reported, not fatal
             out["diagnostics"] = {"error": str(e)}
+    if prec == pint.FP64 and not args.no_sl:
+        try:
+            out["sl_settls_t127"] = measure_sl()
+        except Exception as e:                      # reported, not fatal
+            out["sl_settls_t127"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -99,6 +99,18 @@ typedef struct {
   unsigned terms;
 } pint_stepper;
 
+/* One semi-Lagrangian semi-implicit SETTLS stepper (Sec. 2.3.2): step size
+ * dt, traj_iters fixed-point iterations of the departure-point estimate (eq.
+ * SETTLS_trajectories; 2 is the usual choice, 0 leaves the departure points
+ * at the arrival points), then backward-Euler viscosity of even order
+ * visc_order >= 2 and coefficient visc_nu >= 0 (Sec. 2.3).  */
+typedef struct {
+  double dt;
+  int traj_iters;
+  int visc_order;
+  double visc_nu;
+} pint_sl_stepper;
+
 typedef struct pint_plan pint_plan;
 
 typedef struct {
@@ -149,6 +161,45 @@ pint_status pint_implicit(pint_plan* plan, const pint_stepper* st, const double*
  * (n steps in one call equal n one-step calls), bitwise.  */
 pint_status pint_step(pint_plan* plan, const pint_stepper* st, const double* u_in, double* u_out,
                       int B, int nsteps, void* stream);
+
+/* nsteps SL-SI-SETTLS steps (Sec. 2.3.2, eqs. SETTLS_trajectories and
+ * SL_SI_SETTLS) of B independent states.  Each step traces the trajectories
+ * arriving at the Gauss grid points back to their departure points (in 3-D,
+ * with the velocity 2 V^n - V^{n-1} extrapolated to t_{n+1/2}), interpolates
+ * R_Phi = Phi' - dt/2 Phibar delta + dt/2 (2 N_R^n - N_R^{n-1}) and the wind
+ * R_V = V - dt/2 (grad Phi' + f k x V) there (bicubic on the Gauss grid,
+ * rows mirrored across the poles, vectors by Cartesian components turned into
+ * the arrival frame), adds dt/2 N_R^n at the arrival points and solves
+ * (I - dt/2 L) U^{n+1} = (R_Phi*, curl R_V*, div R_V*) per zonal
+ * wavenumber; N_R = -Phi' delta.
+ * u_prev = NULL: the first step is the one-step variant of Sec. 3.3 (U^{n-1}
+ * replaced by U^n); otherwise u_prev holds U^{n-1}.  Later steps use the
+ * two-step scheme.  out receives U^{n+nsteps}, and out_prev (if not NULL)
+ * U^{n+nsteps-1}, so that a later call can continue the two-step scheme.
+ * All state arrays are [B][3][ncoef][2] device memory; out and out_prev may
+ * alias u but not each other.  The plan must be PINT_FP64 with
+ * max_batch >= 2 (two states per trajectory are transformed together);
+ * larger B is processed in chunks of max_batch / 2.  Results for a state do
+ * not depend on B or the other states.  PINT_E_INVAL for bad arguments.  */
+pint_status pint_sl_steps(pint_plan* plan, const pint_sl_stepper* st, const double* u_prev,
+                          const double* u, double* out, double* out_prev, int B, int nsteps,
+                          void* stream);
+
+/* Parareal (Sec. 3.1) with the fine IMEX propagator (fine_steps steps of
+ * `fine` per slice, on `plan`) and an SL-SI-SETTLS coarse propagator
+ * (coarse_steps steps of `coarse` per slice, on coarse_plan, or on `plan`
+ * when coarse_plan is NULL; a coarse plan of lower truncation works on the
+ * truncated states and pads its results with zeros).  Each coarse
+ * propagation starts a slice and takes its first step in the one-step
+ * variant (Sec. 3.3).  n_iter iterations; iteration k recomputes slices
+ * k..N-1 only (slice k's input is converged).  u_slices [n_slices + 1]
+ * receives the slice-boundary states, u_slices[0] = u0.  Runs on `stream`
+ * alone; the coarse plan must be PINT_FP64 with max_batch >= 2 and share the
+ * planet and Phibar of `plan`.  */
+pint_status pint_parareal_sl(pint_plan* plan, const pint_stepper* fine, int fine_steps,
+                             pint_plan* coarse_plan, const pint_sl_stepper* coarse,
+                             int coarse_steps, int n_slices, int n_iter, const double* u0,
+                             double* u_slices, void* stream);
 
 /* Parallel-in-time solve of dU/dt = L U + N(U) on [0, n_intervals * DT].
  * method 0 = Parareal (Sec. 3.1): slices of length DT = fine.dt *
@@ -369,7 +420,8 @@ pint_status pint_server_clock(pint_server* server, double* t);
  * the record.  kind: 0 spectral prep, 1 Legendre synthesis GEMM, 2 ring
  * FFT + tendencies, 3 Legendre analysis GEMM, 4 tendency assembly + RK
  * combine, 5 Crank-Nicolson solve, 6 layout conversion, 7 PinT update and
- * norms, 8 scalar-transform rings.  out has room for cap entries; *n
+ * norms, 8 scalar-transform and semi-Lagrangian rings, 9 semi-Lagrangian
+ * grid-point kernels (trajectories and interpolation).  out has room for cap entries; *n
  * receives the number written.  */
 typedef struct {
   int kind;

@@ -97,31 +97,6 @@ static pint_status propagate(Plan& p, const pint_stepper& st, const double* in, 
 // than any before it, so repeated solves neither allocate nor synchronise on
 // frees.  Calls on one plan are ordered on their stream; a plan is not
 // shared between concurrent calls.
-struct DevBuf {
-  Plan& pl;
-  int slot;
-  double* p = nullptr;
-  DevBuf(Plan& plan, int s) : pl(plan), slot(s) {}
-  pint_status alloc(size_t n) {
-    if (pl.pool.size() <= (size_t)slot) pl.pool.resize(slot + 1, {nullptr, 0});
-    auto& b = pl.pool[slot];
-    if (b.second < n) {
-      if (b.first) (void)hipFree(b.first);
-      b = {nullptr, 0};
-      if (hipMalloc(&b.first, n * sizeof(double)) != hipSuccess) {
-        b.first = nullptr;
-        set_error("hipMalloc(%zu bytes) failed in pint_solve", n * sizeof(double));
-        return PINT_E_NOMEM;
-      }
-      b.second = n;
-    }
-    p = b.first;
-    return PINT_OK;
-  }
-};
-enum PoolSlot { kSlotGold, kSlotFv, kSlotUprev, kSlotGtmp, kSlotCin, kSlotCinSide, kSlotW,
-                kSlotFl, kSlotGl, kSlotTmp, kSlotF2, kSlotG2, kSlotGz };
-
 static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -627,6 +602,86 @@ pint_status pint_step(pint_plan* plan, const pint_stepper* st, const double* u_i
     return PINT_E_INVAL;
   }
   return propagate(plan->p, *st, u_in, u_out, B, nsteps, (hipStream_t)stream);
+}
+
+pint_status pint_sl_steps(pint_plan* plan, const pint_sl_stepper* st, const double* u_prev,
+                          const double* u, double* out, double* out_prev, int B, int nsteps,
+                          void* stream) {
+  API_GUARD(plan);
+  if (!st) {
+    set_error("null stepper");
+    return PINT_E_INVAL;
+  }
+  return sl_steps(plan->p, *st, u_prev, u, out, out_prev, B, nsteps, (hipStream_t)stream);
+}
+
+// Parareal (Sec. 3.1) with an SL-SI-SETTLS coarse propagator (Sec. 2.3.2):
+// every coarse propagation starts a slice, so its first step is the one-step
+// variant (Sec. 3.3).  Iteration k leaves slices n < k untouched (they are
+// converged), propagates slices k..N-1 with the fine IMEX steps as one batch
+// and sweeps U_{n+1} = (G(U_n) - G_old_n) + F_n serially (G at slice k is
+// unchanged, its input being converged).  All on one stream.
+pint_status pint_parareal_sl(pint_plan* plan, const pint_stepper* fine, int fine_steps,
+                             pint_plan* coarse_plan, const pint_sl_stepper* coarse,
+                             int coarse_steps, int n_slices, int n_iter, const double* u0,
+                             double* u_slices, void* stream) {
+  API_GUARD(plan);
+  if (!fine || !coarse || !u0 || !u_slices) {
+    set_error("null argument");
+    return PINT_E_INVAL;
+  }
+  Plan& p = plan->p;
+  Plan& pc = coarse_plan ? coarse_plan->p : p;
+  PINT_TRY(check_stepper(p, fine));
+  if (fine_steps < 1 || coarse_steps < 1 || n_slices < 1 || n_iter < 0) {
+    set_error("fine_steps, coarse_steps, n_slices must be >= 1 and n_iter >= 0");
+    return PINT_E_INVAL;
+  }
+  if (pc.M > p.M || pc.a != p.a || pc.omega != p.omega || pc.phibar != p.phibar) {
+    set_error("coarse plan must have M <= the fine M and the same planet and Phibar");
+    return PINT_E_INVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int N = n_slices;
+  const size_t sd = (size_t)3 * p.ncoef * 2, sdc = (size_t)3 * pc.ncoef * 2;
+  const size_t sb = sd * sizeof(double);
+  const bool trunc = pc.M != p.M;
+  DevBuf gold(p, kSlotPsGold), fv(p, kSlotPsFv), g(p, kSlotPsG), cin(p, kSlotPsCin),
+      cout_(p, kSlotPsCout);
+  PINT_TRY(gold.alloc(sd * N));
+  PINT_TRY(fv.alloc(sd * N));
+  PINT_TRY(g.alloc(sd));
+  if (trunc) {
+    PINT_TRY(cin.alloc(sdc));
+    PINT_TRY(cout_.alloc(sdc));
+  }
+  // G(x) -> y, one state
+  auto G = [&](const double* x, double* y) -> pint_status {
+    if (!trunc) return sl_steps(pc, *coarse, nullptr, x, y, nullptr, 1, coarse_steps, s);
+    PINT_TRY(spec_truncate(x, p.M, cin.p, pc.M, 1, s));
+    PINT_TRY(sl_steps(pc, *coarse, nullptr, cin.p, cout_.p, nullptr, 1, coarse_steps, s));
+    return spec_pad(cout_.p, pc.M, y, p.M, 1, s);
+  };
+  double* U = u_slices;
+  if (U != u0) PINT_HIP(hipMemcpyAsync(U, u0, sb, hipMemcpyDeviceToDevice, s));
+  for (int n = 0; n < N; ++n) {
+    PINT_TRY(G(U + n * sd, gold.p + n * sd));
+    PINT_HIP(hipMemcpyAsync(U + (n + 1) * sd, gold.p + n * sd, sb, hipMemcpyDeviceToDevice, s));
+  }
+  for (int k = 0; k < n_iter && k < N; ++k) {
+    PINT_TRY(propagate(p, *fine, U + k * sd, fv.p + k * sd, N - k, fine_steps, s));
+    for (int n = k; n < N; ++n) {
+      double* gn = gold.p + n * sd;
+      if (n > k) {
+        PINT_TRY(G(U + n * sd, g.p));
+        PINT_TRY(pr_update(p, g.p, gn, fv.p + n * sd, U + (n + 1) * sd, sd, s));
+        PINT_HIP(hipMemcpyAsync(gn, g.p, sb, hipMemcpyDeviceToDevice, s));
+      } else {
+        PINT_TRY(pr_update(p, gn, gn, fv.p + n * sd, U + (n + 1) * sd, sd, s));
+      }
+    }
+  }
+  return PINT_OK;
 }
 
 pint_status pint_solve(pint_plan* plan, const pint_pint_params* prm, const double* u0,

@@ -66,7 +66,7 @@ struct GemmTiles {       // (problem, row tile) list of one ragged batched GEMM
 
 enum ProfKind {
   PK_PREP = 0, PK_SYNTH, PK_RING, PK_ANAL, PK_ASSEMBLE, PK_CN, PK_LAYOUT, PK_PINT, PK_SRING,
-  PK_COUNT
+  PK_SL, PK_COUNT
 };
 
 struct ProfRec {
@@ -115,6 +115,7 @@ struct Plan {
   double* red = nullptr;       // reduction scratch
   double* diag = nullptr;      // L2-error partial sums [3 max_batch][nlat][2]
   double* h_red = nullptr;     // pinned host mirror
+  bool sl_lat_ready = false;   // extended latitudes of the SL interpolation uploaded
   size_t ws_bytes = 0;
   // device scratch of the PinT drivers, kept between calls and grown on
   // demand (slot -> buffer, doubles)
@@ -236,6 +237,43 @@ pint_status grid_l2_errors(Plan& p, const double* u, const double* ref, double* 
 // sums of squares over each ring of nspec / 2 synthesised pairs held in F:
 // part[pair][latitude][2]
 pint_status ring_sumsq(Plan& p, int nspec, double* part, hipStream_t s);
+
+// Device scratch kept in the plan between calls, grown on demand.
+struct DevBuf {
+  Plan& pl;
+  int slot;
+  double* p = nullptr;
+  DevBuf(Plan& plan, int s) : pl(plan), slot(s) {}
+  pint_status alloc(size_t n) {
+    if (pl.pool.size() <= (size_t)slot) pl.pool.resize(slot + 1, {nullptr, 0});
+    auto& b = pl.pool[slot];
+    if (b.second < n) {
+      if (b.first) (void)hipFree(b.first);
+      b = {nullptr, 0};
+      if (hipMalloc(&b.first, n * sizeof(double)) != hipSuccess) {
+        b.first = nullptr;
+        set_error("hipMalloc(%zu bytes) of solver scratch failed", n * sizeof(double));
+        return PINT_E_NOMEM;
+      }
+      b.second = n;
+    }
+    p = b.first;
+    return PINT_OK;
+  }
+};
+enum PoolSlot { kSlotGold, kSlotFv, kSlotUprev, kSlotGtmp, kSlotCin, kSlotCinSide, kSlotW,
+                kSlotFl, kSlotGl, kSlotTmp, kSlotF2, kSlotG2, kSlotGz, kSlotSlGrid, kSlotSlF,
+                kSlotSlO, kSlotSlLat, kSlotSlCur, kSlotSlPrev, kSlotPsGold, kSlotPsFv, kSlotPsG,
+                kSlotPsCin, kSlotPsCout };
+
+
+// Semi-Lagrangian SETTLS steps (Sec. 2.3.2, Sec. 3.3)
+pint_status ring_sl_grid(Plan& p, double* grid, int Bt, hipStream_t s);
+pint_status ring_sl_anal(Plan& p, const double* grid, int B, hipStream_t s);
+pint_status sp_sl_solve(Plan& p, const CnFactors& f, double dt, int visc_order, double visc_nu,
+                        double* out, int B, hipStream_t s);
+pint_status sl_steps(Plan& p, const pint_sl_stepper& st, const double* u_prev, const double* u,
+                     double* out, double* out_prev, int B, int nsteps, hipStream_t s);
 
 }  // namespace pint
 

@@ -1036,4 +1036,164 @@ pint_status scalar_analysis(Plan& p, const double* grid, double* spec, int B, hi
   return PINT_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Semi-Lagrangian step (Sec. 2.3.2): rings between the synthesised Fourier
+// coefficients and grid-point fields.
+// k_ring_sl_grid: the six synthesised fields of state b (record layout of the
+//   tendency path) -> grid[b][o][j][k] for o = delta, Phi', G = (1-mu^2)
+//   dPhi'/dmu, dPhi'/dlambda, U = u cos(lat), V = v cos(lat); three pairs of
+//   real signals through one complex FFT each.
+// k_ring_sl_anal: grid[b][g][j][k] for g = (R_Phi, A, B) -> ring-output
+//   records (N_Phi <- R_Phi, K <- 0, A, B) scaled by w_j / nlon, the layout
+//   the analysis GEMM and the tendency assembly read.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(kRingThreads) void k_ring_sl_grid(const double* __restrict__ F,
+                                                               double* __restrict__ grid,
+                                                               const double2* __restrict__ tw,
+                                                               int M, int nlat, int Bt) {
+  constexpr int nlon = N;
+  using L = RingLds<N>;
+  extern __shared__ double2 zb[];
+  __shared__ double red[kRingWaves * 6];
+  const int j = blockIdx.x, b = blockIdx.y;
+  const int ncs = 12 * Bt;
+  const size_t fstride = fourier_pitch<double>(nlat, ncs);
+  const double* rec = F + (size_t)j * ncs + (size_t)b * 12;
+  // pair s: (X, Y) = (delta, Phi'), (G, i m Phi'), (U, V)
+  auto coef = [&](int m, int s, double2* X, double2* Y) {
+    const double* r = rec + m * fstride;
+    if (s == 0) {
+      *X = *reinterpret_cast<const double2*>(r + 2);
+      *Y = *reinterpret_cast<const double2*>(r + 4);
+    } else if (s == 1) {
+      *X = *reinterpret_cast<const double2*>(r + 6);
+      const double2 ph = *reinterpret_cast<const double2*>(r + 4);
+      *Y = make_double2(-m * ph.y, m * ph.x);
+    } else {
+      *X = *reinterpret_cast<const double2*>(r + 8);
+      *Y = *reinterpret_cast<const double2*>(r + 10);
+    }
+  };
+  double nrm[6] = {0, 0, 0, 0, 0, 0};
+  for (int m = threadIdx.x; m <= M; m += kRingThreads) {
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      double2 x, y;
+      coef(m, s, &x, &y);
+      nrm[2 * s] += x.x * x.x + x.y * x.y;
+      nrm[2 * s + 1] += y.x * y.x + y.y * y.y;
+    }
+  }
+  block_sum<6>(nrm, red, threadIdx.x);
+  double sc[3];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) sc[s] = pair_scale(nrm[2 * s], nrm[2 * s + 1]);
+  for (int i = threadIdx.x; i < 3 * L::SP; i += kRingThreads) zb[i] = make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int m = threadIdx.x; m <= M; m += kRingThreads) {
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      double2 x, y;
+      coef(m, s, &x, &y);
+      put_pair<N>(zb, s, m, x, c_scl(y, sc[s]));
+    }
+  }
+  __syncthreads();
+  fft_lds<N, 3>(zb, 1.0, tw, threadIdx.x);
+  const size_t plane = (size_t)nlat * nlon;
+  double* out = grid + (size_t)b * 6 * plane + (size_t)j * nlon;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const double isc = 1.0 / sc[s];
+    for (int k = threadIdx.x; k < nlon; k += kRingThreads) {
+      const double2 z = zb[L::at(s, k)];
+      out[(2 * s) * plane + k] = z.x;
+      out[(2 * s + 1) * plane + k] = z.y * isc;
+    }
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(kRingThreads) void k_ring_sl_anal(const double* __restrict__ grid,
+                                                               double* __restrict__ Gout,
+                                                               const double* __restrict__ w,
+                                                               const double2* __restrict__ tw,
+                                                               int M, int nlat, int B) {
+  constexpr int nlon = N;
+  using L = RingLds<N>;
+  extern __shared__ double2 zb[];
+  __shared__ double red[kRingWaves * 2];
+  const int j = blockIdx.x, b = blockIdx.y;
+  const size_t plane = (size_t)nlat * nlon;
+  const double* g = grid + (size_t)b * 3 * plane + (size_t)j * nlon;
+  const double sc = w[j] / nlon;
+  double nrm[2] = {0, 0};
+  for (int k = threadIdx.x; k < nlon; k += kRingThreads) {
+    const double x = g[k], y = g[plane + k];
+    nrm[0] += x * x;
+    nrm[1] += y * y;
+  }
+  block_sum<2>(nrm, red, threadIdx.x);
+  const double s0 = pair_scale(nrm[0], nrm[1]);
+  for (int k = threadIdx.x; k < nlon; k += kRingThreads) {
+    zb[L::at(0, k)] = make_double2(g[k] * sc, g[plane + k] * s0 * sc);
+    zb[L::at(1, k)] = make_double2(g[2 * plane + k] * sc, 0.0);
+  }
+  __syncthreads();
+  fft_lds<N, 2>(zb, -1.0, tw, threadIdx.x);
+  const int ncg = 8 * B;
+  const double is0 = 1.0 / s0;
+  for (int m = threadIdx.x; m <= M; m += kRingThreads) {
+    double2 X, Y, Z, D;
+    get_pair<N>(zb, 0, m, &X, &Y);
+    get_pair<N>(zb, 1, m, &Z, &D);
+    double2* r = reinterpret_cast<double2*>(Gout + m * fourier_pitch<double>(nlat, ncg) +
+                                            (size_t)j * ncg + (size_t)b * 8);
+    r[0] = X;
+    r[1] = make_double2(0.0, 0.0);
+    r[2] = c_scl(Y, is0);
+    r[3] = Z;
+  }
+}
+
+pint_status ring_sl_grid(Plan& p, double* grid, int Bt, hipStream_t s) {
+  ProfScope ps(p, PK_SRING, Bt, s);
+  switch (p.nlon) {
+#define PINT_CASE(n)                                                                            \
+  case n:                                                                                       \
+    hipLaunchKernelGGL(k_ring_sl_grid<n>, dim3(p.nlat, Bt), dim3(kRingThreads),                 \
+                       (size_t)3 * RingLds<n>::SP * sizeof(double2), s, p.F, grid, p.twid, p.M, \
+                       p.nlat, Bt);                                                             \
+    break;
+    PINT_FOR_EACH_NLON(PINT_CASE)
+#undef PINT_CASE
+    default:
+      set_error("no ring FFT for nlon=%d", p.nlon);
+      return PINT_E_INVAL;
+  }
+  PINT_HIP(hipGetLastError());
+  return PINT_OK;
+}
+
+pint_status ring_sl_anal(Plan& p, const double* grid, int B, hipStream_t s) {
+  ProfScope ps(p, PK_SRING, B, s);
+  switch (p.nlon) {
+#define PINT_CASE(n)                                                                            \
+  case n:                                                                                       \
+    hipLaunchKernelGGL(k_ring_sl_anal<n>, dim3(p.nlat, B), dim3(kRingThreads),                  \
+                       (size_t)2 * RingLds<n>::SP * sizeof(double2), s, grid, p.G, p.w, p.twid, \
+                       p.M, p.nlat, B);                                                         \
+    break;
+    PINT_FOR_EACH_NLON(PINT_CASE)
+#undef PINT_CASE
+    default:
+      set_error("no ring FFT for nlon=%d", p.nlon);
+      return PINT_E_INVAL;
+  }
+  PINT_HIP(hipGetLastError());
+  return PINT_OK;
+}
+
 }  // namespace pint

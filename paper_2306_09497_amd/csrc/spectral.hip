@@ -143,6 +143,9 @@ struct CnArgs {
   const double2 *alph, *gam, *invpiv;
   double a, W, lgf, pb, alpha, vdt, nu;
   int q;
+  // the right-hand side is given (semi-Lagrangian step): solve
+  // (I - alpha L) x = y instead of (I - alpha L) x = (I + alpha L) y
+  int rhs_given;
 };
 
 template <int SEG>
@@ -174,9 +177,10 @@ __device__ inline void cn_lane(double2 (&V)[SEG][3], const WaveAt& w, int ncoef,
         axi = cadd(axi, cscale(dep, C));
         ade = csub(ade, cscale(xip, C));
       }
-      const double2 rxi = cadd(yxi, cscale(axi, c.alpha));
-      const double2 rde = cadd(yde, cscale(ade, c.alpha));
-      rphi[k] = csub(yphi, cscale(yde, c.alpha * c.pb));
+      const double ex = c.rhs_given ? 0.0 : c.alpha;
+      const double2 rxi = cadd(yxi, cscale(axi, ex));
+      const double2 rde = cadd(yde, cscale(ade, ex));
+      rphi[k] = csub(yphi, cscale(yde, ex * c.pb));
       const double2 rdp = cadd(rde, cscale(rphi[k], c.alpha * lap));
       rv[0][k] = xi_on_chain0(i) ? rxi : rdp;
       rv[1][k] = xi_on_chain0(i) ? rdp : rxi;
@@ -491,6 +495,24 @@ __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_cn(const double* __restr
   store_state<SEG>(out, w, sa.ncoef, V);
 }
 
+// Semi-Lagrangian step (Sec. 2.3.2, eq. SL_SI_SETTLS): the analysed
+// departure-point right-hand side (R_Phi*, curl R_V*, div R_V*) -> U^{n+1}
+// solving (I - dt/2 L) U^{n+1} = rhs, then the viscosity.  Q holds the
+// analysis of (R_Phi*, K = 0, A, B) with (A, B) = (-v*, u*) / cos(lat), so
+// that the assembly's (-div, curl) of (A, B) is (curl, div) of (u*, v*).
+template <int SEG>
+__global__ __launch_bounds__(64 * kSpecWaves) void k_sp_sl_solve(const double* __restrict__ Q,
+                                                    double* __restrict__ out, SpecArgs sa,
+                                                    CnArgs c) {
+  const WaveAt w = wave_at<SEG>(sa.M, sa.B);
+  if (w.b >= sa.B) return;                            // uniform per wave
+  double2 V[SEG][3];
+  asm_lane<SEG, double>(Q, sa.rowoff, w, sa.B, sa.a, V);
+  if (w.m == 0 && w.lane == 0) V[0][0].x += sa.phibar;   // Phi = Phibar + Phi'
+  cn_lane<SEG>(V, w, sa.ncoef, c);
+  store_state<SEG>(out, w, sa.ncoef, V);
+}
+
 // ---- launchers ----
 static int seg_of(int M) {
   const int K = M + 1;
@@ -527,6 +549,7 @@ static CnArgs cn_args(const Plan& p, const CnFactors& f, const pint_stepper& st,
   c.vdt = st.dt;
   c.nu = (visc && (st.terms & PINT_T_VISC)) ? st.visc_nu : 0.0;
   c.q = st.visc_order;
+  c.rhs_given = 0;
   return c;
 }
 
@@ -803,6 +826,31 @@ pint_status spec_pad(const double* in, int Mc, double* out, int Mf, int B, hipSt
   if (B <= 0) return PINT_OK;
   const dim3 grid((unsigned)((Mf + 64) / 64), (unsigned)(Mf + 1), (unsigned)(3 * B));
   hipLaunchKernelGGL(k_pad, grid, dim3(64), 0, s, in, out, Mc, Mf);
+  PINT_HIP(hipGetLastError());
+  return PINT_OK;
+}
+
+pint_status sp_sl_solve(Plan& p, const CnFactors& f, double dt, int visc_order, double visc_nu,
+                        double* out, int B, hipStream_t s) {
+  ProfScope ps(p, PK_CN, B, s);
+  const SpecArgs sa = spec_args(p, B);
+  pint_stepper st{2.0 * dt, visc_order, visc_nu, PINT_T_ALL};
+  CnArgs c = cn_args(p, f, st, true);      // alpha = (2 dt) / 4 = dt / 2
+  c.vdt = dt;
+  c.rhs_given = 1;
+  const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
+  switch (seg_of(p.M)) {
+#define L(SEG)                                                                              \
+  case SEG:                                                                                 \
+    hipLaunchKernelGGL((k_sp_sl_solve<SEG>), grid, dim3(spec_threads(B)), 0, s, p.Q, out, sa, \
+                       c);                                                                  \
+    break;
+    L(1) L(2) L(4) L(8)
+#undef L
+    default:
+      set_error("chains longer than 512 coefficients are not supported (M=%d)", p.M);
+      return PINT_E_INVAL;
+  }
   PINT_HIP(hipGetLastError());
   return PINT_OK;
 }

@@ -24,7 +24,7 @@ STATUS = {0: "PINT_OK", -1: "PINT_E_INVAL", -2: "PINT_E_NOMEM", -3: "PINT_E_HIP"
 
 EXPORTS = ["pint_plan_create", "pint_plan_destroy", "pint_plan_info", "pint_grid_coords",
            "pint_synthesis", "pint_analysis", "pint_tendency", "pint_implicit", "pint_step",
-           "pint_solve", "pint_rel_diff", "pint_ke_spectrum", "pint_spectral_errors",
+           "pint_sl_steps", "pint_parareal_sl", "pint_solve", "pint_rel_diff", "pint_ke_spectrum", "pint_spectral_errors",
            "pint_grid_l2_errors", "pint_stability_map", "pint_server_create", "pint_server_destroy",
            "pint_server_submit", "pint_server_tick", "pint_server_status", "pint_server_clock",
            "pint_profile_enable", "pint_profile_read", "pint_last_error"]
@@ -32,7 +32,7 @@ EXPORTS = ["pint_plan_create", "pint_plan_destroy", "pint_plan_info", "pint_grid
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
 PROF_KINDS = ["prep", "legendre_synth", "ring_tendency", "legendre_anal", "assemble_rk",
-              "cn_solve", "layout", "pint_ops", "scalar_ring"]
+              "cn_solve", "layout", "pint_ops", "scalar_ring", "sl_points"]
 
 
 class Config(ctypes.Structure):
@@ -181,6 +181,15 @@ def stepper(dt, visc_order=2, visc_nu=0.0, terms=T_ALL):
     return Stepper(float(dt), int(visc_order), float(visc_nu), int(terms))
 
 
+class SlStepper(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("traj_iters", ctypes.c_int),
+                ("visc_order", ctypes.c_int), ("visc_nu", ctypes.c_double)]
+
+
+def sl_stepper(dt, traj_iters=2, visc_order=2, visc_nu=0.0):
+    return SlStepper(float(dt), int(traj_iters), int(visc_order), float(visc_nu))
+
+
 class Plan:
     """A truncation / grid / planet and the device tables and workspace.
 
@@ -244,6 +253,19 @@ class Plan:
     def step(self, st, u_in, u_out, B, nsteps, stream=None):
         _check(load().pint_step(self._h, ctypes.byref(st), _ptr(u_in), _ptr(u_out), int(B),
                                 int(nsteps), _stream(stream)))
+
+    def sl_steps(self, st, u, out, B, nsteps, u_prev=None, out_prev=None, stream=None):
+        """nsteps SL-SI-SETTLS steps; u_prev None = one-step first step."""
+        _check(load().pint_sl_steps(self._h, ctypes.byref(st), _ptr(u_prev), _ptr(u), _ptr(out),
+                                    _ptr(out_prev), int(B), int(nsteps), _stream(stream)))
+
+    def parareal_sl(self, fine, fine_steps, coarse, coarse_steps, n_slices, n_iter, u0, u_slices,
+                    coarse_plan=None, stream=None):
+        """Parareal with an SL-SI-SETTLS coarse propagator (fine: IMEX stepper)."""
+        cp = None if coarse_plan is None else coarse_plan._h
+        _check(load().pint_parareal_sl(self._h, ctypes.byref(fine), int(fine_steps), cp,
+                                       ctypes.byref(coarse), int(coarse_steps), int(n_slices),
+                                       int(n_iter), _ptr(u0), _ptr(u_slices), _stream(stream)))
 
     def solve(self, params, u0, u_slices, stream=None):
         rep = Report()

@@ -1,0 +1,170 @@
+"""GPU parity of the SL-SI-SETTLS steps (Sec. 2.3.2, one-step variant of
+Sec. 3.3) against the FP64 oracle, through the C ABI.  Bar: the FP64 parity
+bar of the IMEX path (relative L2 1e-11 on Phi' and the wind)."""
+
+import numpy as np
+import pytest
+
+from gpu_util import assert_parity, from_dev, to_dev
+from oracle import sl
+from oracle.swe import Model
+from paper_2306_09497_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2306_09497_amd import pint  # noqa: E402
+
+PHIBAR = 9.80616e4
+CONFIGS = {"T21": (21, 64, 32), "T42": (42, 128, 64), "T127": (127, 384, 192)}
+_cache = {}
+
+
+def setup(key, max_batch=8):
+    k = (key, max_batch)
+    if k not in _cache:
+        M, nlon, nlat = CONFIGS[key]
+        _cache[k] = (Model(M, nlon, nlat, phibar=PHIBAR),
+                     pint.Plan(M, nlon, nlat, phibar=PHIBAR, max_batch=max_batch))
+    return _cache[k]
+
+
+def states(md, n, seed):
+    """Jet-and-bump flows (the paper's unstable jet, seeded bump longitudes)
+    with a little white noise: smooth, strongly advective initial states."""
+    out = []
+    for i in range(n):
+        G = workloads.jet_bump_grid(md.grid.mu, md.grid.nlon, phibar=PHIBAR, amp=120.0,
+                                    lam_c=0.3 + 1.7 * i)
+        U = np.stack([md.grid.anal(G[f]) for f in range(3)])
+        out.append(workloads.white_noise(md.M, U, 1e-3, seed + i))
+    return np.stack(out)
+
+
+def run(plan, st, U, nsteps, Uprev=None, want_prev=False):
+    B = U.shape[0]
+    u = to_dev(U, torch)
+    out = torch.empty_like(u)
+    prev = torch.empty_like(u) if want_prev else None
+    plan.sl_steps(st, u, out, B, nsteps, u_prev=None if Uprev is None else to_dev(Uprev, torch),
+                  out_prev=prev)
+    torch.cuda.synchronize()
+    return (out, prev) if want_prev else out
+
+
+@pytest.mark.parametrize("key,dt,iters", [("T21", 1800.0, 2), ("T21", 3600.0, 0),
+                                          ("T42", 900.0, 3)])
+def test_one_step_variant(key, dt, iters):
+    md, plan = setup(key)
+    U = states(md, 3, 10)
+    got = from_dev(run(plan, pint.sl_stepper(dt, iters), U, 1))
+    ost = sl.SLStepper(md, dt, iters=iters)
+    for b in range(3):
+        assert_parity(got[b], ost.step(U[b]), md.M)
+
+
+def test_two_step_scheme_and_continuation():
+    """Three two-step steps from (U^{n-1}, U^n) with viscosity; out_prev
+    continues the scheme: 2 + 1 steps equal 3 steps bitwise."""
+    md, plan = setup("T21")
+    U = states(md, 3, 20)
+    Up = states(md, 3, 30)
+    st = pint.sl_stepper(1200.0, 2, 2, 1e5)
+    got, gprev = run(plan, st, U, 3, Uprev=Up, want_prev=True)
+    ost = sl.SLStepper(md, 1200.0, nu=1e5, q=2, iters=2)
+    for b in range(3):
+        want, wprev = ost.propagate(U[b], 3, Up[b])
+        assert_parity(from_dev(got)[b], want, md.M)
+        assert_parity(from_dev(gprev)[b], wprev, md.M)
+    two, tprev = run(plan, st, U, 2, Uprev=Up, want_prev=True)
+    u3 = torch.empty_like(two)
+    plan.sl_steps(st, two, u3, 3, 1, u_prev=tprev)
+    torch.cuda.synchronize()
+    assert torch.equal(u3, got)
+
+
+def test_batch_invariance_and_chunks():
+    """B = 5 on a plan of max_batch 4 (chunks of 2): each state's result is
+    bitwise the one it gets alone."""
+    md, plan = setup("T21", max_batch=4)
+    U = states(md, 5, 40)
+    st = pint.sl_stepper(1800.0)
+    allb = run(plan, st, U, 2)
+    for b in range(5):
+        assert torch.equal(run(plan, st, U[b:b + 1], 2)[0], allb[b])
+
+
+def test_t127_coarse_configuration():
+    """The coarse SL configuration of the paper's two-level runs: T127,
+    dt = 1800 s, second-order viscosity 1e5, five instances, three steps."""
+    md, plan = setup("T127")
+    U = states(md, 5, 50)
+    st = pint.sl_stepper(1800.0, 2, 2, 1e5)
+    got = from_dev(run(plan, st, U, 3))
+    ost = sl.SLStepper(md, 1800.0, nu=1e5, q=2, iters=2)
+    for b in (0, 4):
+        want, _ = ost.propagate(U[b], 3)
+        assert_parity(got[b], want, md.M)
+
+
+def test_rejected_arguments():
+    md, plan = setup("T21")
+    u = to_dev(states(md, 1, 60), torch)
+    with pytest.raises(pint.PintError):
+        plan.sl_steps(pint.sl_stepper(-1.0), u, u, 1, 1)
+    with pytest.raises(pint.PintError):
+        plan.sl_steps(pint.sl_stepper(60.0, 2, 3), u, u, 1, 1)
+    with pytest.raises(pint.PintError):
+        plan.sl_steps(pint.sl_stepper(60.0, 65), u, u, 1, 1)
+    small = pint.Plan(21, 64, 32, phibar=PHIBAR, max_batch=1)
+    with pytest.raises(pint.PintError):
+        small.sl_steps(pint.sl_stepper(60.0), u, u, 1, 1)
+    f32 = pint.Plan(21, 64, 32, phibar=PHIBAR, max_batch=4, precision=pint.LEG_FP32)
+    with pytest.raises(pint.PintError):
+        f32.sl_steps(pint.sl_stepper(60.0), u, u, 1, 1)
+    # zero steps copy the state (and the previous one)
+    out = torch.empty_like(u)
+    prev = torch.empty_like(u)
+    plan.sl_steps(pint.sl_stepper(60.0), u, out, 1, 0, out_prev=prev)
+    torch.cuda.synchronize()
+    assert torch.equal(out, u) and torch.equal(prev, u)
+
+
+@pytest.mark.parametrize("fine_key,coarse_key", [("T21", None), ("T42", "T21")])
+def test_parareal_with_sl_coarse(fine_key, coarse_key):
+    """Parareal (Sec. 3.1), fine IMEX, coarse SL-SI-SETTLS (one-step variant
+    at every slice start), 4 slices, 3 iterations, against the oracle's
+    Parareal with the same propagators (the coarse one on the truncated
+    state, padded back)."""
+    from oracle import pint as opint
+    from oracle.sht import pad, truncate
+    md, plan = setup(fine_key)
+    N, fsteps, csteps, dtf, dtc = 4, 8, 2, 225.0, 900.0
+    U0 = states(md, 1, 70)[0]
+    fine = pint.stepper(dtf, 2, 1e5, pint.T_ALL)
+    coarse = pint.sl_stepper(dtc, 2, 2, 1e6)
+    if coarse_key is None:
+        mdc, cplan = md, None
+    else:
+        mdc, cplan = setup(coarse_key)
+    ost = sl.SLStepper(mdc, dtc, nu=1e6, q=2, iters=2)
+
+    def G(U):
+        Uc = np.stack([truncate(U[f], md.M, mdc.M) for f in range(3)])
+        Vc, _ = ost.propagate(Uc, csteps)
+        return np.stack([pad(Vc[f], mdc.M, md.M) for f in range(3)])
+
+    def F(U):
+        return md.propagate(U, dtf, fsteps, nu=1e5, q=2)
+
+    want, _ = opint.parareal(U0, N, F, G, 3)
+    slices = torch.zeros((N + 1, 3, md.grid.nc, 2), dtype=torch.float64, device="cuda")
+    plan.parareal_sl(fine, fsteps, coarse, csteps, N, 3, to_dev(U0, torch), slices,
+                     coarse_plan=cplan)
+    torch.cuda.synchronize()
+    got = from_dev(slices)
+    for n in range(N + 1):
+        assert_parity(got[n], want[n], md.M)
