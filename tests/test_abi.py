@@ -73,3 +73,15 @@ def test_server_and_diagnostics_argument_checks():
     assert lib.pint_ke_spectrum(None, None, None, 1, None) == -1
     assert lib.pint_spectral_errors(None, None, None, None, 1, None) == -1
     assert lib.pint_grid_l2_errors(None, None, None, None, 1, None) == -1
+
+
+def test_sl_entry_points_reject_a_null_plan():
+    from paper_2306_09497_amd import pint
+    lib = pint.load()
+    st = pint.sl_stepper(900.0)
+    assert lib.pint_sl_steps(None, ctypes.byref(st), None, None, None, None, 1, 1, None) == -1
+    assert b"null plan" in lib.pint_last_error()
+    fine = pint.stepper(60.0)
+    assert lib.pint_parareal_sl(None, ctypes.byref(fine), 4, None, ctypes.byref(st), 1, 4, 2,
+                                None, None, None) == -1
+    assert b"null plan" in lib.pint_last_error()
