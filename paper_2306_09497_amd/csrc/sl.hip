@@ -124,21 +124,23 @@ __device__ inline double interp(const double* __restrict__ f, const Stencil& st)
   return acc;
 }
 
-// Grid-point right-hand sides at t_n (state b; U^{n-1} is state B + b when
-// `two`, else U^n itself):
+// Grid-point right-hand sides at t_n.  The synthesised states are two halves
+// of B states: U^n of state b is in half `cur`, U^{n-1} in the other half
+// when `two`, else U^n itself:
 //   f7[0..2] = 2 V^n - V^{n-1}   (Cartesian, m/s)
 //   f7[3]    = R_Phi = Phi' - dt/2 Phibar delta + dt/2 (2 N_R^n - N_R^{n-1})
 //   f7[4..6] = R_V = V - dt/2 (grad Phi' + f k x V)   (Cartesian)
 __global__ __launch_bounds__(kSlThreads) void k_sl_fields(const double* __restrict__ g6,
                                                           double* __restrict__ f7, SlGeom g,
-                                                          int B, int two) {
+                                                          int B, int two, int cur) {
   const int npts = g.nlat * g.nlon;
   const int pt = blockIdx.x * kSlThreads + threadIdx.x;
   if (pt >= npts) return;
   const int b = blockIdx.y;
   const int j = pt / g.nlon, k = pt - j * g.nlon;
-  const double* gn = g6 + (size_t)b * 6 * npts + pt;
-  const double* gp = g6 + (size_t)(two ? B + b : b) * 6 * npts + pt;
+  const int bn = cur * B + b;
+  const double* gn = g6 + (size_t)bn * 6 * npts + pt;
+  const double* gp = g6 + (size_t)(two ? (1 - cur) * B + b : bn) * 6 * npts + pt;
   const double de = gn[0], ph = gn[npts], G = gn[2 * npts], Pl = gn[3 * npts];
   const double ic = 1.0 / sqrt(g.c2[j]), cs = sqrt(g.c2[j]), sn = g.mu[j];
   const double u = gn[4 * npts] * ic, v = gn[5 * npts] * ic;
@@ -170,11 +172,16 @@ __global__ __launch_bounds__(kSlThreads) void k_sl_fields(const double* __restri
 __global__ __launch_bounds__(kSlThreads) void k_sl_points(const double* __restrict__ g6,
                                                           const double* __restrict__ f7,
                                                           double* __restrict__ o3, SlGeom g,
-                                                          int iters) {
+                                                          int iters, int B, int cur) {
   const int npts = g.nlat * g.nlon;
-  const int pt = blockIdx.x * kSlThreads + threadIdx.x;
+  // one-dimensional grid of (state, point block) remapped so that every XCD
+  // works through one contiguous range: the 16-point gathers of neighbouring
+  // arrival points then hit the same L2
+  const int nblk = (npts + kSlThreads - 1) / kSlThreads;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = lb / nblk;
+  const int pt = (lb - b * nblk) * kSlThreads + threadIdx.x;
   if (pt >= npts) return;
-  const int b = blockIdx.y;
   const int j = pt / g.nlon, k = pt - j * g.nlon;
   const double cs = sqrt(g.c2[j]), sn = g.mu[j], ic = 1.0 / cs;
   double sl, cl;
@@ -182,7 +189,7 @@ __global__ __launch_bounds__(kSlThreads) void k_sl_points(const double* __restri
   const double xa[3] = {cs * cl, cs * sl, sn};
   const double ea[3] = {-sl, cl, 0.0};
   const double no[3] = {-sn * cl, -sn * sl, cs};
-  const double* gn = g6 + (size_t)b * 6 * npts;
+  const double* gn = g6 + (size_t)(cur * B + b) * 6 * npts;
   const double u = gn[4 * npts + pt] * ic, v = gn[5 * npts + pt] * ic;
   double vn[3];
 #pragma unroll
@@ -275,12 +282,10 @@ pint_status sl_steps(Plan& p, const pint_sl_stepper& st, const double* u_prev, c
   }
   const int nbmax = p.max_batch / 2;
   const size_t npts = (size_t)p.nlat * p.nlon;
-  DevBuf grid(p, kSlotSlGrid), f7(p, kSlotSlF), o3(p, kSlotSlO), lat(p, kSlotSlLat),
-      cur(p, kSlotSlCur);
+  DevBuf grid(p, kSlotSlGrid), f7(p, kSlotSlF), o3(p, kSlotSlO), lat(p, kSlotSlLat);
   PINT_TRY(grid.alloc((size_t)2 * nbmax * 6 * npts));
   PINT_TRY(f7.alloc((size_t)nbmax * 7 * npts));
   PINT_TRY(o3.alloc((size_t)nbmax * 3 * npts));
-  PINT_TRY(cur.alloc((size_t)nbmax * sd));
   PINT_TRY(lat.alloc((size_t)p.nlat + 4));
   if (!p.sl_lat_ready) {
     std::vector<double> mu(p.nlat), lx(p.nlat + 4);
@@ -300,11 +305,14 @@ pint_status sl_steps(Plan& p, const pint_sl_stepper& st, const double* u_prev, c
   SlGeom g{p.mu, p.c2, lat.p, p.nlat, p.nlon, p.a, p.omega, p.phibar, 0.5 * st.dt};
   for (int b0 = 0; b0 < B; b0 += nbmax) {
     const int nb = (B - b0) < nbmax ? (B - b0) : nbmax;
-    double* now = p.Ua;                       // [U^n (nb) | U^{n-1} (nb)]
-    double* prev = p.Ua + (size_t)nb * sd;
-    PINT_HIP(hipMemcpyAsync(now, u + b0 * sd, nb * sb, hipMemcpyDeviceToDevice, s));
+    // two halves of nb states: U^n in half `cur`, U^{n-1} in the other; a
+    // step writes U^{n+1} over U^{n-1} and flips `cur` (no copies)
+    double* half[2] = {p.Ua, p.Ua + (size_t)nb * sd};
+    int cur = 0;
+    PINT_HIP(hipMemcpyAsync(half[0], u + b0 * sd, nb * sb, hipMemcpyDeviceToDevice, s));
     bool two = u_prev != nullptr;
-    if (two) PINT_HIP(hipMemcpyAsync(prev, u_prev + b0 * sd, nb * sb, hipMemcpyDeviceToDevice, s));
+    if (two)
+      PINT_HIP(hipMemcpyAsync(half[1], u_prev + b0 * sd, nb * sb, hipMemcpyDeviceToDevice, s));
     for (int step = 0; step < nsteps; ++step) {
       const bool last = step == nsteps - 1;
       const int nt = two ? 2 * nb : nb;
@@ -315,21 +323,21 @@ pint_status sl_steps(Plan& p, const pint_sl_stepper& st, const double* u_prev, c
         ProfScope ps(p, PK_SL, nb, s);
         const dim3 lg((unsigned)((npts + kSlThreads - 1) / kSlThreads), (unsigned)nb);
         hipLaunchKernelGGL(k_sl_fields, lg, dim3(kSlThreads), 0, s, grid.p, f7.p, g, nb,
-                           two ? 1 : 0);
-        hipLaunchKernelGGL(k_sl_points, lg, dim3(kSlThreads), 0, s, grid.p, f7.p, o3.p, g,
-                           st.traj_iters);
+                           two ? 1 : 0, cur);
+        hipLaunchKernelGGL(k_sl_points, dim3(lg.x * lg.y), dim3(kSlThreads), 0, s, grid.p, f7.p,
+                           o3.p, g, st.traj_iters, nb, cur);
         PINT_HIP(hipGetLastError());
       }
       PINT_TRY(ring_sl_anal(p, o3.p, nb, s));
       PINT_TRY(legendre_anal(p, nb, kAnaFields, PINT_FP64, s));
-      double* dst = last ? out + b0 * sd : cur.p;
+      double* dst = last ? out + b0 * sd : half[1 - cur];
       PINT_TRY(sp_sl_solve(p, *f, st.dt, st.visc_order, st.visc_nu, dst, nb, s));
       if (last) {
         if (out_prev)
-          PINT_HIP(hipMemcpyAsync(out_prev + b0 * sd, now, nb * sb, hipMemcpyDeviceToDevice, s));
+          PINT_HIP(hipMemcpyAsync(out_prev + b0 * sd, half[cur], nb * sb,
+                                  hipMemcpyDeviceToDevice, s));
       } else {
-        PINT_HIP(hipMemcpyAsync(prev, now, nb * sb, hipMemcpyDeviceToDevice, s));
-        PINT_HIP(hipMemcpyAsync(now, cur.p, nb * sb, hipMemcpyDeviceToDevice, s));
+        cur = 1 - cur;
         two = true;
       }
     }
