@@ -168,3 +168,33 @@ def test_parareal_with_sl_coarse(fine_key, coarse_key):
     got = from_dev(slices)
     for n in range(N + 1):
         assert_parity(got[n], want[n], md.M)
+
+
+def test_largest_ring_rest_and_steady_flow():
+    """The largest ring (T340 on 1024 x 512): the state at rest is kept
+    exactly, and steady solid-body rotation (polar axis, gradient-wind
+    balance) moves by less than 1e-6 of its size over three steps; the
+    two states of one launch are bitwise the same as alone."""
+    M, nlon, nlat = 340, 1024, 512
+    plan = pint.Plan(M, nlon, nlat, phibar=PHIBAR, max_batch=4)
+    nc = plan.ncoef
+    rest = torch.zeros((1, 3, nc, 2), dtype=torch.float64, device="cuda")
+    rest[0, 0, 0, 0] = PHIBAR
+    out = torch.empty_like(rest)
+    plan.sl_steps(pint.sl_stepper(1800.0), rest, out, 1, 3)
+    torch.cuda.synchronize()
+    assert torch.equal(out, rest)
+    U0 = workloads.solid_body(M, phi0=PHIBAR)
+    u = to_dev(np.stack([U0, U0]), torch)
+    o2 = torch.empty_like(u)
+    st = pint.sl_stepper(1800.0, 2, 2, 0.0)
+    plan.sl_steps(st, u, o2, 2, 3)
+    o1 = torch.empty_like(u[:1])
+    plan.sl_steps(st, u[:1], o1, 1, 3)
+    torch.cuda.synchronize()
+    assert torch.equal(o1[0], o2[0]) and torch.equal(o2[0], o2[1])
+    d = (o2[0] - u[0]).double()
+    ref = u[0].clone()
+    ref[0, 0, 0] -= PHIBAR
+    assert float(torch.linalg.vector_norm(d)) < 1e-6 * float(torch.linalg.vector_norm(ref))
+    plan.close()
