@@ -85,3 +85,12 @@ def test_sl_entry_points_reject_a_null_plan():
     assert lib.pint_parareal_sl(None, ctypes.byref(fine), 4, None, ctypes.byref(st), 1, 4, 2,
                                 None, None, None) == -1
     assert b"null plan" in lib.pint_last_error()
+
+
+def test_struct_layouts_match_the_header():
+    """The ctypes mirrors have the sizes the C structs have under the x86-64
+    ABI (double 8, int 4, natural alignment)."""
+    from paper_2306_09497_amd import pint
+    assert ctypes.sizeof(pint.Stepper) == 32          # double, int (+4), double, unsigned (+4)
+    assert ctypes.sizeof(pint.SlStepper) == 24        # double, int, int, double
+    assert pint.SlStepper.traj_iters.offset == 8 and pint.SlStepper.visc_nu.offset == 16
