@@ -431,28 +431,30 @@ def measure_sl(reps=10):
     out["config"] = "T127 384x192, dt 1800 s, q 2, nu 1e5, 2 trajectory iterations"
     # Parareal with the SL coarse propagator (Sec. 3.1, C4 shape): 64 slices
     # of 4 days / 64, fine IMEX 30 s x 180 per slice, coarse SL 1800 s x 3;
-    # one instance (the driver runs one initial state at a time)
+    # one instance, and the five instances together
     fplan = pint.Plan(Mc, nlon, nlat, phibar=PHIBAR, max_batch=64)
     fine = pint.stepper(30.0, 2, 0.0, pint.T_ALL)
     N = 64
-    slices = torch.zeros((N + 1, 3, plan.ncoef, 2), dtype=torch.float64, device="cuda")
-    times = {}
-    for it in (0, 0, 2):
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
-        t0.record()
-        fplan.parareal_sl(fine, 180, st, 3, N, it, u[:1], slices, coarse_plan=plan)
-        t1.record()
-        torch.cuda.synchronize()
-        times[it] = t0.elapsed_time(t1)
-    per_it = (times[2] - times[0]) / 2
-    out["parareal_sl_t127"] = {
-        "slices": N, "fine_steps_per_slice": 180, "coarse_sl_steps_per_slice": 3,
-        "initial_coarse_sweep_ms": times[0], "ms_per_iteration": per_it,
-        # iterations 0 and 1 recompute 64 and 63 slices
-        "fine_slice_steps_per_s": (2 * N - 1) * 180 / ((times[2] - times[0]) * 1e-3),
-        "finite": bool(torch.isfinite(slices).all()),
-    }
+    for I in (1, 5):
+        slices = torch.zeros((N + 1, I, 3, plan.ncoef, 2), dtype=torch.float64, device="cuda")
+        times = {}
+        for it in (0, 0, 2):
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            fplan.parareal_sl(fine, 180, st, 3, N, it, u[:I], slices, n_inst=I, coarse_plan=plan)
+            t1.record()
+            torch.cuda.synchronize()
+            times[it] = t0.elapsed_time(t1)
+        per_it = (times[2] - times[0]) / 2
+        out["parareal_sl_t127" + ("" if I == 1 else "_x%d" % I)] = {
+            "instances": I, "slices": N, "fine_steps_per_slice": 180,
+            "coarse_sl_steps_per_slice": 3,
+            "initial_coarse_sweep_ms": times[0], "ms_per_iteration": per_it,
+            # iterations 0 and 1 recompute 64 and 63 slices of every instance
+            "fine_slice_steps_per_s": I * (2 * N - 1) * 180 / ((times[2] - times[0]) * 1e-3),
+            "finite": bool(torch.isfinite(slices).all()),
+        }
     fplan.close()
     plan.close()
     return out

@@ -189,17 +189,19 @@ pint_status pint_sl_steps(pint_plan* plan, const pint_sl_stepper* st, const doub
  * `fine` per slice, on `plan`) and an SL-SI-SETTLS coarse propagator
  * (coarse_steps steps of `coarse` per slice, on coarse_plan, or on `plan`
  * when coarse_plan is NULL; a coarse plan of lower truncation works on the
- * truncated states and pads its results with zeros).  Each coarse
- * propagation starts a slice and takes its first step in the one-step
- * variant (Sec. 3.3).  n_iter iterations; iteration k recomputes slices
- * k..N-1 only (slice k's input is converged).  u_slices [n_slices + 1]
- * receives the slice-boundary states, u_slices[0] = u0.  Runs on `stream`
- * alone; the coarse plan must be PINT_FP64 with max_batch >= 2 and share the
- * planet and Phibar of `plan`.  */
+ * truncated states and pads its results with zeros), for n_inst independent
+ * instances (initial states) at once.  Each coarse propagation starts a
+ * slice and takes its first step in the one-step variant (Sec. 3.3).
+ * n_iter iterations; iteration k recomputes slices k..N-1 only (slice k's
+ * input is converged).  u0 is [n_inst][3][ncoef][2]; u_slices is
+ * [n_slices + 1][n_inst][3][ncoef][2] and receives the slice-boundary
+ * states, u_slices[0] = u0.  Results of an instance do not depend on the
+ * others.  Runs on `stream` alone; the coarse plan must be PINT_FP64 with
+ * max_batch >= 2 and share the planet and Phibar of `plan`.  */
 pint_status pint_parareal_sl(pint_plan* plan, const pint_stepper* fine, int fine_steps,
                              pint_plan* coarse_plan, const pint_sl_stepper* coarse,
-                             int coarse_steps, int n_slices, int n_iter, const double* u0,
-                             double* u_slices, void* stream);
+                             int coarse_steps, int n_slices, int n_inst, int n_iter,
+                             const double* u0, double* u_slices, void* stream);
 
 /* Parallel-in-time solve of dU/dt = L U + N(U) on [0, n_intervals * DT].
  * method 0 = Parareal (Sec. 3.1): slices of length DT = fine.dt *

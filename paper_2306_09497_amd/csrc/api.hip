@@ -618,13 +618,14 @@ pint_status pint_sl_steps(pint_plan* plan, const pint_sl_stepper* st, const doub
 // Parareal (Sec. 3.1) with an SL-SI-SETTLS coarse propagator (Sec. 2.3.2):
 // every coarse propagation starts a slice, so its first step is the one-step
 // variant (Sec. 3.3).  Iteration k leaves slices n < k untouched (they are
-// converged), propagates slices k..N-1 with the fine IMEX steps as one batch
-// and sweeps U_{n+1} = (G(U_n) - G_old_n) + F_n serially (G at slice k is
-// unchanged, its input being converged).  All on one stream.
+// converged), propagates slices k..N-1 of all instances with the fine IMEX
+// steps as one batch and sweeps U_{n+1} = (G(U_n) - G_old_n) + F_n serially
+// over n, the instances of a slice together (G at slice k is unchanged, its
+// input being converged).  All on one stream.  States are [slice][instance].
 pint_status pint_parareal_sl(pint_plan* plan, const pint_stepper* fine, int fine_steps,
                              pint_plan* coarse_plan, const pint_sl_stepper* coarse,
-                             int coarse_steps, int n_slices, int n_iter, const double* u0,
-                             double* u_slices, void* stream) {
+                             int coarse_steps, int n_slices, int n_inst, int n_iter,
+                             const double* u0, double* u_slices, void* stream) {
   API_GUARD(plan);
   if (!fine || !coarse || !u0 || !u_slices) {
     set_error("null argument");
@@ -633,8 +634,8 @@ pint_status pint_parareal_sl(pint_plan* plan, const pint_stepper* fine, int fine
   Plan& p = plan->p;
   Plan& pc = coarse_plan ? coarse_plan->p : p;
   PINT_TRY(check_stepper(p, fine));
-  if (fine_steps < 1 || coarse_steps < 1 || n_slices < 1 || n_iter < 0) {
-    set_error("fine_steps, coarse_steps, n_slices must be >= 1 and n_iter >= 0");
+  if (fine_steps < 1 || coarse_steps < 1 || n_slices < 1 || n_inst < 1 || n_iter < 0) {
+    set_error("fine_steps, coarse_steps, n_slices, n_inst must be >= 1 and n_iter >= 0");
     return PINT_E_INVAL;
   }
   if (pc.M > p.M || pc.a != p.a || pc.omega != p.omega || pc.phibar != p.phibar) {
@@ -642,42 +643,43 @@ pint_status pint_parareal_sl(pint_plan* plan, const pint_stepper* fine, int fine
     return PINT_E_INVAL;
   }
   hipStream_t s = (hipStream_t)stream;
-  const int N = n_slices;
+  const int N = n_slices, I = n_inst;
   const size_t sd = (size_t)3 * p.ncoef * 2, sdc = (size_t)3 * pc.ncoef * 2;
-  const size_t sb = sd * sizeof(double);
+  const size_t ss = sd * I;                       // doubles per slice (all instances)
+  const size_t sb = ss * sizeof(double);
   const bool trunc = pc.M != p.M;
   DevBuf gold(p, kSlotPsGold), fv(p, kSlotPsFv), g(p, kSlotPsG), cin(p, kSlotPsCin),
       cout_(p, kSlotPsCout);
-  PINT_TRY(gold.alloc(sd * N));
-  PINT_TRY(fv.alloc(sd * N));
-  PINT_TRY(g.alloc(sd));
+  PINT_TRY(gold.alloc(ss * N));
+  PINT_TRY(fv.alloc(ss * N));
+  PINT_TRY(g.alloc(ss));
   if (trunc) {
-    PINT_TRY(cin.alloc(sdc));
-    PINT_TRY(cout_.alloc(sdc));
+    PINT_TRY(cin.alloc(sdc * I));
+    PINT_TRY(cout_.alloc(sdc * I));
   }
-  // G(x) -> y, one state
+  // G(x) -> y, the I instances of one slice
   auto G = [&](const double* x, double* y) -> pint_status {
-    if (!trunc) return sl_steps(pc, *coarse, nullptr, x, y, nullptr, 1, coarse_steps, s);
-    PINT_TRY(spec_truncate(x, p.M, cin.p, pc.M, 1, s));
-    PINT_TRY(sl_steps(pc, *coarse, nullptr, cin.p, cout_.p, nullptr, 1, coarse_steps, s));
-    return spec_pad(cout_.p, pc.M, y, p.M, 1, s);
+    if (!trunc) return sl_steps(pc, *coarse, nullptr, x, y, nullptr, I, coarse_steps, s);
+    PINT_TRY(spec_truncate(x, p.M, cin.p, pc.M, I, s));
+    PINT_TRY(sl_steps(pc, *coarse, nullptr, cin.p, cout_.p, nullptr, I, coarse_steps, s));
+    return spec_pad(cout_.p, pc.M, y, p.M, I, s);
   };
   double* U = u_slices;
   if (U != u0) PINT_HIP(hipMemcpyAsync(U, u0, sb, hipMemcpyDeviceToDevice, s));
   for (int n = 0; n < N; ++n) {
-    PINT_TRY(G(U + n * sd, gold.p + n * sd));
-    PINT_HIP(hipMemcpyAsync(U + (n + 1) * sd, gold.p + n * sd, sb, hipMemcpyDeviceToDevice, s));
+    PINT_TRY(G(U + n * ss, gold.p + n * ss));
+    PINT_HIP(hipMemcpyAsync(U + (n + 1) * ss, gold.p + n * ss, sb, hipMemcpyDeviceToDevice, s));
   }
   for (int k = 0; k < n_iter && k < N; ++k) {
-    PINT_TRY(propagate(p, *fine, U + k * sd, fv.p + k * sd, N - k, fine_steps, s));
+    PINT_TRY(propagate(p, *fine, U + k * ss, fv.p + k * ss, (N - k) * I, fine_steps, s));
     for (int n = k; n < N; ++n) {
-      double* gn = gold.p + n * sd;
+      double* gn = gold.p + n * ss;
       if (n > k) {
-        PINT_TRY(G(U + n * sd, g.p));
-        PINT_TRY(pr_update(p, g.p, gn, fv.p + n * sd, U + (n + 1) * sd, sd, s));
+        PINT_TRY(G(U + n * ss, g.p));
+        PINT_TRY(pr_update(p, g.p, gn, fv.p + n * ss, U + (n + 1) * ss, ss, s));
         PINT_HIP(hipMemcpyAsync(gn, g.p, sb, hipMemcpyDeviceToDevice, s));
       } else {
-        PINT_TRY(pr_update(p, gn, gn, fv.p + n * sd, U + (n + 1) * sd, sd, s));
+        PINT_TRY(pr_update(p, gn, gn, fv.p + n * ss, U + (n + 1) * ss, ss, s));
       }
     }
   }

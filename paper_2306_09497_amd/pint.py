@@ -260,12 +260,14 @@ class Plan:
                                     _ptr(out_prev), int(B), int(nsteps), _stream(stream)))
 
     def parareal_sl(self, fine, fine_steps, coarse, coarse_steps, n_slices, n_iter, u0, u_slices,
-                    coarse_plan=None, stream=None):
-        """Parareal with an SL-SI-SETTLS coarse propagator (fine: IMEX stepper)."""
+                    n_inst=1, coarse_plan=None, stream=None):
+        """Parareal with an SL-SI-SETTLS coarse propagator (fine: IMEX stepper);
+        u0 [n_inst] states, u_slices [n_slices + 1][n_inst] states."""
         cp = None if coarse_plan is None else coarse_plan._h
         _check(load().pint_parareal_sl(self._h, ctypes.byref(fine), int(fine_steps), cp,
                                        ctypes.byref(coarse), int(coarse_steps), int(n_slices),
-                                       int(n_iter), _ptr(u0), _ptr(u_slices), _stream(stream)))
+                                       int(n_inst), int(n_iter), _ptr(u0), _ptr(u_slices),
+                                       _stream(stream)))
 
     def solve(self, params, u0, u_slices, stream=None):
         rep = Report()

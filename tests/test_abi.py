@@ -82,7 +82,7 @@ def test_sl_entry_points_reject_a_null_plan():
     assert lib.pint_sl_steps(None, ctypes.byref(st), None, None, None, None, 1, 1, None) == -1
     assert b"null plan" in lib.pint_last_error()
     fine = pint.stepper(60.0)
-    assert lib.pint_parareal_sl(None, ctypes.byref(fine), 4, None, ctypes.byref(st), 1, 4, 2,
+    assert lib.pint_parareal_sl(None, ctypes.byref(fine), 4, None, ctypes.byref(st), 1, 4, 1, 2,
                                 None, None, None) == -1
     assert b"null plan" in lib.pint_last_error()
 

@@ -136,14 +136,15 @@ def test_rejected_arguments():
 @pytest.mark.parametrize("fine_key,coarse_key", [("T21", None), ("T42", "T21")])
 def test_parareal_with_sl_coarse(fine_key, coarse_key):
     """Parareal (Sec. 3.1), fine IMEX, coarse SL-SI-SETTLS (one-step variant
-    at every slice start), 4 slices, 3 iterations, against the oracle's
-    Parareal with the same propagators (the coarse one on the truncated
-    state, padded back)."""
+    at every slice start), 4 slices, 3 iterations, two instances at once,
+    against the oracle's Parareal with the same propagators (the coarse one
+    on the truncated state, padded back); an instance run alone is bitwise
+    the same."""
     from oracle import pint as opint
     from oracle.sht import pad, truncate
     md, plan = setup(fine_key)
     N, fsteps, csteps, dtf, dtc = 4, 8, 2, 225.0, 900.0
-    U0 = states(md, 1, 70)[0]
+    U0 = states(md, 2, 70)
     fine = pint.stepper(dtf, 2, 1e5, pint.T_ALL)
     coarse = pint.sl_stepper(dtc, 2, 2, 1e6)
     if coarse_key is None:
@@ -160,14 +161,19 @@ def test_parareal_with_sl_coarse(fine_key, coarse_key):
     def F(U):
         return md.propagate(U, dtf, fsteps, nu=1e5, q=2)
 
-    want, _ = opint.parareal(U0, N, F, G, 3)
-    slices = torch.zeros((N + 1, 3, md.grid.nc, 2), dtype=torch.float64, device="cuda")
-    plan.parareal_sl(fine, fsteps, coarse, csteps, N, 3, to_dev(U0, torch), slices,
+    slices = torch.zeros((N + 1, 2, 3, md.grid.nc, 2), dtype=torch.float64, device="cuda")
+    plan.parareal_sl(fine, fsteps, coarse, csteps, N, 3, to_dev(U0, torch), slices, n_inst=2,
+                     coarse_plan=cplan)
+    one = torch.zeros((N + 1, 1, 3, md.grid.nc, 2), dtype=torch.float64, device="cuda")
+    plan.parareal_sl(fine, fsteps, coarse, csteps, N, 3, to_dev(U0[1:], torch), one, n_inst=1,
                      coarse_plan=cplan)
     torch.cuda.synchronize()
+    assert torch.equal(one[:, 0], slices[:, 1])
     got = from_dev(slices)
-    for n in range(N + 1):
-        assert_parity(got[n], want[n], md.M)
+    for i in range(2):
+        want, _ = opint.parareal(U0[i], N, F, G, 3)
+        for n in range(N + 1):
+            assert_parity(got[n, i], want[n], md.M)
 
 
 def test_largest_ring_rest_and_steady_flow():
