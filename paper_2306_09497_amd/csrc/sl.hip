@@ -3,7 +3,7 @@
 //
 // One step of B states:
 //   spectral prep + Legendre synthesis GEMM  (shared with the IMEX path) of
-//     U^n and U^{n-1} together (2B states)
+//     U^n and U^{n-1} together (2B states; B in the one-step variant)
 //   k_ring_sl_grid   Fourier -> grid: delta, Phi', G, dPhi'/dlambda, U, V
 //   k_sl_fields      per grid point: the extrapolated wind 2V^n - V^{n-1},
 //                    R_Phi and the wind right-hand side R_V (Cartesian)
