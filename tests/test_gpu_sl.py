@@ -99,8 +99,9 @@ def test_batch_invariance_and_chunks():
 
 def test_t127_coarse_configuration():
     """The coarse SL configuration of the paper's two-level runs: T127,
-    dt = 1800 s, second-order viscosity 1e5, five instances, three steps."""
-    md, plan = setup("T127")
+    dt = 1800 s, second-order viscosity 1e5, five instances, three steps, in
+    the launch configuration the bench times (max_batch 10: one chunk)."""
+    md, plan = setup("T127", max_batch=10)
     U = states(md, 5, 50)
     st = pint.sl_stepper(1800.0, 2, 2, 1e5)
     got = from_dev(run(plan, st, U, 3))
