@@ -458,16 +458,18 @@ def measure_sl(reps=10):
     # convergence of the SL-coarse Parareal (the paper's stability question
     # for this coarse scheme): largest relative increment over the slices of
     # Phi' and of the wind, iterations 1..4 against the iterate before
-    prev = None
-    incr = []
-    for it in range(5):
-        sl_k = torch.zeros((N + 1, 3, plan.ncoef, 2), dtype=torch.float64, device="cuda")
-        fplan.parareal_sl(fine, 180, st, 3, N, it, u[:1], sl_k, coarse_plan=plan)
-        if prev is not None:
-            d = fplan.rel_diff(sl_k, prev, N + 1)
-            incr.append([float(d[:, 0].max()), float(d[:, 3].max())])
-        prev = sl_k
-    out["parareal_sl_t127"]["increments_phi_wind"] = incr
+    for nu, key in ((1.0e5, "increments_phi_wind"), (1.0e6, "increments_phi_wind_nu1e6")):
+        stn = pint.sl_stepper(1800.0, 2, 2, nu)
+        prev = None
+        incr = []
+        for it in range(5):
+            sl_k = torch.zeros((N + 1, 3, plan.ncoef, 2), dtype=torch.float64, device="cuda")
+            fplan.parareal_sl(fine, 180, stn, 3, N, it, u[:1], sl_k, coarse_plan=plan)
+            if prev is not None:
+                d = fplan.rel_diff(sl_k, prev, N + 1)
+                incr.append([float(d[:, 0].max()), float(d[:, 3].max())])
+            prev = sl_k
+        out["parareal_sl_t127"][key] = incr
     fplan.close()
     plan.close()
     return out
