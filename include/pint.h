@@ -9,7 +9,7 @@
  * it batched over many time slices inside Parareal (Sec. 3.1) and two- and
  * three-level MGRIT (Sec. 3.2).  Around that path: a server that runs many
  * such solves at once, the error norms and kinetic-energy spectrum of
- * Sec. 5-6 and the stability maps of Sec. 4, all on the device.
+ * Sec. 5 and the stability maps of Sec. 4, all on the device.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -116,7 +116,14 @@ typedef struct pint_plan pint_plan;
 typedef struct {
   int M, nlon, nlat, ncoef, max_batch;
   size_t state_doubles;        /* 3 * ncoef * 2: doubles per state           */
-  size_t workspace_bytes;      /* device memory the plan holds               */
+  size_t workspace_bytes;      /* device memory the plan holds now           */
+  long long allocations;       /* device allocations the plan made after its
+                                  creation (driver scratch and factor sets)  */
+  int gemm_shape[2][2];        /* Legendre GEMM launch shape in use, [synthesis,
+                                  analysis][launches of few states, of many]:
+                                  0 = k-slabs of 16, 1 = of 32               */
+  double gemm_us[2][2];        /* the autotuner's time per launch of that shape
+                                  (0 = not tuned)                            */
 } pint_info;
 
 /* Create a plan: Gauss nodes and weights (Newton iteration), normalised
@@ -172,7 +179,7 @@ pint_status pint_step(pint_plan* plan, const pint_stepper* st, const double* u_i
  * the arrival frame), adds dt/2 N_R^n at the arrival points and solves
  * (I - dt/2 L) U^{n+1} = (R_Phi*, curl R_V*, div R_V*) per zonal
  * wavenumber; N_R = -Phi' delta.
- * u_prev = NULL: the first step is the one-step variant of Sec. 3.3 (U^{n-1}
+ * u_prev = NULL: the first step is the one-step variant of Sec. 3.2.4 (U^{n-1}
  * replaced by U^n); otherwise u_prev holds U^{n-1}.  Later steps use the
  * two-step scheme.  out receives U^{n+nsteps}, and out_prev (if not NULL)
  * U^{n+nsteps-1}, so that a later call can continue the two-step scheme.
@@ -190,17 +197,23 @@ pint_status pint_sl_steps(pint_plan* plan, const pint_sl_stepper* st, const doub
  * (coarse_steps steps of `coarse` per slice, on coarse_plan, or on `plan`
  * when coarse_plan is NULL; a coarse plan of lower truncation works on the
  * truncated states and pads its results with zeros), for n_inst independent
- * instances (initial states) at once.  Each coarse propagation starts a
- * slice and takes its first step in the one-step variant (Sec. 3.3).
+ * instances (initial states) at once.  The serial coarse sweep is the
+ * coarsest level, where the two-step scheme runs in every step (Sec. 3.2.4):
+ * with restart = 0 each slice's coarse run starts from the corrected slice
+ * state and the last-but-one coarse state of the previous slice's run, and
+ * only the first step of the horizon takes the one-step variant; restart = 1
+ * takes the one-step variant at every slice start (as on a level whose
+ * slices belong to different processors).
  * n_iter iterations; iteration k recomputes slices k..N-1 only (slice k's
  * input is converged).  u0 is [n_inst][3][ncoef][2]; u_slices is
  * [n_slices + 1][n_inst][3][ncoef][2] and receives the slice-boundary
  * states, u_slices[0] = u0.  Results of an instance do not depend on the
  * others.  Runs on `stream` alone; the coarse plan must be PINT_FP64 with
- * max_batch >= 2 and share the planet and Phibar of `plan`.  */
+ * max_batch >= 2 and share the planet and Phibar of `plan`.  The driver's
+ * scratch is kept in the plan and grown on first use.  */
 pint_status pint_parareal_sl(pint_plan* plan, const pint_stepper* fine, int fine_steps,
                              pint_plan* coarse_plan, const pint_sl_stepper* coarse,
-                             int coarse_steps, int n_slices, int n_inst, int n_iter,
+                             int coarse_steps, int n_slices, int n_inst, int n_iter, int restart,
                              const double* u0, double* u_slices, void* stream);
 
 /* Parallel-in-time solve of dU/dt = L U + N(U) on [0, n_intervals * DT].
@@ -270,15 +283,64 @@ typedef struct {
 
 typedef struct {
   int iters;                     /* iterations performed                      */
-  double incr[128];              /* max relative increment per iteration      */
-  double seconds[128];           /* wall time per iteration                   */
+  double incr[128];              /* max relative increment per iteration (the
+                                    stopping measure: Phi' and the wind)      */
+  double incr_field[128][4];     /* per iteration, the largest relative
+                                    increment over slices of Phi', xi, delta
+                                    and the wind, each on its own             */
+  double seconds[128];           /* host wall time per iteration              */
+  double fine_seconds[128];      /* device time from the iteration's start to
+                                    the end of its batched fine propagation
+                                    (relaxation included)                     */
+  double coarse_seconds[128];    /* device time from the iteration's start to
+                                    the end of its serial coarse part (the
+                                    correction sweep, or the level-1 cycles
+                                    with three levels); it runs beside the
+                                    fine propagation, so the iteration takes
+                                    about the larger of the two               */
   long long fine_slice_steps;    /* fine IMEX steps executed (sum over slices)*/
   long long coarse_steps;        /* coarse IMEX steps executed (all coarse
                                     levels, single-state and batched)        */
+  int graph_iters;               /* iterations replayed from a HIP graph: an
+                                    iteration that repeats the launches of the
+                                    one before (MGRIT, or Parareal resumed,
+                                    which recompute every slice) is captured
+                                    once and replayed, bitwise the same       */
 } pint_report;
 
 pint_status pint_solve(pint_plan* plan, const pint_pint_params* p, const double* u0,
                        double* u_slices, pint_report* report, void* stream);
+
+/* Device footprint of a workload on a plan, and its reservation (the problem
+ * statement of Sec. 3: slices, fine and coarse propagators, levels).
+ * pint_plan_workspace_bytes writes to *bytes the device memory the plan
+ * holds once it is ready for
+ *   - pint_solve with parameters q (q may be NULL): its driver scratch
+ *     (about 3 n_intervals + 2 states, more with three levels or spatial
+ *     coarsening) and the Crank-Nicolson factors of its steppers -- those of
+ *     the coarse levels counted even when they live on q->coarse_plan; and
+ *     pint_step / pint_implicit with q->fine or q->coarse;
+ *   - pint_sl_steps with stepper sl (may be NULL): grid scratch for
+ *     max_batch / 2 state pairs and the (I - dt/2 L) factors,
+ * plus the tables and workspace made at creation.  It is a pure function of
+ * the plan's configuration and the arguments.  pint_plan_reserve allocates
+ * exactly that (enqueueing the factor kernels on `stream`) and then tunes the
+ * plan's Legendre GEMM launch shapes for the workload: it times every shape
+ * of each transform at one state per launch (the serial sweep's launches)
+ * and at min(n_intervals, max_batch) states (max_batch without q), keeps the
+ * fastest (on the coarse plan too), and synchronises `stream`.  The shapes
+ * give bitwise the same results, so tuning never changes an answer;
+ * pint_info.gemm_us reports the tuned times.  Afterwards those
+ * calls allocate and free no device memory and copy nothing to or from the
+ * host, and on a plan that had reserved nothing else
+ * pint_info.workspace_bytes equals the query.  Reserving is optional: the
+ * calls otherwise grow the same buffers on first use.  A server admits a
+ * request by the same footprint (its driver scratch plus the slice states).
+ * PINT_E_INVAL for invalid parameters, PINT_E_NOMEM if allocation fails.  */
+pint_status pint_plan_workspace_bytes(const pint_plan* plan, const pint_pint_params* q,
+                                      const pint_sl_stepper* sl, size_t* bytes);
+pint_status pint_plan_reserve(pint_plan* plan, const pint_pint_params* q,
+                              const pint_sl_stepper* sl, void* stream);
 
 /* Relative L2 differences used by the stopping test: for each of B state
  * pairs, out[b] = { ||dPhi'||/||Phi'||, ||dxi||/||xi||, ||ddelta||/||delta||,
@@ -290,7 +352,7 @@ pint_status pint_solve(pint_plan* plan, const pint_pint_params* p, const double*
 pint_status pint_rel_diff(pint_plan* plan, const double* a, const double* c, double* out_host,
                           int B, void* stream);
 
-/* Kinetic-energy spectrum of a triangular truncation (Sec. 6, Gaussian bumps
+/* Kinetic-energy spectrum of a triangular truncation (Sec. 5.1, Gaussian bumps
  * test case, after Koshyk and Hamilton): for each of B states
  *   e[b][n] = a^2 / (4 n (n+1)) * sum_{m=-n..n} (|xi_{m,n}|^2 + |delta_{m,n}|^2),
  * n = 0..M, e[b][0] = 0; the m < 0 coefficients of a real field are the
@@ -360,7 +422,9 @@ pint_status pint_stability_map(const pint_stability_cfg* cfg, double* out, void*
  * different requests share launches, and so do the serial coarse sweeps of
  * different requests.  A request's chunks depend only on its own step
  * counts and the propagator is batch invariant, so its result is bitwise
- * the same alone and in any mix.  Request state (4 n_intervals + 3 states)
+ * the same alone and in any mix.  Request state (the pint_solve driver
+ * scratch that pint_plan_workspace_bytes counts for its parameters, plus its
+ * n_intervals + 1 slice states: 4 n_intervals + 3 states)
  * lives in a device arena of arena_bytes allocated at creation; requests are
  * admitted first in first out when their state fits, and nothing is
  * allocated while serving.  The plans are borrowed: they must outlive the

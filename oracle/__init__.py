@@ -18,7 +18,7 @@ Gauss-Legendre nodes, dense LU) as the only building blocks:
 * ``pint``  -- Parareal (Sec. 3.1) and two-level MGRIT with F(CF)^nu
                relaxation and FAS coarse correction (Sec. 3.2).
 * ``sl``    -- the SL-SI-SETTLS step (Sec. 2.3.2) and its one-step variant
-               (Sec. 3.3): trajectories, bicubic interpolation, the
+               (Sec. 3.2.4): trajectories, bicubic interpolation, the
                semi-implicit solve.
 * ``norms`` -- spectral (area-weighted) L2 norms and the paper's spectral
                max-norm error (Sec. 5).

@@ -1,10 +1,10 @@
-"""Oracle: the diagnostics of paper Sec. 5 and Sec. 6 -- kinetic-energy
+"""Oracle: the diagnostics of paper Sec. 5 and Sec. 5.1 -- kinetic-energy
 spectrum, spectral max-norm errors per resolution, physical-space L2 errors.
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
 * ``ke_spectrum``: the kinetic-energy spectrum of a triangular truncation
-  (Sec. 6, Gaussian bumps test case, after Koshyk and Hamilton),
+  (Sec. 5.1, Gaussian bumps test case, after Koshyk and Hamilton),
       E(n) = 1/4 * a^2 / (n (n+1)) * sum_{m=-n..n} (|xi_{m,n}|^2 + |delta_{m,n}|^2),
   E(0) = 0.  The fields are real, so xi_{-m,n} = conj(xi_{m,n}) and the sum
   over m = -n..n is |.|_{0,n}^2 + 2 sum_{m=1..n} |.|_{m,n}^2.  With the

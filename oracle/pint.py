@@ -13,6 +13,18 @@ bitwise the update returns F(U^k_n) bitwise; slices n < k are already exact
 and are not recomputed.  Converges to the serial fine solution in at most N
 iterations (Sec. 3.1).
 
+Parareal with a two-step coarse scheme (SL-SI-SETTLS, Sec. 2.3.2) follows
+the rule of Sec. 3.2.4 for the coarsest level: the two-step scheme runs in
+every step of the serial sweep, the one-step variant only where two
+consecutive steps belong to different processors -- which never happens in
+a sweep on one device.  Reading: the coarse propagator maps (U_n, P_{n-1})
+to (G_n, P_n), P_n being the last state before the end of its run, and the
+sweep hands P_{n-1} of the slice before to the coarse run of slice n (the
+solution at t_{n-1} carried with the one at t_n).  The very first step of
+the run has no history and takes the one-step variant.  Slice k's G and P
+are unchanged in iteration k (its input and the carried state are those of
+the previous sweep), so they are kept, as in the one-step case.
+
 Two-level MGRIT with F(CF)^nu relaxation and FAS (Sec. 3.2):
     fine grid t_j = j dt_0 with one-step propagator Phi_0, C-points every m
     fine points, coarse propagator Phi_1 over one C-interval.
@@ -47,6 +59,9 @@ iteration holds.
 
 Pins: tests/test_oracle_pint.py (Parareal stability function on the scalar
 test equation, finite termination, MGRIT(2,0) = Parareal, MGRIT termination;
+carried two-step coarse scheme: the first sweep is the uninterrupted serial
+two-step run, a coarse scheme ignoring its carried state gives Parareal,
+finite termination;
 three-level: one level-2 interval = two-level bitwise, exact level-2
 propagator on a linear problem = two-level, finite termination).
 """
@@ -87,6 +102,37 @@ def parareal(u0, n_slices, fine, coarse, n_iter, record=False, incr_fn=None,
         if tol > 0 and incrs and incrs[-1] <= tol:
             break
     return U, (history, incrs)
+
+
+def parareal_carry(u0, n_slices, fine, coarse, n_iter, record=False):
+    """Parareal whose coarse propagator carries its previous state across
+    slices: coarse(U, P) -> (G, P'), P = None for the first slice of the
+    horizon.  Returns (U, history) as ``parareal``."""
+    N = n_slices
+    U = [u0] + [None] * N
+    G = [None] * N
+    P = [None] * N
+    prev = None
+    for n in range(N):
+        G[n], P[n] = coarse(U[n], prev)
+        U[n + 1] = G[n]
+        prev = P[n]
+    history = [list(U)] if record else None
+    for k in range(n_iter):
+        if k >= N:
+            break
+        F = [None] * N
+        for n in range(k, N):
+            F[n] = fine(U[n])
+        Unew, Gnew, Pnew = list(U), list(G), list(P)
+        for n in range(k, N):
+            if n > k:
+                Gnew[n], Pnew[n] = coarse(Unew[n], Pnew[n - 1])
+            Unew[n + 1] = (Gnew[n] - G[n]) + F[n]
+        U, G, P = Unew, Gnew, Pnew
+        if record:
+            history.append(list(U))
+    return U, (history, [])
 
 
 def mgrit2(u0, n_coarse, m, phi0, phi1, nu, n_iter, record=False,

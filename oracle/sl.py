@@ -1,5 +1,5 @@
 """Oracle: the semi-Lagrangian semi-implicit SETTLS step (Sec. 2.3.2, eqs.
-SETTLS_trajectories and SL_SI_SETTLS) and its one-step variant (Sec. 3.3).
+SETTLS_trajectories and SL_SI_SETTLS) and its one-step variant (Sec. 3.2.4).
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
@@ -27,7 +27,7 @@ read in the advective form of the equations of Sec. 2.1 (readings R33-R36):
 * Interpolation: tensor-product cubic Lagrange in (longitude, latitude) on
   the Gauss grid; the two rows beyond a pole are the two rows next to it,
   mirrored across the pole, at longitude + pi.
-* One-step variant (Sec. 3.3): U^{n-1} is replaced by U^n.
+* One-step variant (Sec. 3.2.4): U^{n-1} is replaced by U^n.
 
 Pins: tests/test_oracle_sl.py (exactness of the interpolation on cubic
 products, its fourth-order convergence across the poles, the closed-form

@@ -41,7 +41,7 @@ pint_status check_stepper(const Plan& p, const pint_stepper* st) {
 // two half steps alone.  out may alias in.
 pint_status imex_steps(Plan& p, const pint_stepper& st, const double* in, double* out, int B,
                        int nsteps, hipStream_t s, const double* cf, double* corr, bool prepped,
-                       bool chain_out) {
+                       bool chain_out, const CnFactors* given) {
   if ((corr || prepped) && (nsteps < 1 || !(st.terms & PINT_T_NL))) {
     set_error("internal: a fused correction needs a nonlinear step");
     return PINT_E_INVAL;
@@ -56,8 +56,8 @@ pint_status imex_steps(Plan& p, const pint_stepper& st, const double* in, double
                               hipMemcpyDeviceToDevice, s));
     return PINT_OK;
   }
-  const CnFactors* f = nullptr;
-  PINT_TRY(cn_factors(p, st.dt, st.terms, s, &f));
+  const CnFactors* f = given;
+  if (!f) PINT_TRY(cn_factors(p, st.dt, st.terms, s, &f));
   if (!(st.terms & PINT_T_NL)) {
     for (int k = 0; k < nsteps; ++k) PINT_TRY(sp_cn(p, *f, st, &st, k ? out : in, out, B, s));
     return PINT_OK;
@@ -326,6 +326,44 @@ static pint_status level1_cycles(Plan& p, const pint_pint_params* q, Level1Bufs&
   return PINT_OK;
 }
 
+// Device memory pint_solve(q) needs on plan p (the coarse plan's factor sets
+// separately): the driver scratch of its pool slots and the Crank-Nicolson
+// factors of its steppers.  Every buffer solve() uses is sized here.
+pint_status solve_footprint(const Plan& p, const pint_pint_params* q, Footprint& fp) {
+  if (!q) return PINT_OK;
+  PINT_TRY(check_params(p, q));
+  const size_t N = (size_t)q->n_intervals;
+  const size_t sd = (size_t)3 * p.ncoef * 2;
+  fp.need(kSlotGold, sd * N);
+  fp.need(kSlotFv, sd * N);
+  fp.need(kSlotUprev, sd * (N + 1));
+  fp.need(kSlotGtmp, sd);
+  fp.need(kSlotIncr, 8 * N);                 // increment sums, one iteration
+  fp.host_doubles = 8 * N;
+  const bool three = q->method == 1 && q->levels == 3;
+  if (three) {
+    const size_t m1 = (size_t)q->cfactor1, N2 = N / m1, rows = m1 * (N2 + 1);
+    fp.need(kSlotW, sd * rows);
+    fp.need(kSlotFl, sd * rows);
+    fp.need(kSlotGl, sd * rows);
+    fp.need(kSlotTmp, sd * N2);
+    fp.need(kSlotF2, sd * N2);
+    fp.need(kSlotG2, sd * N2);
+    fp.need(kSlotGz, sd);
+  }
+  const Plan* pc = q->coarse_plan ? &q->coarse_plan->p : nullptr;
+  if (pc && pc->M != p.M) {
+    const size_t sdc = (size_t)3 * pc->ncoef * 2;
+    fp.need(kSlotCin, sdc * N);
+    fp.need(kSlotCinSide, sdc);
+  }
+  fp.factors(fp.cn, q->fine.dt, q->fine.terms);
+  auto& cc = pc && pc != &p ? fp.cn_coarse : fp.cn;
+  fp.factors(cc, q->coarse.dt, q->coarse.terms);
+  if (three) fp.factors(cc, q->coarse2.dt, q->coarse2.terms);
+  return PINT_OK;
+}
+
 static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, double* U,
                          pint_report* rep, hipStream_t s) {
   PINT_TRY(check_params(p, q));
@@ -335,6 +373,12 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
   pint_report local;
   pint_report* r = rep ? rep : &local;
   memset(r, 0, sizeof *r);
+  // the scratch this problem needs (no allocation when reserved before)
+  {
+    Footprint fp;
+    PINT_TRY(solve_footprint(p, q, fp));
+    PINT_TRY(reserve(p, q->coarse_plan ? &q->coarse_plan->p : nullptr, fp, s));
+  }
   DevBuf Gold(p, kSlotGold), Fv(p, kSlotFv), Uprev(p, kSlotUprev), Gtmp(p, kSlotGtmp);
   PINT_TRY(Gold.alloc(sd * N));
   PINT_TRY(Fv.alloc(sd * N));
@@ -371,12 +415,21 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
       r->coarse_steps += q->coarse_steps;
     }
   }
-  pint_status result = PINT_OK;
-  for (int k = 0; k < q->max_iter; ++k) {
-    const double t0 = now_s();
-    // slices before `first` are already exact (Parareal); MGRIT recomputes all
-    const int first = (mgrit || q->resume) ? 0 : (k < N ? k : N);
-    if (first >= N) break;
+  // One iteration's device work, enqueued on s (and the sweep stream joined
+  // back into s): relaxation and batched fine propagation, the serial
+  // correction sweep or level-1 cycles, and the increment sums copied to
+  // pinned host memory.  Nothing in it waits or allocates, so it can be
+  // captured into a graph; `capturing` turns the phase events into
+  // external event nodes of the graph.
+  DevBuf Incr(p, kSlotIncr);
+  PINT_TRY(Incr.alloc((size_t)8 * N));
+  bool capturing = false;
+  auto rec = [&](hipEvent_t ev, hipStream_t st) -> pint_status {
+    PINT_HIP(hipEventRecordWithFlags(ev, st, capturing ? hipEventRecordExternal : 0));
+    return PINT_OK;
+  };
+  auto iteration = [&](int first, hipStream_t s) -> pint_status {
+    PINT_TRY(rec(p.ph_ev[0], s));
     PINT_HIP(hipMemcpyAsync(Uprev.p, U, sb * (N + 1), hipMemcpyDeviceToDevice, s));
     const double* src = U;   // C-points the fine propagation starts from
     if (nrelax > 0) {
@@ -403,7 +456,9 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
       }
       PINT_TRY(propagate(p, q->fine, U, Fv.p, N, q->fine_steps, s));
       r->fine_slice_steps += (long long)N * q->fine_steps;
+      PINT_TRY(rec(p.ph_ev[1], s));
       PINT_TRY(level1_cycles(p, q, l1, coarse, U, Fv.p, Gold.p, r, s));
+      PINT_TRY(rec(p.ph_ev[2], s));
     } else {
       // fine propagation of every active slice (the parallel part), in chunks
       // of cs slices; chunk c's event releases the sweep steps that need it
@@ -421,6 +476,7 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
         PINT_TRY(propagate(p, q->fine, src + n0 * sd, Fv.p + n0 * sd, nb, q->fine_steps, s));
         PINT_HIP(hipEventRecord(p.chunk_ev[c], s));
       }
+      PINT_TRY(rec(p.ph_ev[1], s));
       r->fine_slice_steps += (long long)nact * q->fine_steps;
       // serial correction sweep U_{n+1} = (G(U_n^new) - G(U_n^old)) + F(U_n^old)
       // on the sweep stream and workspace, beside the later chunks.  Step n
@@ -446,24 +502,99 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
             r->coarse_steps += q->coarse_steps;
           }
         }
+        PINT_TRY(rec(p.ph_ev[2], ss));
         PINT_HIP(hipEventRecord(p.join_ev, ss));
       }
       PINT_HIP(hipStreamWaitEvent(s, p.join_ev, 0));
     }
-    // increments (synchronises)
-    PINT_TRY(rel_diff(p, U + sd, Uprev.p + sd, incr.data(), N, s));
+    return rel_diff_enqueue(p, U + sd, Uprev.p + sd, Incr.p, p.h_incr, N, s);
+  };
+
+  // Iterations that repeat the same launches (every slice each time: MGRIT,
+  // and Parareal resumed from an iterate) run from a HIP graph captured at
+  // the second iteration, on the plan's capture stream, and launched into s.
+  struct GraphExec {
+    hipGraphExec_t e = nullptr;
+    ~GraphExec() {
+      if (e) (void)hipGraphExecDestroy(e);
+    }
+  } graph;
+  long long g_fine = 0, g_coarse = 0;   // counters of one replayed iteration
+  bool graphable = (mgrit || q->resume) && p.use_graphs && !p.prof_on &&
+                   !(coarse.pc && coarse.pc->prof_on);
+  pint_status result = PINT_OK;
+  for (int k = 0; k < q->max_iter; ++k) {
+    const double t0 = now_s();
+    // slices before `first` are already exact (Parareal); MGRIT recomputes all
+    const int first = (mgrit || q->resume) ? 0 : (k < N ? k : N);
+    if (first >= N) break;
+    if (graph.e) {
+      PINT_HIP(hipGraphLaunch(graph.e, s));
+      r->fine_slice_steps += g_fine;
+      r->coarse_steps += g_coarse;
+      ++r->graph_iters;
+    } else if (graphable && k >= 1) {
+      // capture (nothing runs while capturing), instantiate, launch; if the
+      // runtime refuses any of it the iteration runs as plain launches and
+      // the solve does not try again
+      const long long f0 = r->fine_slice_steps, c0 = r->coarse_steps;
+      hipStream_t cs = p.capture_stream;
+      hipGraph_t g = nullptr;
+      bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        capturing = true;
+        const pint_status st = iteration(first, cs);
+        capturing = false;
+        ok = hipStreamEndCapture(cs, &g) == hipSuccess && st == PINT_OK && g != nullptr;
+      }
+      if (ok) ok = hipGraphInstantiate(&graph.e, g, nullptr, nullptr, 0) == hipSuccess;
+      if (g) (void)hipGraphDestroy(g);
+      if (ok) {
+        g_fine = r->fine_slice_steps - f0;
+        g_coarse = r->coarse_steps - c0;
+        PINT_HIP(hipGraphLaunch(graph.e, s));
+        ++r->graph_iters;
+      } else {
+        (void)hipGetLastError();
+        graph.e = nullptr;
+        graphable = false;
+        r->fine_slice_steps = f0;
+        r->coarse_steps = c0;
+        PINT_TRY(iteration(first, s));
+      }
+    } else {
+      PINT_TRY(iteration(first, s));
+    }
+    PINT_HIP(hipStreamSynchronize(s));
+    rel_diff_finish(p.h_incr, incr.data(), N);
     // stopping measure: Phi' and the wind (entries 0 and 3 of each slice)
     double worst = 0.0;
     bool bad = false;
+    double fld[4] = {0.0, 0.0, 0.0, 0.0};
     for (int n = 0; n < N; ++n) {
       for (int f = 0; f < 4; ++f) {
         const double v = incr[(size_t)n * 4 + f];
         if (!isfinite(v)) bad = true;
-        else if ((f == 0 || f == 3) && v > worst) worst = v;
+        else {
+          if (v > fld[f]) fld[f] = v;
+          if ((f == 0 || f == 3) && v > worst) worst = v;
+        }
       }
     }
     r->incr[k] = bad ? NAN : worst;
+    for (int f = 0; f < 4; ++f) r->incr_field[k][f] = bad ? NAN : fld[f];
     r->seconds[k] = now_s() - t0;
+    {
+      // all three events are complete (s was synchronised)
+      float ms_f = 0.0f, ms_c = 0.0f;
+      if (hipEventElapsedTime(&ms_f, p.ph_ev[0], p.ph_ev[1]) != hipSuccess ||
+          hipEventElapsedTime(&ms_c, p.ph_ev[0], p.ph_ev[2]) != hipSuccess) {
+        (void)hipGetLastError();
+        ms_f = ms_c = -1e3f;         // not measurable: reported as -1 s
+      }
+      r->fine_seconds[k] = 1e-3 * ms_f;
+      r->coarse_seconds[k] = 1e-3 * ms_c;
+    }
     r->iters = k + 1;
     if (bad || worst > 1e6) {
       set_error("PinT iteration %d diverged (increment %g)", k, worst);
@@ -527,6 +658,57 @@ pint_status pint_plan_info(const pint_plan* plan, pint_info* info) {
   info->max_batch = p.max_batch;
   info->state_doubles = (size_t)3 * p.ncoef * 2;
   info->workspace_bytes = p.ws_bytes;
+  info->allocations = p.n_allocs;
+  for (int k = 0; k < 2; ++k)
+    for (int c = 0; c < 2; ++c) {
+      info->gemm_shape[k][c] = p.gemm_variant[k][c];
+      info->gemm_us[k][c] = 1e3 * p.gemm_tuned_ms[k][c];
+    }
+  return PINT_OK;
+}
+
+static pint_status workload_footprint(const Plan& p, const pint_pint_params* q,
+                                      const pint_sl_stepper* sl, Footprint& fp) {
+  PINT_TRY(solve_footprint(p, q, fp));
+  if (sl) {
+    PINT_TRY(sl_check(p, *sl, 0, 0));
+    sl_footprint(p, *sl, fp);
+  }
+  return PINT_OK;
+}
+
+pint_status pint_plan_workspace_bytes(const pint_plan* plan, const pint_pint_params* q,
+                                      const pint_sl_stepper* sl, size_t* bytes) {
+  API_GUARD(plan);
+  if (!bytes) {
+    set_error("null output");
+    return PINT_E_INVAL;
+  }
+  Footprint fp;
+  PINT_TRY(workload_footprint(plan->p, q, sl, fp));
+  *bytes = footprint_bytes(plan->p, q && q->coarse_plan ? &q->coarse_plan->p : nullptr, fp);
+  return PINT_OK;
+}
+
+pint_status pint_plan_reserve(pint_plan* plan, const pint_pint_params* q,
+                              const pint_sl_stepper* sl, void* stream) {
+  API_GUARD(plan);
+  Footprint fp;
+  PINT_TRY(workload_footprint(plan->p, q, sl, fp));
+  Plan* pc = q && q->coarse_plan ? &q->coarse_plan->p : nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  PINT_TRY(reserve(plan->p, pc, fp, s));
+  // launch shapes of the Legendre GEMMs for this workload: single states
+  // (the serial sweep) and the batched propagation's launches
+  const int big = q ? (q->n_intervals < plan->p.max_batch ? q->n_intervals : plan->p.max_batch)
+                    : plan->p.max_batch;
+  const int states[2] = {1, big};
+  PINT_TRY(tune_legendre(plan->p, states, s));
+  if (pc && pc != &plan->p) {
+    const int cbig = big < pc->max_batch ? big : pc->max_batch;
+    const int cstates[2] = {1, cbig};
+    PINT_TRY(tune_legendre(*pc, cstates, s));
+  }
   return PINT_OK;
 }
 
@@ -615,16 +797,21 @@ pint_status pint_sl_steps(pint_plan* plan, const pint_sl_stepper* st, const doub
   return sl_steps(plan->p, *st, u_prev, u, out, out_prev, B, nsteps, (hipStream_t)stream);
 }
 
-// Parareal (Sec. 3.1) with an SL-SI-SETTLS coarse propagator (Sec. 2.3.2):
-// every coarse propagation starts a slice, so its first step is the one-step
-// variant (Sec. 3.3).  Iteration k leaves slices n < k untouched (they are
-// converged), propagates slices k..N-1 of all instances with the fine IMEX
-// steps as one batch and sweeps U_{n+1} = (G(U_n) - G_old_n) + F_n serially
-// over n, the instances of a slice together (G at slice k is unchanged, its
-// input being converged).  All on one stream.  States are [slice][instance].
+// Parareal (Sec. 3.1) with an SL-SI-SETTLS coarse propagator (Sec. 2.3.2).
+// The serial sweep is the coarsest level, where Sec. 3.2.4 runs the two-step
+// scheme in every step: each slice's coarse run starts from the corrected
+// U_n and the last-but-one state P_{n-1} of the previous slice's run (saved
+// per slice in Pold), the very first step of the horizon in the one-step
+// variant.  restart = 1 instead starts every slice's run in the one-step
+// variant.  Iteration k leaves slices n < k untouched (they are converged),
+// propagates slices k..N-1 of all instances with the fine IMEX steps as one
+// batch and sweeps U_{n+1} = (G(U_n, P_{n-1}) - G_old_n) + F_n serially over
+// n, the instances of a slice together (G and P at slice k are unchanged:
+// their inputs are those of the previous sweep).  All on one stream.
+// States are [slice][instance].
 pint_status pint_parareal_sl(pint_plan* plan, const pint_stepper* fine, int fine_steps,
                              pint_plan* coarse_plan, const pint_sl_stepper* coarse,
-                             int coarse_steps, int n_slices, int n_inst, int n_iter,
+                             int coarse_steps, int n_slices, int n_inst, int n_iter, int restart,
                              const double* u0, double* u_slices, void* stream) {
   API_GUARD(plan);
   if (!fine || !coarse || !u0 || !u_slices) {
@@ -634,8 +821,10 @@ pint_status pint_parareal_sl(pint_plan* plan, const pint_stepper* fine, int fine
   Plan& p = plan->p;
   Plan& pc = coarse_plan ? coarse_plan->p : p;
   PINT_TRY(check_stepper(p, fine));
-  if (fine_steps < 1 || coarse_steps < 1 || n_slices < 1 || n_inst < 1 || n_iter < 0) {
-    set_error("fine_steps, coarse_steps, n_slices, n_inst must be >= 1 and n_iter >= 0");
+  if (fine_steps < 1 || coarse_steps < 1 || n_slices < 1 || n_inst < 1 || n_iter < 0 ||
+      (restart != 0 && restart != 1)) {
+    set_error("fine_steps, coarse_steps, n_slices, n_inst must be >= 1, n_iter >= 0 and "
+              "restart 0 or 1");
     return PINT_E_INVAL;
   }
   if (pc.M > p.M || pc.a != p.a || pc.omega != p.omega || pc.phibar != p.phibar) {
@@ -646,28 +835,33 @@ pint_status pint_parareal_sl(pint_plan* plan, const pint_stepper* fine, int fine
   const int N = n_slices, I = n_inst;
   const size_t sd = (size_t)3 * p.ncoef * 2, sdc = (size_t)3 * pc.ncoef * 2;
   const size_t ss = sd * I;                       // doubles per slice (all instances)
+  const size_t ssc = sdc * I;                     // the same at the coarse truncation
   const size_t sb = ss * sizeof(double);
   const bool trunc = pc.M != p.M;
   DevBuf gold(p, kSlotPsGold), fv(p, kSlotPsFv), g(p, kSlotPsG), cin(p, kSlotPsCin),
-      cout_(p, kSlotPsCout);
+      cout_(p, kSlotPsCout), pold(p, kSlotPsPold);
   PINT_TRY(gold.alloc(ss * N));
   PINT_TRY(fv.alloc(ss * N));
   PINT_TRY(g.alloc(ss));
+  if (!restart) PINT_TRY(pold.alloc(ssc * N));
   if (trunc) {
-    PINT_TRY(cin.alloc(sdc * I));
-    PINT_TRY(cout_.alloc(sdc * I));
+    PINT_TRY(cin.alloc(ssc));
+    PINT_TRY(cout_.alloc(ssc));
   }
-  // G(x) -> y, the I instances of one slice
-  auto G = [&](const double* x, double* y) -> pint_status {
-    if (!trunc) return sl_steps(pc, *coarse, nullptr, x, y, nullptr, I, coarse_steps, s);
+  // G over slice n: x -> y for the I instances; the carried state enters
+  // from slice n-1's Pold and slice n's leaves in Pold[n]
+  auto G = [&](int n, const double* x, double* y) -> pint_status {
+    const double* prev = (restart || n == 0) ? nullptr : pold.p + (size_t)(n - 1) * ssc;
+    double* pout = restart ? nullptr : pold.p + (size_t)n * ssc;
+    if (!trunc) return sl_steps(pc, *coarse, prev, x, y, pout, I, coarse_steps, s);
     PINT_TRY(spec_truncate(x, p.M, cin.p, pc.M, I, s));
-    PINT_TRY(sl_steps(pc, *coarse, nullptr, cin.p, cout_.p, nullptr, I, coarse_steps, s));
+    PINT_TRY(sl_steps(pc, *coarse, prev, cin.p, cout_.p, pout, I, coarse_steps, s));
     return spec_pad(cout_.p, pc.M, y, p.M, I, s);
   };
   double* U = u_slices;
   if (U != u0) PINT_HIP(hipMemcpyAsync(U, u0, sb, hipMemcpyDeviceToDevice, s));
   for (int n = 0; n < N; ++n) {
-    PINT_TRY(G(U + n * ss, gold.p + n * ss));
+    PINT_TRY(G(n, U + n * ss, gold.p + n * ss));
     PINT_HIP(hipMemcpyAsync(U + (n + 1) * ss, gold.p + n * ss, sb, hipMemcpyDeviceToDevice, s));
   }
   for (int k = 0; k < n_iter && k < N; ++k) {
@@ -675,7 +869,7 @@ pint_status pint_parareal_sl(pint_plan* plan, const pint_stepper* fine, int fine
     for (int n = k; n < N; ++n) {
       double* gn = gold.p + n * ss;
       if (n > k) {
-        PINT_TRY(G(U + n * ss, g.p));
+        PINT_TRY(G(n, U + n * ss, g.p));
         PINT_TRY(pr_update(p, g.p, gn, fv.p + n * ss, U + (n + 1) * ss, ss, s));
         PINT_HIP(hipMemcpyAsync(gn, g.p, sb, hipMemcpyDeviceToDevice, s));
       } else {

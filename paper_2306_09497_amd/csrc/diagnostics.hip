@@ -1,4 +1,4 @@
-// Diagnostics of Sec. 5 and Sec. 6 on the device, over states in the public
+// Diagnostics of Sec. 5 and Sec. 5.1 on the device, over states in the public
 // layout [B][3][ncoef][2]:
 //   * the kinetic-energy spectrum of a triangular truncation,
 //       E(n) = a^2 / (4 n (n+1)) sum_{m=-n..n} (|xi_{m,n}|^2 + |delta_{m,n}|^2),

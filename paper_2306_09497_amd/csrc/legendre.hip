@@ -187,12 +187,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // of each pair.  The row-wave groups of the first half of the tile take the
 // even rows, the others the odd rows.  Per output element the matrix cores
 // consume k in steps of 4 in increasing order, as in every other shape.
-template <typename E, int TC>
+template <typename E, int TC, int TK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_legendre_anal(
     const E* __restrict__ Tt, const int* __restrict__ rowoff, const int* __restrict__ tiles,
     const E* __restrict__ G, E* __restrict__ Q, int nlat, int nlat2, int ncol, int nrows) {
   using MM = Mma<E>;
-  constexpr int TK = kGemmTK, TR2 = 32, TR = 2 * TR2;
+  constexpr int TR2 = 32, TR = 2 * TR2;
   constexpr int LDA = TR + 2, LDB = TC + 2;
   constexpr int NA = TK * TR / 256;                  // A elements per thread per slab
   constexpr int NB = TK * TC / 256;                  // G pairs per thread per slab
@@ -601,12 +601,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   }
 }
 
+// Launch shapes.  Every shape consumes k in the same order (steps of 4,
+// increasing, per parity), so all give bitwise the same results and the
+// choice between them is a matter of speed only: narrow column tiles (16)
+// for launches of up to two states (synthesis) or four (analysis), 64
+// otherwise, and a k-slab depth TK of 16 or 32 per launch class, chosen per
+// plan by the autotuner (tune_legendre) or left at the default (TK 16).
+enum { kClassSmall = 0, kClassLarge = 1 };
+static int gemm_class(int ncol) { return ncol <= 32 ? kClassSmall : kClassLarge; }
+
 template <typename E>
 static void launch_synth(Plan& p, const E* T, const E* S, E* F, int ncol, hipStream_t s) {
-  if (ncol <= 32) {
+  const int cls = gemm_class(ncol);
+  const int v = p.gemm_variant[0][cls];
+  if (cls == kClassSmall) {
     dim3 grid(((ncol + 15) / 16) * p.syn_tiles.count);
-    hipLaunchKernelGGL((k_legendre_synth<E, kGemmTR, 16, kGemmTK>), grid, dim3(256), 0, s, T,
-                       p.rowoff, p.syn_tiles.dev, S, F, p.nlat, p.nlat2, ncol);
+    if (v == 1)
+      hipLaunchKernelGGL((k_legendre_synth<E, kGemmTR, 16, 32>), grid, dim3(256), 0, s, T,
+                         p.rowoff, p.syn_tiles.dev, S, F, p.nlat, p.nlat2, ncol);
+    else
+      hipLaunchKernelGGL((k_legendre_synth<E, kGemmTR, 16, kGemmTK>), grid, dim3(256), 0, s, T,
+                         p.rowoff, p.syn_tiles.dev, S, F, p.nlat, p.nlat2, ncol);
   } else {
     dim3 grid(((ncol + 63) / 64) * p.syn_tiles.count);
     hipLaunchKernelGGL((k_legendre_synth<E, kGemmTR, 64, kGemmTK>), grid, dim3(256), 0, s, T,
@@ -616,16 +631,30 @@ static void launch_synth(Plan& p, const E* T, const E* S, E* F, int ncol, hipStr
 
 template <typename E>
 static void launch_anal(Plan& p, const E* Tt, const E* G, E* Q, int ncol, hipStream_t s) {
-  if (ncol <= 32) {
+  const int cls = gemm_class(ncol);
+  const int v = p.gemm_variant[1][cls];
+  if (cls == kClassSmall) {
     dim3 grid(((ncol + 15) / 16) * p.ana_tiles.count);
-    hipLaunchKernelGGL((k_legendre_anal<E, 16>), grid, dim3(256), 0, s, Tt, p.rowoff,
-                       p.ana_tiles.dev, G, Q, p.nlat, p.nlat2, ncol, p.nrows);
+    if (v == 1)
+      hipLaunchKernelGGL((k_legendre_anal<E, 16, 32>), grid, dim3(256), 0, s, Tt, p.rowoff,
+                         p.ana_tiles.dev, G, Q, p.nlat, p.nlat2, ncol, p.nrows);
+    else
+      hipLaunchKernelGGL((k_legendre_anal<E, 16, kGemmTK>), grid, dim3(256), 0, s, Tt, p.rowoff,
+                         p.ana_tiles.dev, G, Q, p.nlat, p.nlat2, ncol, p.nrows);
   } else {
     dim3 grid(((ncol + 63) / 64) * p.ana_tiles.count);
-    hipLaunchKernelGGL((k_legendre_anal<E, 64>), grid, dim3(256), 0, s, Tt, p.rowoff,
-                       p.ana_tiles.dev, G, Q, p.nlat, p.nlat2, ncol, p.nrows);
+    if (v == 1)
+      hipLaunchKernelGGL((k_legendre_anal<E, 64, 32>), grid, dim3(256), 0, s, Tt, p.rowoff,
+                         p.ana_tiles.dev, G, Q, p.nlat, p.nlat2, ncol, p.nrows);
+    else
+      hipLaunchKernelGGL((k_legendre_anal<E, 64, kGemmTK>), grid, dim3(256), 0, s, Tt, p.rowoff,
+                         p.ana_tiles.dev, G, Q, p.nlat, p.nlat2, ncol, p.nrows);
   }
 }
+
+// Variants per (transform, launch class); synthesis with 64-column tiles has
+// only TK 16 (TK 32 would need more than 64 KiB of LDS).
+static int gemm_variants(int kind, int cls) { return (kind == 0 && cls == kClassLarge) ? 1 : 2; }
 
 static void launch_synth_bf3(Plan& p, int ncol, hipStream_t s) {
   const float* T = p.ptab32;
@@ -683,6 +712,51 @@ pint_status legendre_anal(Plan& p, int B, int nf, int prec, hipStream_t s) {
     launch_anal<double>(p, p.ptabT, p.G, p.Q, ncol, s);
   PINT_HIP(hipGetLastError());
   return PINT_OK;
+}
+
+// Autotuner: for each transform and launch class, time every variant on the
+// plan's workspace (launches of `states` states: the classes' batch sizes of
+// the coming work) and keep the fastest.  The variants give bitwise the same
+// results, so the choice never changes an answer.  Synchronises `s`.
+pint_status tune_legendre(Plan& p, const int (&states)[2], hipStream_t s) {
+  if (p.prec == PINT_LEG_BF16X3) return PINT_OK;   // one shape per class there
+  hipEvent_t e0, e1;
+  PINT_HIP(hipEventCreate(&e0));
+  PINT_HIP(hipEventCreate(&e1));
+  pint_status st = PINT_OK;
+  for (int kind = 0; kind < 2 && st == PINT_OK; ++kind) {
+    for (int cls = 0; cls < 2 && st == PINT_OK; ++cls) {
+      const int B = states[cls];
+      if (B < 1 || B > p.max_batch) continue;
+      const int nf = kind == 0 ? kSynFields : kAnaFields;
+      if (gemm_class(2 * nf * B) != cls) continue;
+      int best = 0;
+      float best_ms = 0.0f;
+      for (int v = 0; v < gemm_variants(kind, cls) && st == PINT_OK; ++v) {
+        p.gemm_variant[kind][cls] = v;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 4 && st == PINT_OK; ++rep) {   // first one warms up
+          if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) st = PINT_E_HIP;
+          if (st == PINT_OK)
+            st = kind == 0 ? legendre_synth(p, B, nf, p.prec, s) : legendre_anal(p, B, nf, p.prec, s);
+        }
+        if (st == PINT_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                              hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          st = PINT_E_HIP;
+        if (st == PINT_OK && (v == 0 || ms < best_ms)) {
+          best = v;
+          best_ms = ms;
+        }
+      }
+      p.gemm_variant[kind][cls] = best;
+      p.gemm_tuned_ms[kind][cls] = best_ms / 3.0f;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == PINT_E_HIP) set_error("timing the Legendre GEMM variants failed");
+  return st;
 }
 
 }  // namespace pint

@@ -109,14 +109,27 @@ struct Plan {
     double *S = nullptr, *F = nullptr, *G = nullptr, *Q = nullptr, *Ua = nullptr, *N1 = nullptr;
   } side;
   hipStream_t side_stream = nullptr;
+  hipStream_t capture_stream = nullptr;  // PinT iterations are captured on it
+  bool use_graphs = true;                // replay repeating iterations from a graph
   std::vector<hipEvent_t> chunk_ev;  // one per fine-propagation chunk
   hipEvent_t join_ev = nullptr;      // end of a sweep on side_stream
   int sweep_chunks = 4;
   double* red = nullptr;       // reduction scratch
   double* diag = nullptr;      // L2-error partial sums [3 max_batch][nlat][2]
   double* h_red = nullptr;     // pinned host mirror
-  bool sl_lat_ready = false;   // extended latitudes of the SL interpolation uploaded
-  size_t ws_bytes = 0;
+  double* h_incr = nullptr;    // pinned host staging of the PinT increments
+  size_t h_incr_n = 0;         //   (doubles), grown on demand
+  double* sl_lat = nullptr;    // [nlat + 4] latitudes extended across the poles (SL)
+  size_t ws_bytes = 0;         // device bytes held: tables, workspace, factors, pool
+  size_t base_bytes = 0;       // of which made at creation
+  long long n_allocs = 0;      // device allocations made since creation
+  // timing events of the PinT phases (iteration start, fine propagation
+  // done, serial coarse part done)
+  hipEvent_t ph_ev[3] = {nullptr, nullptr, nullptr};
+  // Legendre GEMM launch shape per (synthesis / analysis, small / large
+  // launch class), set by the autotuner; and the tuned time per launch
+  int gemm_variant[2][2] = {{0, 0}, {0, 0}};
+  float gemm_tuned_ms[2][2] = {{0.0f, 0.0f}, {0.0f, 0.0f}};
   // device scratch of the PinT drivers, kept between calls and grown on
   // demand (slot -> buffer, doubles)
   std::vector<std::pair<double*, size_t>> pool;
@@ -174,6 +187,8 @@ void destroy(pint_plan* pp);
 // ---- kernels / launchers (each returns PINT_OK or an error) ----
 pint_status build_tables(Plan& p, hipStream_t s);
 pint_status cn_factors(Plan& p, double dt, unsigned terms, hipStream_t s, const CnFactors** out);
+pint_status cn_factors_fill(const Plan& p, double dt, unsigned terms, const CnFactors& f,
+                            hipStream_t s);
 
 // Spectral kernels on public-layout states (one wave per (m, state)):
 //  sp_cn_prep  Ua = CN(in) (no viscosity); S = synthesis input of Ua
@@ -202,9 +217,11 @@ pint_status check_params(const Plan& p, const pint_pint_params* q);
 // correction fused into the last step); chain_out: the last kernel also
 // makes the first half step of corr (the next sweep step), which a call
 // with prepped = true then starts from instead of `in`.
+// given: use this factor set instead of the plan's cached one.
 pint_status imex_steps(Plan& p, const pint_stepper& st, const double* in, double* out, int B,
                        int nsteps, hipStream_t s, const double* cf = nullptr,
-                       double* corr = nullptr, bool prepped = false, bool chain_out = false);
+                       double* corr = nullptr, bool prepped = false, bool chain_out = false,
+                       const CnFactors* given = nullptr);
 
 // transforms on the GEMM workspace
 // prec: PINT_FP64 (also used by the public scalar transforms) or PINT_LEG_FP32
@@ -212,6 +229,9 @@ pint_status spec_truncate(const double* in, int Mf, double* out, int Mc, int B, 
 pint_status spec_pad(const double* in, int Mc, double* out, int Mf, int B, hipStream_t s);
 pint_status legendre_synth(Plan& p, int B, int nf, int prec, hipStream_t s);
 pint_status legendre_anal(Plan& p, int B, int nf, int prec, hipStream_t s);
+// time the launch shapes of both transforms at states[0] (small launch
+// class) and states[1] (large) states per launch, keep the fastest
+pint_status tune_legendre(Plan& p, const int (&states)[2], hipStream_t s);
 pint_status ring_tendency(Plan& p, int B, hipStream_t s);
 bool ring_supported(int nlon);
 size_t ring_lds_bytes(int nlon, int prec);
@@ -226,8 +246,11 @@ pint_status pr_update(Plan& p, const double* gnew, const double* gold, const dou
                       double* out, size_t n, hipStream_t s);
 pint_status rel_diff(Plan& p, const double* a, const double* c, double* out_host, int B,
                      hipStream_t s);
+pint_status rel_diff_enqueue(Plan& p, const double* a, const double* c, double* dev,
+                             double* host, int B, hipStream_t s);
+void rel_diff_finish(const double* host, double* out_host, int B);
 
-// diagnostics (Sec. 5, Sec. 6): KE spectrum [B][M+1] and spectral max-norm
+// diagnostics (Sec. 5, Sec. 5.1): KE spectrum [B][M+1] and spectral max-norm
 // errors [B][3][M+1] on the device, physical-space L2 errors [B][3] to the host
 pint_status ke_spectrum(Plan& p, const double* u, double* e, int B, hipStream_t s);
 pint_status spectral_errors(Plan& p, const double* u, const double* ref, double* e, int B,
@@ -249,13 +272,16 @@ struct DevBuf {
     auto& b = pl.pool[slot];
     if (b.second < n) {
       if (b.first) (void)hipFree(b.first);
+      pl.ws_bytes -= b.second * sizeof(double);
       b = {nullptr, 0};
+      ++pl.n_allocs;
       if (hipMalloc(&b.first, n * sizeof(double)) != hipSuccess) {
         b.first = nullptr;
         set_error("hipMalloc(%zu bytes) of solver scratch failed", n * sizeof(double));
         return PINT_E_NOMEM;
       }
       b.second = n;
+      pl.ws_bytes += n * sizeof(double);
     }
     p = b.first;
     return PINT_OK;
@@ -263,11 +289,38 @@ struct DevBuf {
 };
 enum PoolSlot { kSlotGold, kSlotFv, kSlotUprev, kSlotGtmp, kSlotCin, kSlotCinSide, kSlotW,
                 kSlotFl, kSlotGl, kSlotTmp, kSlotF2, kSlotG2, kSlotGz, kSlotSlGrid, kSlotSlF,
-                kSlotSlO, kSlotSlLat, kSlotSlCur, kSlotSlPrev, kSlotPsGold, kSlotPsFv, kSlotPsG,
-                kSlotPsCin, kSlotPsCout };
+                kSlotSlO, kSlotPsGold, kSlotPsFv, kSlotPsG, kSlotPsCin, kSlotPsCout,
+                kSlotPsPrev, kSlotPsPold, kSlotIncr, kSlotCount };
+
+// Device memory a workload needs on one plan: doubles per pool slot and the
+// Crank-Nicolson factor keys (dt, terms) it uses.  Filled by the drivers'
+// footprint functions; reserve() allocates exactly this.
+struct Footprint {
+  size_t slot[kSlotCount] = {};
+  std::vector<std::pair<double, unsigned>> cn;        // on the plan itself
+  std::vector<std::pair<double, unsigned>> cn_coarse; // on the coarse plan
+  size_t host_doubles = 0;                            // pinned host staging
+  void need(int s, size_t n) {
+    if (n > slot[s]) slot[s] = n;
+  }
+  void factors(std::vector<std::pair<double, unsigned>>& v, double dt, unsigned terms) {
+    const auto k = std::make_pair(dt, terms & (PINT_T_LG | PINT_T_LC));
+    for (const auto& e : v)
+      if (e == k) return;
+    v.push_back(k);
+  }
+};
+size_t cn_factor_bytes(const Plan& p);
+// footprint of pint_solve(q) (q may be NULL) and of pint_sl_steps with
+// stepper sl (may be NULL) on plan p
+pint_status solve_footprint(const Plan& p, const pint_pint_params* q, Footprint& fp);
+void sl_footprint(const Plan& p, const pint_sl_stepper& st, Footprint& fp);
+pint_status sl_check(const Plan& p, const pint_sl_stepper& st, int B, int nsteps);
+size_t footprint_bytes(const Plan& p, const Plan* pc, const Footprint& fp);
+pint_status reserve(Plan& p, Plan* pc, const Footprint& fp, hipStream_t s);
 
 
-// Semi-Lagrangian SETTLS steps (Sec. 2.3.2, Sec. 3.3)
+// Semi-Lagrangian SETTLS steps (Sec. 2.3.2; one-step variant, Sec. 3.2.4)
 pint_status ring_sl_grid(Plan& p, double* grid, int Bt, hipStream_t s);
 pint_status ring_sl_anal(Plan& p, const double* grid, int B, hipStream_t s);
 pint_status sp_sl_solve(Plan& p, const CnFactors& f, double dt, int visc_order, double visc_nu,

@@ -137,6 +137,23 @@ __global__ void k_cn_coef(int M, int ncoef, double a, const int* coefmn, double4
   co[i] = make_double4(c.A, c.B, c.C, c.lap);
 }
 
+// Latitudes of the Gauss rows extended by two mirrored rows beyond each pole
+// (the semi-Lagrangian interpolation stencil crosses the poles): entry j + 2
+// is asin(mu_j); the rows beyond the north pole are pi - lat of the first
+// rows, those beyond the south pole -pi - lat of the last rows.
+__global__ void k_sl_lat(int nlat, const double* mu, double* lat) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nlat + 4) return;
+  const double pi = 3.14159265358979323846264338328;
+  double v;
+  if (i == 0) v = pi - asin(mu[1]);
+  else if (i == 1) v = pi - asin(mu[0]);
+  else if (i == nlat + 2) v = -pi - asin(mu[nlat - 1]);
+  else if (i == nlat + 3) v = -pi - asin(mu[nlat - 2]);
+  else v = asin(mu[i - 2]);
+  lat[i] = v;
+}
+
 template <typename T>
 static pint_status dalloc(T** ptr, size_t count, size_t* total) {
   void* v = nullptr;
@@ -155,7 +172,7 @@ static void free_plan(Plan& p) {
   void* ptrs[] = {p.mu, p.w, p.c2, p.ptab, p.ptabT, p.ptab32, p.ptabT32, p.twid32,
                   p.rowoff, p.rowinfo, p.coefmn, p.twid, p.cnco, p.syn_tiles.dev,
                   p.ana_tiles.dev, p.S, p.F, p.G, p.Q, p.Ua, p.N1, p.red, p.diag,
-                  p.side.S, p.side.F, p.side.G, p.side.Q, p.side.Ua, p.side.N1};
+                  p.side.S, p.side.F, p.side.G, p.side.Q, p.side.Ua, p.side.N1, p.sl_lat};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto& b : p.pool)
@@ -165,9 +182,16 @@ static void free_plan(Plan& p) {
   p.chunk_ev.clear();
   if (p.join_ev) (void)hipEventDestroy(p.join_ev);
   p.join_ev = nullptr;
+  for (hipEvent_t& e : p.ph_ev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
   if (p.side_stream) (void)hipStreamDestroy(p.side_stream);
   p.side_stream = nullptr;
+  if (p.capture_stream) (void)hipStreamDestroy(p.capture_stream);
+  p.capture_stream = nullptr;
   if (p.h_red) (void)hipHostFree(p.h_red);
+  if (p.h_incr) (void)hipHostFree(p.h_incr);
   for (hipEvent_t e : p.ev_pool) (void)hipEventDestroy(e);
   p.ev_pool.clear();
   for (auto& kv : p.cn_cache) {
@@ -328,6 +352,7 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
   PLAN_TRY(dalloc(&p.side.N1, (size_t)p.ncoef * 3 * 2, &tot));
   PLAN_TRY(dalloc(&p.red, (size_t)8 * B + 64, &tot));
   PLAN_TRY(dalloc(&p.diag, (size_t)6 * B * nlat, &tot));
+  PLAN_TRY(dalloc(&p.sl_lat, (size_t)nlat + 4, &tot));
   if (hipHostMalloc((void**)&p.h_red, (8 * B + 64) * sizeof(double), 0) != hipSuccess) {
     free_plan(p);
     delete pp;
@@ -335,14 +360,24 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
     return PINT_E_NOMEM;
   }
   p.ws_bytes = tot;
+  p.base_bytes = tot;
   // the sweep stream does not synchronise with the legacy null stream:
   // ordering against the caller's stream is by events only
   if (hipStreamCreateWithFlags(&p.side_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&p.capture_stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&p.join_ev, hipEventDisableTiming) != hipSuccess) {
     free_plan(p);
     delete pp;
     set_error("hipStreamCreateWithFlags / hipEventCreateWithFlags failed");
     return PINT_E_HIP;
+  }
+  for (hipEvent_t& e : p.ph_ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      free_plan(p);
+      delete pp;
+      set_error("hipEventCreate failed");
+      return PINT_E_HIP;
+    }
   }
   p.chunk_ev.assign(kMaxSweepChunks, nullptr);
   for (hipEvent_t& e : p.chunk_ev) {
@@ -352,6 +387,11 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
       set_error("hipEventCreateWithFlags failed");
       return PINT_E_HIP;
     }
+  }
+  if (const char* env = getenv("PINT_GRAPHS")) p.use_graphs = atoi(env) != 0;
+  if (const char* env = getenv("PINT_GEMM_VARIANT")) {   // fixed launch shapes (tests)
+    const int v = atoi(env) ? 1 : 0;
+    p.gemm_variant[0][0] = p.gemm_variant[1][0] = p.gemm_variant[1][1] = v;
   }
   if (const char* env = getenv("PINT_SWEEP_CHUNKS")) {
     const int v = atoi(env);
@@ -377,6 +417,7 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
   hipLaunchKernelGGL(k_ptab, dim3((p.nlat2 + 63) / 64, M + 1), dim3(64), 0, s, M, p.nlat2,
                      p.nrows, p.mu, p.c2, p.rowoff, p.ptab, p.ptabT);
   hipLaunchKernelGGL(k_twiddle, dim3((nlon + 255) / 256), dim3(256), 0, s, nlon, p.twid);
+  hipLaunchKernelGGL(k_sl_lat, dim3((nlat + 4 + 63) / 64), dim3(64), 0, s, nlat, p.mu, p.sl_lat);
   if (p.prec != PINT_FP64) {
     const size_t nt = (size_t)p.nrows * p.nlat2;
     hipLaunchKernelGGL(k_to_float, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, p.ptab,
@@ -505,6 +546,19 @@ __global__ void k_cn_factor(int M, int ncoef, double a, double W, double phibar,
   }
 }
 
+// Factor set of (dt, terms) into the buffers of f (2 ncoef double2 each).
+pint_status cn_factors_fill(const Plan& p, double dt, unsigned terms, const CnFactors& f,
+                            hipStream_t s) {
+  const unsigned key_terms = terms & (PINT_T_LG | PINT_T_LC);
+  const double W = (key_terms & PINT_T_LC) ? 2.0 * p.omega : 0.0;
+  const bool lg = (key_terms & PINT_T_LG) != 0;
+  const int nt = 2 * (p.M + 1);
+  hipLaunchKernelGGL(k_cn_factor, dim3((nt + 63) / 64), dim3(64), 0, s, p.M, p.ncoef, p.a, W,
+                     lg ? p.phibar : 0.0, dt / 4.0, lg ? 1 : 0, f.alph, f.gam, f.invpiv);
+  PINT_HIP(hipGetLastError());
+  return PINT_OK;
+}
+
 pint_status cn_factors(Plan& p, double dt, unsigned terms, hipStream_t s, const CnFactors** out) {
   const unsigned key_terms = terms & (PINT_T_LG | PINT_T_LC);
   auto key = std::make_pair(dt, key_terms);
@@ -515,17 +569,51 @@ pint_status cn_factors(Plan& p, double dt, unsigned terms, hipStream_t s, const 
   }
   CnFactors f;
   const size_t n = (size_t)2 * p.ncoef;
+  p.n_allocs += 3;
   PINT_TRY(dalloc(&f.alph, n, &p.ws_bytes));
   PINT_TRY(dalloc(&f.gam, n, &p.ws_bytes));
   PINT_TRY(dalloc(&f.invpiv, n, &p.ws_bytes));
-  const double W = (key_terms & PINT_T_LC) ? 2.0 * p.omega : 0.0;
-  const bool lg = (key_terms & PINT_T_LG) != 0;
-  const int nt = 2 * (p.M + 1);
-  hipLaunchKernelGGL(k_cn_factor, dim3((nt + 63) / 64), dim3(64), 0, s, p.M, p.ncoef, p.a, W,
-                     lg ? p.phibar : 0.0, dt / 4.0, lg ? 1 : 0, f.alph, f.gam, f.invpiv);
-  PINT_HIP(hipGetLastError());
+  PINT_TRY(cn_factors_fill(p, dt, terms, f, s));
   auto ins = p.cn_cache.emplace(key, f);
   *out = &ins.first->second;
+  return PINT_OK;
+}
+
+size_t cn_factor_bytes(const Plan& p) { return (size_t)3 * 2 * p.ncoef * sizeof(double2); }
+
+// Bytes a footprint adds to the plan's (and the coarse plan's) creation-time
+// memory: pool slots at their needed sizes plus the factor sets.
+size_t footprint_bytes(const Plan& p, const Plan* pc, const Footprint& fp) {
+  size_t b = p.base_bytes;
+  for (int i = 0; i < kSlotCount; ++i) b += fp.slot[i] * sizeof(double);
+  b += fp.cn.size() * cn_factor_bytes(p);
+  if (pc && pc != &p) b += fp.cn_coarse.size() * cn_factor_bytes(*pc);
+  else b += fp.cn_coarse.size() * cn_factor_bytes(p);
+  return b;
+}
+
+pint_status reserve(Plan& p, Plan* pc, const Footprint& fp, hipStream_t s) {
+  if (fp.host_doubles > p.h_incr_n) {
+    if (p.h_incr) (void)hipHostFree(p.h_incr);
+    p.h_incr = nullptr;
+    p.h_incr_n = 0;
+    ++p.n_allocs;
+    if (hipHostMalloc((void**)&p.h_incr, fp.host_doubles * sizeof(double), 0) != hipSuccess) {
+      p.h_incr = nullptr;
+      set_error("hipHostMalloc(%zu bytes) failed", fp.host_doubles * sizeof(double));
+      return PINT_E_NOMEM;
+    }
+    p.h_incr_n = fp.host_doubles;
+  }
+  for (int i = 0; i < kSlotCount; ++i)
+    if (fp.slot[i]) {
+      DevBuf b(p, i);
+      PINT_TRY(b.alloc(fp.slot[i]));
+    }
+  const CnFactors* f = nullptr;
+  for (const auto& k : fp.cn) PINT_TRY(cn_factors(p, k.first, k.second, s, &f));
+  Plan& c = pc ? *pc : p;
+  for (const auto& k : fp.cn_coarse) PINT_TRY(cn_factors(c, k.first, k.second, s, &f));
   return PINT_OK;
 }
 

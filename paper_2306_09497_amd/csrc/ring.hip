@@ -2,10 +2,18 @@
 // fused with the pointwise nonlinear terms (Sec. 2.1, A-grid pseudospectral
 // evaluation).  One workgroup per (latitude j, state b); the ring lives in LDS.
 //
-// Real signals are transformed in pairs through one complex FFT (x + i y).
-// The FFT is a mixed-radix (4, 2, 3, 5) Stockham transform in a single LDS
-// buffer per signal: each pass loads its butterflies' operands into
-// registers, synchronises, then writes the butterfly outputs.
+// Two FFT forms live here:
+//  * the tendency kernel (k_ring_tendency, the hot one) carries every real
+//    field of a ring as a half-length complex signal z[n] = x[2n] + i x[2n+1]
+//    and transforms it in place in LDS, decimation in frequency for the
+//    inverse transforms and decimation in time for the forward ones, so that
+//    the pointwise products work on digit-reversed points (described above
+//    the kernel);
+//  * the scalar-transform, diagnostic and semi-Lagrangian ring kernels pair
+//    two real signals in one complex FFT (x + i y), a mixed-radix
+//    (4, 2, 3, 5) Stockham transform in one LDS buffer per signal pair:
+//    each pass loads its butterflies' operands into registers, synchronises,
+//    then writes the butterfly outputs.
 #include <type_traits>
 
 #include "pint_internal.h"

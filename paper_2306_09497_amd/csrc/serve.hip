@@ -506,8 +506,15 @@ pint_status pint_server_submit(pint_server* S, const pint_request* req, long lon
     set_error("null u0 or u_slices");
     return PINT_E_INVAL;
   }
+  // footprint: the driver scratch pint_solve needs for these parameters (the
+  // same function as pint_plan_workspace_bytes) plus the request's own copy
+  // of its slice states
   const int N = q.n_intervals;
-  const size_t bytes = (4 * (size_t)N + 3) * state_doubles(p) * sizeof(double);
+  Footprint fp;
+  PINT_TRY(solve_footprint(p, &q, fp));
+  size_t scratch = 0;
+  for (int i = 0; i < kSlotCount; ++i) scratch += fp.slot[i];
+  const size_t bytes = (scratch + ((size_t)N + 1) * state_doubles(p)) * sizeof(double);
   if (Arena::round(bytes) > S->arena.capacity()) {
     set_error("request needs %zu bytes of state, the arena holds %zu", bytes,
               S->arena.capacity());

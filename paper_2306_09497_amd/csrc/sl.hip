@@ -1,5 +1,5 @@
 // Semi-Lagrangian semi-implicit SETTLS steps (Sec. 2.3.2, eqs.
-// SETTLS_trajectories and SL_SI_SETTLS; one-step variant of Sec. 3.3).
+// SETTLS_trajectories and SL_SI_SETTLS; one-step variant of Sec. 3.2.4).
 //
 // One step of B states:
 //   spectral prep + Legendre synthesis GEMM  (shared with the IMEX path) of
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kSlThreads) void k_sl_points(const double* __restri
   o[2 * npts] = us * ic;
 }
 
-static pint_status sl_check(const Plan& p, const pint_sl_stepper& st, int B, int nsteps) {
+pint_status sl_check(const Plan& p, const pint_sl_stepper& st, int B, int nsteps) {
   if (p.prec != PINT_FP64) {
     set_error("semi-Lagrangian steps need a PINT_FP64 plan");
     return PINT_E_INVAL;
@@ -264,6 +264,18 @@ static pint_status sl_check(const Plan& p, const pint_sl_stepper& st, int B, int
   return PINT_OK;
 }
 
+// Scratch of pint_sl_steps on plan p: grid fields of max_batch / 2 state
+// pairs, the seven interpolated fields and three results per point, and the
+// (I - dt/2 L) factors (a Crank-Nicolson factor set at step 2 dt).
+void sl_footprint(const Plan& p, const pint_sl_stepper& st, Footprint& fp) {
+  const size_t nbmax = (size_t)(p.max_batch / 2);
+  const size_t npts = (size_t)p.nlat * p.nlon;
+  fp.need(kSlotSlGrid, 2 * nbmax * 6 * npts);
+  fp.need(kSlotSlF, nbmax * 7 * npts);
+  fp.need(kSlotSlO, nbmax * 3 * npts);
+  fp.factors(fp.cn, 2.0 * st.dt, PINT_T_ALL);
+}
+
 pint_status sl_steps(Plan& p, const pint_sl_stepper& st, const double* u_prev, const double* u,
                      double* out, double* out_prev, int B, int nsteps, hipStream_t s) {
   PINT_TRY(sl_check(p, st, B, nsteps));
@@ -282,27 +294,15 @@ pint_status sl_steps(Plan& p, const pint_sl_stepper& st, const double* u_prev, c
   }
   const int nbmax = p.max_batch / 2;
   const size_t npts = (size_t)p.nlat * p.nlon;
-  DevBuf grid(p, kSlotSlGrid), f7(p, kSlotSlF), o3(p, kSlotSlO), lat(p, kSlotSlLat);
-  PINT_TRY(grid.alloc((size_t)2 * nbmax * 6 * npts));
-  PINT_TRY(f7.alloc((size_t)nbmax * 7 * npts));
-  PINT_TRY(o3.alloc((size_t)nbmax * 3 * npts));
-  PINT_TRY(lat.alloc((size_t)p.nlat + 4));
-  if (!p.sl_lat_ready) {
-    std::vector<double> mu(p.nlat), lx(p.nlat + 4);
-    PINT_HIP(hipStreamSynchronize(s));
-    PINT_HIP(hipMemcpy(mu.data(), p.mu, p.nlat * sizeof(double), hipMemcpyDeviceToHost));
-    const double pi = 3.14159265358979323846264338328;
-    for (int j = 0; j < p.nlat; ++j) lx[j + 2] = asin(mu[j]);
-    lx[0] = pi - lx[3];
-    lx[1] = pi - lx[2];
-    lx[p.nlat + 2] = -pi - lx[p.nlat + 1];
-    lx[p.nlat + 3] = -pi - lx[p.nlat];
-    PINT_HIP(hipMemcpy(lat.p, lx.data(), lx.size() * sizeof(double), hipMemcpyHostToDevice));
-    p.sl_lat_ready = true;
-  }
+  Footprint fp;
+  sl_footprint(p, st, fp);
+  DevBuf grid(p, kSlotSlGrid), f7(p, kSlotSlF), o3(p, kSlotSlO);
+  PINT_TRY(grid.alloc(fp.slot[kSlotSlGrid]));
+  PINT_TRY(f7.alloc(fp.slot[kSlotSlF]));
+  PINT_TRY(o3.alloc(fp.slot[kSlotSlO]));
   const CnFactors* f = nullptr;
   PINT_TRY(cn_factors(p, 2.0 * st.dt, PINT_T_ALL, s, &f));   // (I - dt/2 L)
-  SlGeom g{p.mu, p.c2, lat.p, p.nlat, p.nlon, p.a, p.omega, p.phibar, 0.5 * st.dt};
+  SlGeom g{p.mu, p.c2, p.sl_lat, p.nlat, p.nlon, p.a, p.omega, p.phibar, 0.5 * st.dt};
   for (int b0 = 0; b0 < B; b0 += nbmax) {
     const int nb = (B - b0) < nbmax ? (B - b0) : nbmax;
     // two halves of nb states: U^n in half `cur`, U^{n-1} in the other; a

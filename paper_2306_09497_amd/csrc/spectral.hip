@@ -742,6 +742,26 @@ pint_status rel_diff(Plan& p, const double* a, const double* c, double* out_host
   return PINT_OK;
 }
 
+// The same sums for B state pairs at once into dev[8 B], copied to the
+// pinned host array host[8 B]; nothing waits (graph-capturable).
+pint_status rel_diff_enqueue(Plan& p, const double* a, const double* c, double* dev,
+                             double* host, int B, hipStream_t s) {
+  if (B <= 0) return PINT_OK;
+  ProfScope ps(p, PK_PINT, B, s);
+  hipLaunchKernelGGL(k_rel_diff, dim3(B), dim3(256), 0, s, a, c, dev, p.coefmn, p.ncoef, p.a);
+  PINT_HIP(hipGetLastError());
+  PINT_HIP(hipMemcpyAsync(host, dev, (size_t)B * 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+  return PINT_OK;
+}
+
+// out_host[B][4] from the sums of rel_diff_enqueue, once they have arrived.
+void rel_diff_finish(const double* host, double* out_host, int B) {
+  for (int i = 0; i < B * 4; ++i) {
+    const double num = host[2 * i], den = host[2 * i + 1];
+    out_host[i] = den > 0.0 ? sqrt(num / den) : sqrt(num);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Scalar transforms: coefficients in/out of the GEMM operands (nf = 1).
 // ---------------------------------------------------------------------------

@@ -22,7 +22,8 @@ FP64, LEG_FP32, LEG_BF16X3 = 0, 1, 2    # pint_config.precision
 STATUS = {0: "PINT_OK", -1: "PINT_E_INVAL", -2: "PINT_E_NOMEM", -3: "PINT_E_HIP",
           -4: "PINT_E_DIVERGED", -5: "PINT_E_NOTCONV"}
 
-EXPORTS = ["pint_plan_create", "pint_plan_destroy", "pint_plan_info", "pint_grid_coords",
+EXPORTS = ["pint_plan_create", "pint_plan_destroy", "pint_plan_info", "pint_plan_workspace_bytes",
+           "pint_plan_reserve", "pint_grid_coords",
            "pint_synthesis", "pint_analysis", "pint_tendency", "pint_implicit", "pint_step",
            "pint_sl_steps", "pint_parareal_sl", "pint_solve", "pint_rel_diff", "pint_ke_spectrum", "pint_spectral_errors",
            "pint_grid_l2_errors", "pint_stability_map", "pint_server_create", "pint_server_destroy",
@@ -47,10 +48,17 @@ class Stepper(ctypes.Structure):
                 ("visc_nu", ctypes.c_double), ("terms", ctypes.c_uint)]
 
 
+class SlStepper(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("traj_iters", ctypes.c_int),
+                ("visc_order", ctypes.c_int), ("visc_nu", ctypes.c_double)]
+
+
 class Info(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int), ("nlon", ctypes.c_int), ("nlat", ctypes.c_int),
                 ("ncoef", ctypes.c_int), ("max_batch", ctypes.c_int),
-                ("state_doubles", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t)]
+                ("state_doubles", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
+                ("allocations", ctypes.c_longlong), ("gemm_shape", (ctypes.c_int * 2) * 2),
+                ("gemm_us", (ctypes.c_double * 2) * 2)]
 
 
 class PintParams(ctypes.Structure):
@@ -97,8 +105,10 @@ class RequestStatus(ctypes.Structure):
 
 class Report(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("incr", ctypes.c_double * 128),
-                ("seconds", ctypes.c_double * 128), ("fine_slice_steps", ctypes.c_longlong),
-                ("coarse_steps", ctypes.c_longlong)]
+                ("incr_field", (ctypes.c_double * 4) * 128),
+                ("seconds", ctypes.c_double * 128), ("fine_seconds", ctypes.c_double * 128),
+                ("coarse_seconds", ctypes.c_double * 128), ("fine_slice_steps", ctypes.c_longlong),
+                ("coarse_steps", ctypes.c_longlong), ("graph_iters", ctypes.c_int)]
 
 
 class PintError(RuntimeError):
@@ -125,6 +135,11 @@ def load(path=LIB_PATH):
     lib.pint_plan_create.argtypes = [ctypes.POINTER(Config), vp, ctypes.POINTER(vp)]
     lib.pint_plan_destroy.argtypes = [vp]
     lib.pint_plan_info.argtypes = [vp, ctypes.POINTER(Info)]
+    lib.pint_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(PintParams),
+                                              ctypes.POINTER(SlStepper),
+                                              ctypes.POINTER(ctypes.c_size_t)]
+    lib.pint_plan_reserve.argtypes = [vp, ctypes.POINTER(PintParams), ctypes.POINTER(SlStepper),
+                                      vp]
     lib.pint_grid_coords.argtypes = [vp, dp, dp, vp]
     lib.pint_synthesis.argtypes = [vp, vp, vp, ip, vp]
     lib.pint_analysis.argtypes = [vp, vp, vp, ip, vp]
@@ -161,12 +176,16 @@ def _check(status):
         raise PintError(status, msg)
 
 
-def _ptr(t):
+def _ptr(t, numel=None):
+    """Device pointer of a contiguous float64 GPU tensor holding at least
+    numel elements (the library reads and writes that many)."""
     if t is None:
         return None
     import torch
     if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
         raise ValueError("device arrays must be contiguous float64 CUDA/HIP tensors")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"device array holds {t.numel()} doubles, the call needs {numel}")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -179,11 +198,6 @@ def _stream(stream):
 
 def stepper(dt, visc_order=2, visc_nu=0.0, terms=T_ALL):
     return Stepper(float(dt), int(visc_order), float(visc_nu), int(terms))
-
-
-class SlStepper(ctypes.Structure):
-    _fields_ = [("dt", ctypes.c_double), ("traj_iters", ctypes.c_int),
-                ("visc_order", ctypes.c_int), ("visc_nu", ctypes.c_double)]
 
 
 def sl_stepper(dt, traj_iters=2, visc_order=2, visc_nu=0.0):
@@ -212,6 +226,25 @@ class Plan:
         self.max_batch = info.max_batch
         self.workspace_bytes = info.workspace_bytes
 
+    def info(self):
+        info = Info()
+        _check(load().pint_plan_info(self._h, ctypes.byref(info)))
+        return info
+
+    def workspace_query(self, params=None, sl=None):
+        """Device bytes the plan holds once reserved for pint_solve(params)
+        and pint_sl_steps(sl) (either may be None)."""
+        n = ctypes.c_size_t()
+        _check(load().pint_plan_workspace_bytes(
+            self._h, None if params is None else ctypes.byref(params),
+            None if sl is None else ctypes.byref(sl), ctypes.byref(n)))
+        return n.value
+
+    def reserve(self, params=None, sl=None, stream=None):
+        _check(load().pint_plan_reserve(self._h, None if params is None else ctypes.byref(params),
+                                        None if sl is None else ctypes.byref(sl),
+                                        _stream(stream)))
+
     def close(self):
         if getattr(self, "_h", None):
             load().pint_plan_destroy(self._h)
@@ -238,47 +271,61 @@ class Plan:
 
     # ---- entry points -------------------------------------------------
     def synthesis(self, spec, grid, B, stream=None):
-        _check(load().pint_synthesis(self._h, _ptr(spec), _ptr(grid), int(B), _stream(stream)))
+        _check(load().pint_synthesis(self._h, _ptr(spec, B * self.ncoef * 2),
+                                     _ptr(grid, B * self.nlat * self.nlon), int(B),
+                                     _stream(stream)))
 
     def analysis(self, grid, spec, B, stream=None):
-        _check(load().pint_analysis(self._h, _ptr(grid), _ptr(spec), int(B), _stream(stream)))
+        _check(load().pint_analysis(self._h, _ptr(grid, B * self.nlat * self.nlon),
+                                    _ptr(spec, B * self.ncoef * 2), int(B), _stream(stream)))
 
     def tendency(self, u, out, B, stream=None):
-        _check(load().pint_tendency(self._h, _ptr(u), _ptr(out), int(B), _stream(stream)))
+        n = self.state_numel(B)
+        _check(load().pint_tendency(self._h, _ptr(u, n), _ptr(out, n), int(B), _stream(stream)))
 
     def implicit(self, st, u, x, B, stream=None):
-        _check(load().pint_implicit(self._h, ctypes.byref(st), _ptr(u), _ptr(x), int(B),
+        n = self.state_numel(B)
+        _check(load().pint_implicit(self._h, ctypes.byref(st), _ptr(u, n), _ptr(x, n), int(B),
                                     _stream(stream)))
 
     def step(self, st, u_in, u_out, B, nsteps, stream=None):
-        _check(load().pint_step(self._h, ctypes.byref(st), _ptr(u_in), _ptr(u_out), int(B),
+        n = self.state_numel(B)
+        _check(load().pint_step(self._h, ctypes.byref(st), _ptr(u_in, n), _ptr(u_out, n), int(B),
                                 int(nsteps), _stream(stream)))
 
     def sl_steps(self, st, u, out, B, nsteps, u_prev=None, out_prev=None, stream=None):
         """nsteps SL-SI-SETTLS steps; u_prev None = one-step first step."""
-        _check(load().pint_sl_steps(self._h, ctypes.byref(st), _ptr(u_prev), _ptr(u), _ptr(out),
-                                    _ptr(out_prev), int(B), int(nsteps), _stream(stream)))
+        n = self.state_numel(B)
+        _check(load().pint_sl_steps(self._h, ctypes.byref(st), _ptr(u_prev, n), _ptr(u, n),
+                                    _ptr(out, n), _ptr(out_prev, n), int(B), int(nsteps),
+                                    _stream(stream)))
 
     def parareal_sl(self, fine, fine_steps, coarse, coarse_steps, n_slices, n_iter, u0, u_slices,
-                    n_inst=1, coarse_plan=None, stream=None):
+                    n_inst=1, coarse_plan=None, restart=False, stream=None):
         """Parareal with an SL-SI-SETTLS coarse propagator (fine: IMEX stepper);
-        u0 [n_inst] states, u_slices [n_slices + 1][n_inst] states."""
+        u0 [n_inst] states, u_slices [n_slices + 1][n_inst] states.  The sweep
+        carries the two-step scheme across slices (restart=True: one-step
+        variant at every slice start)."""
         cp = None if coarse_plan is None else coarse_plan._h
         _check(load().pint_parareal_sl(self._h, ctypes.byref(fine), int(fine_steps), cp,
                                        ctypes.byref(coarse), int(coarse_steps), int(n_slices),
-                                       int(n_inst), int(n_iter), _ptr(u0), _ptr(u_slices),
+                                       int(n_inst), int(n_iter), int(bool(restart)),
+                                       _ptr(u0, self.state_numel(n_inst)),
+                                       _ptr(u_slices, self.state_numel((n_slices + 1) * n_inst)),
                                        _stream(stream)))
 
     def solve(self, params, u0, u_slices, stream=None):
         rep = Report()
-        _check(load().pint_solve(self._h, ctypes.byref(params), _ptr(u0), _ptr(u_slices),
+        _check(load().pint_solve(self._h, ctypes.byref(params), _ptr(u0, self.state_numel()),
+                                 _ptr(u_slices, self.state_numel(params.n_intervals + 1)),
                                  ctypes.byref(rep), _stream(stream)))
         return rep
 
     def solve_status(self, params, u0, u_slices, stream=None):
         """Like solve() but returns (status, report, message) instead of raising."""
         rep = Report()
-        st = load().pint_solve(self._h, ctypes.byref(params), _ptr(u0), _ptr(u_slices),
+        st = load().pint_solve(self._h, ctypes.byref(params), _ptr(u0, self.state_numel()),
+                               _ptr(u_slices, self.state_numel(params.n_intervals + 1)),
                                ctypes.byref(rep), _stream(stream))
         msg = load().pint_last_error().decode(errors="replace") if st else ""
         return st, rep, msg
@@ -305,18 +352,22 @@ class Plan:
         import numpy as np
         out = np.zeros((B, 4))
         dp = ctypes.POINTER(ctypes.c_double)
-        _check(load().pint_rel_diff(self._h, _ptr(a), _ptr(c), out.ctypes.data_as(dp), int(B),
-                                    _stream(stream)))
+        n = self.state_numel(B)
+        _check(load().pint_rel_diff(self._h, _ptr(a, n), _ptr(c, n), out.ctypes.data_as(dp),
+                                    int(B), _stream(stream)))
         return out
 
-    # ---- diagnostics (Sec. 5, Sec. 6) ---------------------------------
+    # ---- diagnostics (Sec. 5, Sec. 5.1) ---------------------------------
     def ke_spectrum(self, u, e, B, stream=None):
         """e (device [B][M+1]) <- kinetic-energy spectrum of the B states u."""
-        _check(load().pint_ke_spectrum(self._h, _ptr(u), _ptr(e), int(B), _stream(stream)))
+        _check(load().pint_ke_spectrum(self._h, _ptr(u, self.state_numel(B)),
+                                       _ptr(e, B * (self.M + 1)), int(B), _stream(stream)))
 
     def spectral_errors(self, u, ref, e, B, stream=None):
         """e (device [B][3][M+1]) <- E_{psi,R} of (Phi', xi, delta), R = 0..M."""
-        _check(load().pint_spectral_errors(self._h, _ptr(u), _ptr(ref), _ptr(e), int(B),
+        n = self.state_numel(B)
+        _check(load().pint_spectral_errors(self._h, _ptr(u, n), _ptr(ref, n),
+                                           _ptr(e, B * 3 * (self.M + 1)), int(B),
                                            _stream(stream)))
 
     def grid_l2_errors(self, u, ref, B, stream=None):
@@ -324,8 +375,9 @@ class Plan:
         import numpy as np
         out = np.zeros((B, 3))
         dp = ctypes.POINTER(ctypes.c_double)
-        _check(load().pint_grid_l2_errors(self._h, _ptr(u), _ptr(ref), out.ctypes.data_as(dp),
-                                          int(B), _stream(stream)))
+        n = self.state_numel(B)
+        _check(load().pint_grid_l2_errors(self._h, _ptr(u, n), _ptr(ref, n),
+                                          out.ctypes.data_as(dp), int(B), _stream(stream)))
         return out
 
 
@@ -371,7 +423,10 @@ class Server:
             pass
 
     def submit(self, plan_index, params, u0, u_slices):
-        req = Request(int(plan_index), params, _ptr(u0), _ptr(u_slices))
+        ok = 0 <= plan_index < len(self._plans)      # else the library refuses the index
+        pl = self._plans[plan_index] if ok else None
+        req = Request(int(plan_index), params, _ptr(u0, pl.state_numel() if ok else None),
+                      _ptr(u_slices, pl.state_numel(params.n_intervals + 1) if ok else None))
         rid = ctypes.c_longlong()
         _check(load().pint_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)))
         self._keep[rid.value] = (u0, u_slices)      # device buffers outlive the request

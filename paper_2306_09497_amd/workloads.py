@@ -17,9 +17,9 @@ Y_{0,2} = sqrt(5) (3 mu^2 - 1) / 2.
 * ``jet_bump_grid``: a midlatitude zonal jet (smooth compact bump profile in
   latitude) in gradient-wind balance, plus a localised Gaussian height bump;
   returns grid-point (Phi, xi, delta) at caller-given Gauss latitudes.  This is
-  a synthetic stand-in with the shape of the unstable-jet test (Sec. 5.3), not
+  a synthetic stand-in with the shape of the unstable-jet test (Sec. 5.2), not
   its published profile.
-* ``gaussian_bumps_grid``: the Gaussian-bumps test case (Sec. 6): a fluid at
+* ``gaussian_bumps_grid``: the Gaussian-bumps test case (Sec. 5.1): a fluid at
   rest with mean depth hbar and three Gaussian height bumps of amplitude A at
   the printed centres and widths; geopotential Phi = g (hbar + A sum_i
   exp(-a_i d_i^2)), d_i the great-circle angle to centre i.  Grid-point
@@ -167,7 +167,7 @@ def jet_bump_params(seed, amp=120.0):
     return dict(lam_c=float(rng.uniform(0.0, 2.0 * math.pi)), amp=float(amp))
 
 
-# centres (longitude, latitude) and sharpness a_i of the three bumps (Sec. 6)
+# centres (longitude, latitude) and sharpness a_i of the three bumps (Sec. 5.1)
 GAUSSIAN_BUMPS = ((math.pi / 5, math.pi / 3, 20.0),
                   (6 * math.pi / 5, math.pi / 5, 80.0),
                   (8 * math.pi / 5, -math.pi / 4, 360.0))

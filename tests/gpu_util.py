@@ -1,5 +1,6 @@
 """Helpers shared by the GPU tests: conversions between the oracle's complex
-arrays and the library's (B, 3, ncoef, 2) float64 device tensors."""
+arrays and the library's (B, 3, ncoef, 2) float64 device tensors, and the
+FP64 parity bar."""
 
 import numpy as np
 
@@ -24,19 +25,99 @@ def field_rel(A, B, M):
     return rel_err(A, B, M)
 
 
-# FP64 parity bar (relative L2).  Phi' and the wind (vorticity + divergence
-# through the velocity they induce) must agree to 1e-11; the plain spectral
-# L2 of the divergence alone carries the float64 rounding floor of the
-# Laplacian of the kinetic energy (~1e-11 at T127/T255 for any float64
-# implementation, see oracle/norms.py), so it is held to a looser bound.
-TOL_STATE = 1e-11
-TOL_PLAIN = (1e-11, 1e-11, 2e-10)
+# FP64 parity bar (relative L2, area-weighted spectral norms).
+#
+# Phi' and the wind (the velocity that vorticity and divergence induce) are
+# well conditioned: after a step their float64 rounding error is ~1e-16, and
+# in one nonlinear tendency evaluation (N-eval) ~1e-14 (Phi') and 1.5-6e-13
+# (wind: the oracle itself against its x87 extended-precision evaluation
+# reaches 4e-13 at T255).  The divergence alone, in its own plain norm, is
+# ill conditioned for these nearly balanced states: it is a small residual of
+# cancelling terms, and the Laplacian of the kinetic energy in its tendency
+# multiplies rounding by n(n+1).  Its bar is per truncation, three times the
+# larger of two floors measured against the extended-precision oracle on the
+# test states: the float64 oracle's own and the GPU's (tests/test_gpu_floors.py
+# checks that the GPU's floor stays within a small factor of the oracle's).
+TOL_STATE = {"neval": (1e-13, 2e-12), "step": (1e-13, 1e-13), "slice": (1e-12, 1e-12),
+             "pint": (1e-11, 1e-11)}
+TOL_DELTA = {
+    "neval": {21: 1e-13, 63: 3e-12, 127: 1.5e-11, 255: 7e-11},
+    "step": {21: 1e-12, 63: 1e-11, 127: 2e-11, 255: 4e-11},
+    "slice": {21: 1e-11, 63: 1e-11, 127: 1e-11, 255: 1e-11},
+    "pint": {21: 5e-11, 63: 1e-11, 127: 1e-11, 255: 1e-11},
+}
+# T340 (1024 x 512, the largest ring): one N-eval of a jet, three times the
+# GPU's measured divergence error against the oracle
+TOL_DELTA["neval"][340] = 2e-10
+# C1's divergence is the 1e-6 noise alone: float64 rounding of the O(1)
+# vorticity puts its relative floor near 1e-16 / 1e-6 (the GPU and the oracle
+# differ by up to 1.1e-11 over all C1 iterates), hence the looser T21 bar
+# per-zonal-wavenumber bar: max over m of ||d_m|| / max(||ref_m||, ETA ||ref||)
+# for Phi' and the wind, so that an error confined to one m (one pair of
+# implicit chains, one Legendre block) is seen at its own scale whenever that
+# m carries at least ETA of the field
+PERM_ETA = 1e-4
+TOL_PERM = {"neval": 1e-11, "step": 1e-11, "slice": 1e-10, "pint": 1e-9, "sl": 1e-9}
+# semi-Lagrangian steps: interpolation at departure points computed in a
+# different order from the oracle's
+TOL_STATE["sl"] = (1e-11, 1e-11)
+TOL_DELTA["sl"] = {340: 2e-10}
 
 
-def assert_parity(got, ref, M, tol_state=TOL_STATE, tol_plain=TOL_PLAIN):
+def delta_bar(ctx, M):
+    """The divergence bar of the smallest tabulated truncation >= M (the
+    largest one beyond the table)."""
+    tab = TOL_DELTA[ctx]
+    keys = sorted(tab)
+    for k in keys:
+        if M <= k:
+            return tab[k]
+    return tab[keys[-1]]
+
+
+def per_m_errors(d, ref, M, a=6.37122e6, eta=PERM_ETA):
+    """(Phi', wind): max over m of ||d_m|| / max(||ref_m||, eta ||ref||), with
+    the area-weighted norms of the stopping test restricted to one m."""
+    from oracle.sht import m_slice
+    n = np.concatenate([np.arange(m, M + 1) for m in range(M + 1)]).astype(np.float64)
+    k = np.zeros_like(n)
+    k[n > 0] = a * a / (n[n > 0] * (n[n > 0] + 1.0))
+
+    def sq(x, f):
+        if f == 0:
+            y = x[0].copy()
+            y[0] = 0.0
+            return np.abs(y) ** 2
+        return k * (np.abs(x[1]) ** 2 + np.abs(x[2]) ** 2)
+
+    out = []
+    for f in (0, 1):
+        dd, rr = sq(d, f), sq(ref, f)
+        tot = np.sqrt(rr.sum())
+        worst = 0.0
+        for m in range(M + 1):
+            sl = m_slice(M, m)
+            den = max(np.sqrt(rr[sl].sum()), eta * tot)
+            if den > 0:
+                worst = max(worst, np.sqrt(dd[sl].sum()) / den)
+        out.append(worst)
+    return np.array(out)
+
+
+def assert_parity(got, ref, M, ctx="step", tol_state=None, tol_delta=None, tol_perm=None):
+    """got vs the oracle's ref: Phi' and the wind (relative L2), vorticity and
+    divergence in their own norms, and the per-m check; ctx selects the bar
+    ("neval", "step", "slice" or "pint")."""
     from oracle.norms import rel_err, state_rel_err
+    ts = TOL_STATE[ctx] if tol_state is None else tol_state
+    td = delta_bar(ctx, M) if tol_delta is None else tol_delta
+    tp = TOL_PERM[ctx] if tol_perm is None else tol_perm
     st = state_rel_err(got, ref, M)
     pl = rel_err(got, ref, M)
-    assert np.all(st < tol_state), ("state (Phi', wind) rel L2", st, "plain", pl)
-    assert np.all(pl < np.asarray(tol_plain)), ("plain (Phi', xi, delta) rel L2", pl, st)
+    pm = per_m_errors(got - ref, ref, M)
+    print(f"parity[{ctx} T{M}] state {st} plain {pl} per-m {pm}", flush=True)
+    assert st[0] < ts[0] and st[1] < ts[1], ("state (Phi', wind) rel L2", st, "plain", pl)
+    assert pl[0] < ts[0] and pl[1] < ts[1], ("plain Phi', xi", pl, st)
+    assert pl[2] < td, ("plain delta", pl, td, st)
+    assert np.all(pm < tp), ("per-m (Phi', wind)", pm, tp)
     return st, pl

@@ -83,7 +83,7 @@ def test_sl_entry_points_reject_a_null_plan():
     assert b"null plan" in lib.pint_last_error()
     fine = pint.stepper(60.0)
     assert lib.pint_parareal_sl(None, ctypes.byref(fine), 4, None, ctypes.byref(st), 1, 4, 1, 2,
-                                None, None, None) == -1
+                                0, None, None, None) == -1
     assert b"null plan" in lib.pint_last_error()
 
 
@@ -94,3 +94,46 @@ def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(pint.Stepper) == 32          # double, int (+4), double, unsigned (+4)
     assert ctypes.sizeof(pint.SlStepper) == 24        # double, int, int, double
     assert pint.SlStepper.traj_iters.offset == 8 and pint.SlStepper.visc_nu.offset == 16
+
+
+def test_struct_layouts_match_a_c_compiler(tmp_path):
+    """Sizes and field offsets of the ctypes mirrors equal those the host C
+    compiler gives the structs of include/pint.h."""
+    import shutil
+    import subprocess
+    from paper_2306_09497_amd import pint
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"pint_config": pint.Config, "pint_stepper": pint.Stepper,
+               "pint_sl_stepper": pint.SlStepper, "pint_info": pint.Info,
+               "pint_pint_params": pint.PintParams, "pint_report": pint.Report,
+               "pint_server_config": pint.ServerConfig, "pint_request": pint.Request,
+               "pint_request_status": pint.RequestStatus, "pint_prof_entry": pint.ProfEntry,
+               "pint_stability_cfg": pint.StabilityCfg}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pint.h"', "int main(void) {"]
+    for cname, cls in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    for line in out.splitlines():
+        cname, what, val = line.split()
+        cls = mirrors[cname]
+        got = ctypes.sizeof(cls) if what == "size" else getattr(cls, what).offset
+        assert got == int(val), (cname, what, got, val)
+
+
+def test_workspace_query_rejects_bad_arguments():
+    from paper_2306_09497_amd import pint
+    lib = pint.load()
+    n = ctypes.c_size_t()
+    assert lib.pint_plan_workspace_bytes(None, None, None, ctypes.byref(n)) == -1
+    assert b"null plan" in lib.pint_last_error()
+    assert lib.pint_plan_reserve(None, None, None, None) == -1

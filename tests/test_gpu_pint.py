@@ -64,7 +64,7 @@ def test_parareal_c1_all_iterates(setup, c1_oracle):
         got, rep = run_solve(pl, c1_params(k), U0, 8)
         assert rep.iters == min(k, 8)
         for n in range(9):
-            assert_parity(got[n], hist[k][n], M)
+            assert_parity(got[n], hist[k][n], M, "pint")
 
 
 def test_parareal_exact_bitwise(setup):
@@ -104,7 +104,7 @@ def test_mgrit_fcf_vs_oracle(setup):
         ref, _ = opint.mgrit2(U0, 6, 4, phi0, phi1, 1, k)
         got, rep = run_solve(pl, pint.params(pint.MGRIT, 6, f, 4, c, 1, nrelax=1, max_iter=k), U0, 6)
         for i in range(7):
-            assert_parity(got[i], ref[i], M)
+            assert_parity(got[i], ref[i], M, "pint")
         assert rep.fine_slice_steps == k * 6 * 4 * 2
 
 
@@ -201,7 +201,7 @@ def test_sweep_overlap_chunks_bitwise(method, nrelax):
     else:
         ref, _ = opint.parareal(U0, 8, phi0, phi1, 2)
     for i in range(9):
-        assert_parity(res[0][i], ref[i], M)
+        assert_parity(res[0][i], ref[i], M, "pint")
 
 
 def mgrit3_params(k, nrelax=1, cycles1=1, cfactor1=2, n=8):
@@ -227,7 +227,7 @@ def test_mgrit3_vs_oracle(setup, cycles1):
         got, rep = run_solve(pl, mgrit3_params(k, cycles1=cycles1), U0, 8)
         assert rep.iters == k
         for i in range(9):
-            assert_parity(got[i], ref[i], M)
+            assert_parity(got[i], ref[i], M, "pint")
 
 
 def test_mgrit3_one_level2_interval_is_two_level_bitwise(setup):
@@ -308,7 +308,7 @@ def test_spatial_coarsening_vs_oracle(setup, coarse_t10, method, nrelax, k):
         prm = pint.params(method, 8, f, 4, c, 2, nrelax=1, max_iter=k, coarse_plan=pc)
     got, _ = run_solve(pl, prm, U0, 8)
     for i in range(9):
-        assert_parity(got[i], ref[i], M)
+        assert_parity(got[i], ref[i], M, "pint")
 
 
 def test_spatial_coarsening_same_truncation_bitwise(setup):

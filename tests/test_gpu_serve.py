@@ -133,8 +133,10 @@ def test_server_argument_checks(plans):
     assert "two-level" in str(e.value)
     huge = pint.params(pint.PARAREAL, 40, prm.fine, prm.fine_steps, prm.coarse,
                        prm.coarse_steps, max_iter=1)
+    u1 = torch.zeros((1, 3, plans[1].ncoef, 2), dtype=torch.float64, device="cuda")
+    out1 = torch.zeros((41, 3, plans[1].ncoef, 2), dtype=torch.float64, device="cuda")
     with pytest.raises(pint.PintError) as e:
-        srv.submit(1, huge, u0, out)
+        srv.submit(1, huge, u1, out1)
     assert e.value.status == -2
     assert srv.tick() == 0                           # nothing was queued
     srv.close()
@@ -153,7 +155,7 @@ def test_served_parareal_vs_oracle(plans):
     ref = ref[0] if isinstance(ref, tuple) else ref
     got = from_dev(outs[0])
     for n in range(1, 5):
-        assert_parity(got[n], ref[n], M)
+        assert_parity(got[n], ref[n], M, "pint")
 
 
 def test_mixed_precision_plan_mix_equals_alone():

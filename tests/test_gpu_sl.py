@@ -1,5 +1,5 @@
 """GPU parity of the SL-SI-SETTLS steps (Sec. 2.3.2, one-step variant of
-Sec. 3.3) against the FP64 oracle, through the C ABI.  Bar: the FP64 parity
+Sec. 3.2.4) against the FP64 oracle, through the C ABI.  Bar: the FP64 parity
 bar of the IMEX path (relative L2 1e-11 on Phi' and the wind)."""
 
 import numpy as np
@@ -63,7 +63,7 @@ def test_one_step_variant(key, dt, iters):
     got = from_dev(run(plan, pint.sl_stepper(dt, iters), U, 1))
     ost = sl.SLStepper(md, dt, iters=iters)
     for b in range(3):
-        assert_parity(got[b], ost.step(U[b]), md.M)
+        assert_parity(got[b], ost.step(U[b]), md.M, "sl")
 
 
 def test_two_step_scheme_and_continuation():
@@ -77,8 +77,8 @@ def test_two_step_scheme_and_continuation():
     ost = sl.SLStepper(md, 1200.0, nu=1e5, q=2, iters=2)
     for b in range(3):
         want, wprev = ost.propagate(U[b], 3, Up[b])
-        assert_parity(from_dev(got)[b], want, md.M)
-        assert_parity(from_dev(gprev)[b], wprev, md.M)
+        assert_parity(from_dev(got)[b], want, md.M, "sl")
+        assert_parity(from_dev(gprev)[b], wprev, md.M, "sl")
     two, tprev = run(plan, st, U, 2, Uprev=Up, want_prev=True)
     u3 = torch.empty_like(two)
     plan.sl_steps(st, two, u3, 3, 1, u_prev=tprev)
@@ -108,7 +108,7 @@ def test_t127_coarse_configuration():
     ost = sl.SLStepper(md, 1800.0, nu=1e5, q=2, iters=2)
     for b in (0, 4):
         want, _ = ost.propagate(U[b], 3)
-        assert_parity(got[b], want, md.M)
+        assert_parity(got[b], want, md.M, "sl")
 
 
 def test_rejected_arguments():
@@ -134,13 +134,15 @@ def test_rejected_arguments():
     assert torch.equal(out, u) and torch.equal(prev, u)
 
 
+@pytest.mark.parametrize("restart", [False, True])
 @pytest.mark.parametrize("fine_key,coarse_key", [("T21", None), ("T42", "T21")])
-def test_parareal_with_sl_coarse(fine_key, coarse_key):
-    """Parareal (Sec. 3.1), fine IMEX, coarse SL-SI-SETTLS (one-step variant
-    at every slice start), 4 slices, 3 iterations, two instances at once,
-    against the oracle's Parareal with the same propagators (the coarse one
-    on the truncated state, padded back); an instance run alone is bitwise
-    the same."""
+def test_parareal_with_sl_coarse(fine_key, coarse_key, restart):
+    """Parareal (Sec. 3.1), fine IMEX, coarse SL-SI-SETTLS, 4 slices, 3
+    iterations, two instances at once, against the oracle's Parareal with
+    the same propagators (the coarse one on the truncated state, padded
+    back): the sweep carrying the two-step scheme across slices (Sec. 3.2.4,
+    coarsest level), or restarting it one-step at every slice; an instance
+    run alone is bitwise the same."""
     from oracle import pint as opint
     from oracle.sht import pad, truncate
     md, plan = setup(fine_key)
@@ -154,27 +156,36 @@ def test_parareal_with_sl_coarse(fine_key, coarse_key):
         mdc, cplan = setup(coarse_key)
     ost = sl.SLStepper(mdc, dtc, nu=1e6, q=2, iters=2)
 
-    def G(U):
-        Uc = np.stack([truncate(U[f], md.M, mdc.M) for f in range(3)])
-        Vc, _ = ost.propagate(Uc, csteps)
-        return np.stack([pad(Vc[f], mdc.M, md.M) for f in range(3)])
+    def tr(U):
+        return np.stack([truncate(U[f], md.M, mdc.M) for f in range(3)])
+
+    def pd(V):
+        return np.stack([pad(V[f], mdc.M, md.M) for f in range(3)])
+
+    def Gc(U, P):
+        """coarse run carrying the truncated last-but-one state"""
+        V, Q = ost.propagate(tr(U), csteps, P)
+        return pd(V), Q
 
     def F(U):
         return md.propagate(U, dtf, fsteps, nu=1e5, q=2)
 
     slices = torch.zeros((N + 1, 2, 3, md.grid.nc, 2), dtype=torch.float64, device="cuda")
     plan.parareal_sl(fine, fsteps, coarse, csteps, N, 3, to_dev(U0, torch), slices, n_inst=2,
-                     coarse_plan=cplan)
+                     coarse_plan=cplan, restart=restart)
     one = torch.zeros((N + 1, 1, 3, md.grid.nc, 2), dtype=torch.float64, device="cuda")
     plan.parareal_sl(fine, fsteps, coarse, csteps, N, 3, to_dev(U0[1:], torch), one, n_inst=1,
-                     coarse_plan=cplan)
+                     coarse_plan=cplan, restart=restart)
     torch.cuda.synchronize()
     assert torch.equal(one[:, 0], slices[:, 1])
     got = from_dev(slices)
     for i in range(2):
-        want, _ = opint.parareal(U0[i], N, F, G, 3)
+        if restart:
+            want, _ = opint.parareal(U0[i], N, F, lambda U: Gc(U, None)[0], 3)
+        else:
+            want, _ = opint.parareal_carry(U0[i], N, F, Gc, 3)
         for n in range(N + 1):
-            assert_parity(got[n, i], want[n], md.M)
+            assert_parity(got[n, i], want[n], md.M, "sl")
 
 
 def test_largest_ring_rest_and_steady_flow():

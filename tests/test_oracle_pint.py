@@ -249,3 +249,50 @@ def test_spatial_coarsening_parareal(c1_small):
     ser = pint.serial(U0, 4, fine)
     for a, b in zip(U, ser):
         assert np.array_equal(a, b)
+
+
+def _ab2_coarse(lam, h, steps):
+    """A two-step coarse scheme on u' = lam u (second-order Adams-Bashforth;
+    without a previous state the first step takes u_{n-1} = u_n, i.e. Euler):
+    (u, p) -> (u after `steps` steps, the state one step before it)."""
+    def G(u, p):
+        prev = u if p is None else p
+        for _ in range(steps):
+            u, prev = u + h * lam * (1.5 * u - 0.5 * prev), u
+        return u, prev
+    return G
+
+
+def test_parareal_carry_first_sweep_is_the_serial_two_step_run():
+    """Iterate 0 of the carried sweep equals the uninterrupted two-step run
+    over the whole horizon, bitwise (one-step only at its very first step)."""
+    lam, h, c, N = -0.3 + 1.1j, 0.05, 3, 6
+    G = _ab2_coarse(lam, h, c)
+    U, _ = pint.parareal_carry(1.0 + 0.5j, N, lambda u: u, G, 0)
+    u, prev = 1.0 + 0.5j, None
+    for n in range(N):
+        u, prev = G(u, prev)
+        assert U[n + 1] == u
+    # the same run restarted one-step at every slice differs
+    R, _ = pint.parareal(1.0 + 0.5j, N, lambda u: u, lambda u: G(u, None)[0], 0)
+    assert R[2] != U[2]
+
+
+def test_parareal_carry_without_history_is_parareal():
+    """A coarse scheme that ignores its carried state gives Parareal's
+    iterates bitwise; with k = N the carried sweep ends at the serial fine
+    solution bitwise (finite termination, Sec. 3.1)."""
+    lam, N = 0.2 - 0.9j, 5
+    F = np.exp(lam * 0.5)
+    R = 1.0 + lam * 0.5
+
+    def fine(u):
+        return F * u
+
+    for k in range(N + 1):
+        A, _ = pint.parareal_carry(1.0 + 0j, N, fine, lambda u, p: (R * u, u), k)
+        B, _ = pint.parareal(1.0 + 0j, N, fine, lambda u: R * u, k)
+        assert A == B
+    G = _ab2_coarse(lam, 0.1, 5)
+    U, _ = pint.parareal_carry(1.0 + 0j, N, fine, G, N)
+    assert U == pint.serial(1.0 + 0j, N, fine)

@@ -1,4 +1,4 @@
-"""Pins of the SL-SI-SETTLS oracle (Sec. 2.3.2, Sec. 3.3) against closed
+"""Pins of the SL-SI-SETTLS oracle (Sec. 2.3.2, Sec. 3.2.4) against closed
 forms and against the dense Galerkin operator of the IMEX oracle."""
 
 import math
