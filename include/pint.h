@@ -169,6 +169,25 @@ pint_status pint_implicit(pint_plan* plan, const pint_stepper* st, const double*
 pint_status pint_step(pint_plan* plan, const pint_stepper* st, const double* u_in, double* u_out,
                       int B, int nsteps, void* stream);
 
+/* pint_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation and the same results, bitwise, with every buffer
+ * beyond u_in, u_out and the plan's tables -- the Crank-Nicolson factors of
+ * st (made by a kernel in each call) and the transform workspace -- taken
+ * from one static device array of the library, 64 MiB per device, held
+ * until the process ends.  The call allocates and frees nothing and reads no
+ * plan cache.  Its states are processed in chunks of the largest count, at
+ * most max_batch, whose workspace fits the array; a state that does not fit
+ * alone (26 MiB for one state at T255 with its factors, 46 MiB at T340; a
+ * truncation above about T430 needs more than 64 MiB) is refused with
+ * PINT_E_INVAL.
+ * Every call on a device shares that device's array, so calls that overlap
+ * in time on one device (different streams, or threads) race: order them.
+ * The plan must have been created on the current device.  Arguments,
+ * layouts and errors otherwise as pint_step.  */
+pint_status pint_step_noalloc(pint_plan* plan, const pint_stepper* st, const double* u_in,
+                              double* u_out, int B, int nsteps, void* stream);
+
 /* nsteps SL-SI-SETTLS steps (Sec. 2.3.2, eqs. SETTLS_trajectories and
  * SL_SI_SETTLS) of B independent states.  Each step traces the trajectories
  * arriving at the Gauss grid points back to their departure points (in 3-D,

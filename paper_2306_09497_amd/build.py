@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpint.so")
-SOURCES = ["plan.hip", "spectral.hip", "legendre.hip", "ring.hip", "diagnostics.hip", "stability.hip", "serve.hip", "sl.hip", "api.hip"]
+SOURCES = ["plan.hip", "spectral.hip", "legendre.hip", "ring.hip", "diagnostics.hip", "stability.hip", "serve.hip", "sl.hip", "api.hip", "noalloc.hip"]
 ARCH = os.environ.get("PINT_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

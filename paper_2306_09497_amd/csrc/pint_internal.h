@@ -189,6 +189,8 @@ pint_status build_tables(Plan& p, hipStream_t s);
 pint_status cn_factors(Plan& p, double dt, unsigned terms, hipStream_t s, const CnFactors** out);
 pint_status cn_factors_fill(const Plan& p, double dt, unsigned terms, const CnFactors& f,
                             hipStream_t s);
+// the library's static scratch of the current device (set up at plan creation)
+pint_status noalloc_init_device();
 
 // Spectral kernels on public-layout states (one wave per (m, state)):
 //  sp_cn_prep  Ua = CN(in) (no viscosity); S = synthesis input of Ua

@@ -432,6 +432,12 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
                      p.coefmn, p.cnco);
   if ((e = hipGetLastError()) != hipSuccess) return fail_hip(e, "table kernels");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+  // the device address of the library's static scratch on this device
+  if ((st = noalloc_init_device()) != PINT_OK) {
+    free_plan(p);
+    delete pp;
+    return st;
+  }
   *out = pp;
   return PINT_OK;
 #undef PLAN_TRY

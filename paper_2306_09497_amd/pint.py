@@ -24,7 +24,7 @@ STATUS = {0: "PINT_OK", -1: "PINT_E_INVAL", -2: "PINT_E_NOMEM", -3: "PINT_E_HIP"
 
 EXPORTS = ["pint_plan_create", "pint_plan_destroy", "pint_plan_info", "pint_plan_workspace_bytes",
            "pint_plan_reserve", "pint_grid_coords",
-           "pint_synthesis", "pint_analysis", "pint_tendency", "pint_implicit", "pint_step",
+           "pint_synthesis", "pint_analysis", "pint_tendency", "pint_implicit", "pint_step", "pint_step_noalloc",
            "pint_sl_steps", "pint_parareal_sl", "pint_solve", "pint_rel_diff", "pint_ke_spectrum", "pint_spectral_errors",
            "pint_grid_l2_errors", "pint_stability_map", "pint_server_create", "pint_server_destroy",
            "pint_server_submit", "pint_server_tick", "pint_server_status", "pint_server_clock",
@@ -146,6 +146,7 @@ def load(path=LIB_PATH):
     lib.pint_tendency.argtypes = [vp, vp, vp, ip, vp]
     lib.pint_implicit.argtypes = [vp, ctypes.POINTER(Stepper), vp, vp, ip, vp]
     lib.pint_step.argtypes = [vp, ctypes.POINTER(Stepper), vp, vp, ip, ip, vp]
+    lib.pint_step_noalloc.argtypes = [vp, ctypes.POINTER(Stepper), vp, vp, ip, ip, vp]
     lib.pint_solve.argtypes = [vp, ctypes.POINTER(PintParams), vp, vp, ctypes.POINTER(Report), vp]
     lib.pint_rel_diff.argtypes = [vp, vp, vp, dp, ip, vp]
     lib.pint_ke_spectrum.argtypes = [vp, vp, vp, ip, vp]
@@ -292,6 +293,12 @@ class Plan:
         n = self.state_numel(B)
         _check(load().pint_step(self._h, ctypes.byref(st), _ptr(u_in, n), _ptr(u_out, n), int(B),
                                 int(nsteps), _stream(stream)))
+
+    def step_noalloc(self, st, u_in, u_out, B, nsteps, stream=None):
+        """pint_step without device allocation (the library's static scratch)."""
+        n = self.state_numel(B)
+        _check(load().pint_step_noalloc(self._h, ctypes.byref(st), _ptr(u_in, n), _ptr(u_out, n),
+                                        int(B), int(nsteps), _stream(stream)))
 
     def sl_steps(self, st, u, out, B, nsteps, u_prev=None, out_prev=None, stream=None):
         """nsteps SL-SI-SETTLS steps; u_prev None = one-step first step."""
