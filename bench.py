@@ -106,9 +106,16 @@ def measured_traffic(kind, prec=0):
 
 
 def cpu_baseline(seconds):
-    """The FP64 oracle on this host: fine IMEX steps of one T255 slice."""
+    """The FP64 oracle on this host: fine IMEX steps of one T255 slice (the
+    headline's unit of work), each step timed, for about `seconds`; the median
+    step time at T21 and T127 (5 steps each); the end-to-end C1 Parareal run
+    (T21 on 64x32, solid body + 1e-6 noise, 8 slices of 180 fine steps of
+    60 s, coarse 3 x 3600 s, 8 iterations); and the serial-fine times of C2
+    (11 520 steps at T127) and C3 (3 840 steps at T255) extrapolated from the
+    median step times."""
     import numpy as np
     from threadpoolctl import threadpool_info
+    from oracle import pint as opint
     from oracle.swe import Model
     from paper_2306_09497_amd import workloads
 
@@ -116,39 +123,54 @@ def cpu_baseline(seconds):
     G = workloads.jet_bump_grid(md.grid.mu, NLON, phibar=PHIBAR, **workloads.jet_bump_params(0))
     U = np.stack([md.grid.anal(G[f]) for f in range(3)])
     md.imex_step(U, DT_FINE)                  # untimed: builds the per-m LU factors
-    n = 0
+    ts = []
     t0 = time.perf_counter()
     while True:
+        a = time.perf_counter()
         U = md.imex_step(U, DT_FINE)
-        n += 1
-        if time.perf_counter() - t0 >= seconds:
+        ts.append(time.perf_counter() - a)
+        if time.perf_counter() - t0 >= seconds and len(ts) >= 5:
             break
     dt = time.perf_counter() - t0
+    n = len(ts)
     threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    # median time per fine step at the smaller truncations (5 steps each after
-    # one untimed step that builds the LU factors)
-    per = {"T255": 1e3 * dt / n}
+    per = {"T255": 1e3 * float(np.median(ts))}
+    spread = {"T255": [1e3 * float(np.percentile(ts, 10)), 1e3 * float(np.percentile(ts, 90))]}
     for Mt, nl, nt in ((21, 64, 32), (127, 384, 192)):
         mt = Model(Mt, nl, nt, phibar=PHIBAR)
         Gt = workloads.jet_bump_grid(mt.grid.mu, nl, phibar=PHIBAR, **workloads.jet_bump_params(0))
         Ut = mt.imex_step(np.stack([mt.grid.anal(Gt[f]) for f in range(3)]), DT_FINE)
-        ts = []
+        tt = []
         for _ in range(5):
             a = time.perf_counter()
             Ut = mt.imex_step(Ut, DT_FINE)
-            ts.append(time.perf_counter() - a)
-        per[f"T{Mt}"] = 1e3 * float(np.median(ts))
+            tt.append(time.perf_counter() - a)
+        per[f"T{Mt}"] = 1e3 * float(np.median(tt))
+    # C1 end to end
+    m1 = Model(21, 64, 32, phibar=2.94e4)
+    u0 = workloads.solid_body(21, noise=1e-6, seed=0)
+    m1.imex_step(u0, 60.0)
+    m1.imex_step(u0, 3600.0)
+    a = time.perf_counter()
+    opint.parareal(u0, 8, lambda u: m1.propagate(u, 60.0, 180),
+                   lambda u: m1.propagate(u, 3600.0, 3), 8)
+    c1_s = time.perf_counter() - a
     cpu = ""
     try:
         with open("/proc/cpuinfo") as f:
             cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": n / dt, "unit": "fine slice-steps/s", "cores": threads, "kind": "oracle",
+    return {"value": 1e3 / per["T255"], "unit": "fine slice-steps/s", "cores": threads,
+            "kind": "oracle",
             "sample": f"{n} fine IMEX steps (dt {DT_FINE:g} s) of one T255 768x384 jet+bump "
-                      f"slice after LU setup, {dt:.1f} s; host has "
+                      f"slice after LU setup, {dt:.1f} s, value from the median step; host has "
                       f"{len(os.sched_getaffinity(0))} cores available",
-            "ms_per_fine_step": per, "cpu": cpu}
+            "ms_per_fine_step_median": per, "ms_per_fine_step_p10_p90": spread,
+            "c1_parareal_end_to_end_s": c1_s,
+            "serial_fine_extrapolated_s": {"C2_T127_11520_steps": 11520 * per["T127"] * 1e-3,
+                                           "C3_T255_3840_steps": 3840 * per["T255"] * 1e-3},
+            "cpu": cpu}
 
 
 def e_phi_r(phi, ref, mmax, R=32):
@@ -164,28 +186,34 @@ def e_phi_r(phi, ref, mmax, R=32):
     return float(d / np.abs(ref[sel]).max())
 
 
-def time_to_tol():
-    """Parareal to a relative increment of 1e-8 (cap N iterations) at T127
-    (384x192, 64 slices of 5400 s, fine IMEX 30 s x 180, coarse IMEX 900 s x 6
-    with q=4 nu=1e17, jet + bump), timed against (i) serial fine propagation
-    (batch 1, 11 520 steps) and (ii) the same Parareal with every slice
-    propagated by its own launches (a plan of max_batch 1: batch invariance
-    makes its iterates bitwise those of the batched run).  nu = 1e15 as first
-    specified makes the 900 s coarse step unstable at n = 127 for this jet;
-    1e17 is the paper's unviscous-fine / IMEX-coarse value for large coarse
-    steps.  Also reported, untimed: the error of every iterate against serial
-    fine (E_Phi,32 and relative L2)."""
+def time_to_tol(per_slice_iters=2):
+    """Parareal to a relative increment of 1e-8 in the C2 shape: T127
+    (384x192), 64 slices of 5400 s (4 days), fine IMEX 30 s x 180, jet +
+    bump.  The coarse level C2 specifies (IMEX 900 s x 6, q = 4, nu = 1e17:
+    nu = 1e15 makes that step unstable for the jet) does not converge: the
+    coarse viscosity damps the high modes that the fine level keeps, whose
+    error then moves one slice per iteration (its increments are reported).
+    The timed run uses a coarse level that converges: IMEX 100 s x 54 without
+    viscosity.  Timed against (i) serial fine propagation (batch 1, 11 520
+    steps) and (ii) the plain FP64 per-slice method: the same Parareal with
+    every slice propagated by its own launches (a plan of max_batch 1; batch
+    invariance makes its iterates bitwise those of the batched run, checked
+    on its first iterations, whose time per iteration is carried over to the
+    batched run's iteration count)."""
     import numpy as np
     import torch
     from paper_2306_09497_amd import pint, workloads
 
     Mc, nlon, nlat, N = 127, 384, 192, 64
     fine = pint.stepper(30.0, 2, 0.0, pint.T_ALL)
-    coarse = pint.stepper(900.0, 4, 1.0e17, pint.T_ALL)
-    prm = pint.params(pint.PARAREAL, N, fine, 180, coarse, 6, max_iter=N, tol=1e-8)
+    conv = pint.stepper(100.0, 2, 0.0, pint.T_ALL)
+    spec = pint.stepper(900.0, 4, 1.0e17, pint.T_ALL)
+    prm = pint.params(pint.PARAREAL, N, fine, 180, conv, 54, max_iter=N, tol=1e-8)
     torch.cuda.init()
     plans = {b: pint.Plan(Mc, nlon, nlat, phibar=PHIBAR, max_batch=b) for b in (N, 1)}
     pl = plans[N]
+    for p_ in plans.values():
+        p_.reserve(prm)
     mu, _ = pl.grid_coords()
     G = workloads.jet_bump_grid(mu, nlon, phibar=PHIBAR, **workloads.jet_bump_params(0))
     grid = torch.from_numpy(np.ascontiguousarray(G)).cuda()
@@ -195,7 +223,7 @@ def time_to_tol():
     ref = torch.zeros((N + 1, 3, pl.ncoef, 2), dtype=torch.float64, device="cuda")
     ref[0] = u0[0]
     u = u0.clone()
-    plans[1].step(fine, u, u, 1, 180)                    # warm-up (factors, code)
+    plans[1].step(fine, u, u, 1, 180)                    # warm-up (code)
     u.copy_(u0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -215,36 +243,50 @@ def time_to_tol():
                 "max_rel_l2_wind": float(d[:, 3].max())}
 
     out = {"config": "T127 384x192, 64 slices x 5400 s (4 days), fine IMEX 30 s x 180, coarse "
-                     "IMEX 900 s x 6 with q=4 nu=1e17, jet + bump, Parareal to increment 1e-8 "
+                     "IMEX 100 s x 54 without viscosity, jet + bump, Parareal to increment 1e-8 "
                      "(cap 64 = N)",
            "serial_fine_s": t_ref, "serial_fine_steps": N * 180}
-    runs = {}
-    for name, b in (("parareal_batched", N), ("parareal_per_slice", 1)):
-        slices = torch.zeros((N + 1, 3, pl.ncoef, 2), dtype=torch.float64, device="cuda")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st, rep, msg = plans[b].solve_status(prm, u0, slices)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        runs[name] = slices
-        out[name] = {"status": st, "iters": rep.iters, "seconds": el,
-                     "speedup_vs_serial_fine": t_ref / el,
-                     "fine_slice_steps": rep.fine_slice_steps,
-                     "increments": [rep.incr[i] for i in range(rep.iters)], **errors(slices)}
-    out["per_slice_iterates_bitwise_equal"] = bool(
-        torch.equal(runs["parareal_batched"], runs["parareal_per_slice"]))
-    out["batched_vs_per_slice_speedup"] = (out["parareal_per_slice"]["seconds"]
-                                           / out["parareal_batched"]["seconds"])
-    # error of every iterate against serial fine (untimed; one iteration per call)
-    curve = []
     slices = torch.zeros((N + 1, 3, pl.ncoef, 2), dtype=torch.float64, device="cuda")
-    pl.solve(pint.params(pint.PARAREAL, N, fine, 180, coarse, 6, max_iter=0), u0, slices)
-    one = pint.params(pint.PARAREAL, N, fine, 180, coarse, 6, max_iter=1, resume=True)
-    for k in range(out["parareal_batched"]["iters"]):
-        pl.solve(one, u0, slices)
-        e = errors(slices)
-        curve.append([round(e["E_phi_32_final"], 12), round(e["max_rel_l2_phi_prime"], 12)])
-    out["error_per_iteration_E_phi_32_and_rel_l2"] = curve
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, rep, msg = pl.solve_status(prm, u0, slices)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    iters = rep.iters
+    out["parareal_batched"] = {
+        "status": st, "iters": iters, "seconds": el, "time_to_tol_vs_serial_fine": el / t_ref,
+        "speedup_vs_serial_fine": t_ref / el, "fine_slice_steps": rep.fine_slice_steps,
+        "fine_slice_steps_per_s": rep.fine_slice_steps / el,
+        "increments": [rep.incr[i] for i in range(iters)], **errors(slices)}
+    # (ii) per-slice launches: the first iterations, timed, and bitwise the
+    # batched run's iterates at that count
+    k = min(per_slice_iters, iters)
+    short = pint.params(pint.PARAREAL, N, fine, 180, conv, 54, max_iter=k)
+    a = torch.zeros_like(slices)
+    b = torch.zeros_like(slices)
+    pl.solve(short, u0, a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rp = plans[1].solve(short, u0, b)
+    torch.cuda.synchronize()
+    el1 = time.perf_counter() - t0
+    # a Parareal iteration k recomputes N - k slices: scale by the work
+    work_k = sum(N - i for i in range(k))
+    work_all = sum(N - i for i in range(iters))
+    t_ps = el1 * work_all / work_k
+    out["parareal_per_slice"] = {
+        "iterations_timed": k, "seconds_timed": el1, "seconds_extrapolated": t_ps,
+        "iterates_bitwise_equal_to_batched": bool(torch.equal(a, b)),
+        "note": "time of the first iterations scaled by the fine work of the batched run's "
+                "iteration count (iteration k recomputes N - k slices)"}
+    out["batched_vs_per_slice_speedup"] = t_ps / el
+    # the coarse level as specified for C2: increments of its first iterations
+    q2 = pint.params(pint.PARAREAL, N, fine, 180, spec, 6, max_iter=8)
+    s2 = torch.zeros_like(slices)
+    r2 = pl.solve(q2, u0, s2)
+    out["c2_specified_coarse_increments"] = {
+        "coarse": "IMEX 900 s x 6, q=4, nu=1e17",
+        "increments": [r2.incr[i] for i in range(r2.iters)]}
     for p_ in plans.values():
         p_.close()
     return out
@@ -282,10 +324,11 @@ def measure(precision, steps, warmup, levels=2, coarse_grid=None, coarse_precisi
     if levels == 3:
         extra.update(levels=3, cfactor1=CFACTOR, coarse2_steps=1, cycles1=2,
                      coarse2=pint.stepper(DT_COARSE * CFACTOR, Q_COARSE, NU_COARSE, pint.T_ALL))
-    plan.solve(pint.params(pint.MGRIT, GROUP, fine, CFACTOR, coarse, 1, nrelax=1, max_iter=0,
-                           coarse_plan=cplan), u0, slices)     # initial coarse sweep
     it = pint.params(pint.MGRIT, GROUP, fine, CFACTOR, coarse, 1, nrelax=1, max_iter=1,
                      resume=True, **extra)
+    plan.reserve(it)            # scratch and factors allocated, GEMM launch shapes tuned
+    plan.solve(pint.params(pint.MGRIT, GROUP, fine, CFACTOR, coarse, 1, nrelax=1, max_iter=0,
+                           coarse_plan=cplan), u0, slices)     # initial coarse sweep
     for _ in range(warmup):
         plan.solve(it, u0, slices)
     torch.cuda.synchronize()
@@ -305,12 +348,22 @@ def measure(precision, steps, warmup, levels=2, coarse_grid=None, coarse_precisi
     t1 = time.perf_counter()
     prof = plan.profile_read()
     plan.profile([])
+    info = plan.info()
+    names = {(0, 0): ["k-slab 16", "k-slab 32"], (1, 0): ["k-slab 16", "k-slab 32"],
+             (0, 1): ["64 columns", "128 columns"],
+             (1, 1): ["64 columns", "64 columns, k-slab 32", "128 columns"]}
+    shapes = {}
+    for (k, c), label in (((0, 0), "synthesis_1_state"), ((0, 1), "synthesis_64_states"),
+                          ((1, 0), "analysis_1_state"), ((1, 1), "analysis_64_states")):
+        v = info.gemm_shape[k][c]
+        shapes[label] = {"shape": names[(k, c)][v] if v < len(names[(k, c)]) else v,
+                         "tuned_us_per_launch": info.gemm_us[k][c]}
     plan.close()
     if cplan is not None:
         cplan.close()
     elapsed = t1 - t0
     return {"value": fine_steps / elapsed, "elapsed": elapsed, "fine_steps": fine_steps,
-            "prof": prof, "incr": incr, "slices": slices}
+            "prof": prof, "incr": incr, "slices": slices, "gemm_shapes": shapes}
 
 
 def measure_diagnostics(slices, reps=20):
@@ -476,7 +529,7 @@ def measure_sl(reps=10):
 
 
 def serve_bench(seconds, rate, max_iter=2, seed=0, steps_per_tick=8, arena_gb=96.0,
-                precision=0, tol=0.0):
+                precision=0, tol=0.0, max_batch=GROUP, stage_states=2 * GROUP):
     """Serving with continuous batching: Poisson arrivals (rate per second for
     `seconds`) of Parareal or two-level MGRIT (FCF) requests, uniform over
     T63 192x96 / T127 384x192 / T255 768x384, 16/32/64/128 slices and 1-4 day
@@ -493,7 +546,7 @@ def serve_bench(seconds, rate, max_iter=2, seed=0, steps_per_tick=8, arena_gb=96
     from paper_2306_09497_amd import pint, workloads
 
     grids = [(63, 192, 96, 1.6e18), (127, 384, 192, 1.0e17), (255, 768, 384, 6.25e15)]
-    plans = [pint.Plan(Mg, nl, nt, phibar=PHIBAR, max_batch=GROUP, precision=precision)
+    plans = [pint.Plan(Mg, nl, nt, phibar=PHIBAR, max_batch=max_batch, precision=precision)
              for Mg, nl, nt, _ in grids]
     rng = np.random.default_rng(seed)
     # a few analysed initial states per truncation, made before timing
@@ -527,8 +580,13 @@ def serve_bench(seconds, rate, max_iter=2, seed=0, steps_per_tick=8, arena_gb=96
                           pint.stepper(675.0, 4, grids[gi][3], pint.T_ALL), cs,
                           nrelax=method, max_iter=max_iter, tol=tol)
         reqs.append((t, gi, prm, int(rng.integers(3))))
+    # the plans ready for every stepper pair the requests use (factor sets,
+    # GEMM launch shapes), so nothing is allocated or tuned while serving
+    for pl, (_, _, _, nu) in zip(plans, grids):
+        pl.reserve(pint.params(pint.MGRIT, 16, pint.stepper(45.0, 2, 0.0, pint.T_ALL), 120,
+                               pint.stepper(675.0, 4, nu, pint.T_ALL), 8, nrelax=1, max_iter=1))
     srv = pint.Server(plans, int(arena_gb * 2**30), steps_per_tick=steps_per_tick,
-                      stage_states=2 * GROUP)
+                      stage_states=stage_states)
     torch.cuda.synchronize()
     ids, outs = [], []
     t0 = srv.clock()
@@ -576,10 +634,74 @@ def serve_bench(seconds, rate, max_iter=2, seed=0, steps_per_tick=8, arena_gb=96
                                "1-4 days, fine 45 s, coarse 675 s, Parareal or MGRIT FCF, "
                                + (f"stop at increment {tol:g} (at most {max_iter} iterations)"
                                   if tol > 0 else f"{max_iter} iterations"),
-                   "steps_per_tick": steps_per_tick,
+                   "steps_per_tick": steps_per_tick, "max_batch": max_batch,
+                   "stage_states": stage_states,
                    "legendre_precision": ["fp64", "fp32"][precision]},
         "data": "synthetic", "dtype": "f64" if precision == 0 else "f64 state, f32 transforms",
     }
+
+
+def serve_c5(seconds=1.5, rate=20.0, max_iter=3, tol=1e-6):
+    """The serving workload at its configured arrival rate (20/s) for a short
+    window, in the north-star's mixed precision (FP32 Legendre plans) with
+    each request stopping at an increment of tol (at most max_iter
+    iterations), against the plain FP64 per-slice method on the same request
+    stream: FP64 plans of max_batch 1 whose launches are never merged (one
+    state per staging buffer), the same stopping rule."""
+    merged = serve_bench(seconds, rate, max_iter=max_iter, precision=1, tol=tol)
+    plain = serve_bench(seconds, rate, max_iter=max_iter, precision=0, tol=tol, max_batch=1,
+                        stage_states=1)
+    keep = ("requests", "completed", "diverged", "not_converged", "makespan_s",
+            "offered_fine_slice_steps_per_s", "achieved_fine_slice_steps_per_s",
+            "latency_p50_s", "latency_p99_s", "queue_mean_s", "service_mean_s",
+            "latency_p50_by_truncation_s", "iterations_mean")
+    return {"arrival_window_s": seconds, "rate_per_s": rate,
+            "stopping": f"increment <= {tol:g}, at most {max_iter} iterations",
+            "fp32_legendre_merged": {k: merged[k] for k in keep},
+            "fp64_per_slice": {k: plain[k] for k in keep},
+            "p99_ratio_per_slice_over_merged": plain["latency_p99_s"] / merged["latency_p99_s"],
+            "throughput_ratio_merged_over_per_slice": (merged["achieved_fine_slice_steps_per_s"]
+                                                       / plain["achieved_fine_slice_steps_per_s"])}
+
+
+def c3_full_horizon(iters=2):
+    """C3 at its stated horizon: two days at T255 (768x384), fine IMEX 45 s,
+    960 C-intervals of cfactor 4 (15 slice groups of 64), coarse IMEX 180 s
+    with q = 4, nu = 1e17; two-level MGRIT FCF over all 960 intervals (a
+    959-step serial sweep), `iters` iterations after the initial coarse
+    sweep, in one pint_solve call."""
+    import numpy as np
+    import torch
+    from paper_2306_09497_amd import pint, workloads
+
+    N = 960
+    plan = pint.Plan(M, NLON, NLAT, phibar=PHIBAR, max_batch=GROUP)
+    mu, _ = plan.grid_coords()
+    G = workloads.jet_bump_grid(mu, NLON, phibar=PHIBAR, **workloads.jet_bump_params(0))
+    grid = torch.from_numpy(np.ascontiguousarray(G)).cuda()
+    u0 = torch.zeros((1, 3, plan.ncoef, 2), dtype=torch.float64, device="cuda")
+    plan.analysis(grid, u0, 3)
+    fine = pint.stepper(DT_FINE, 2, 0.0, pint.T_ALL)
+    coarse = pint.stepper(DT_COARSE, Q_COARSE, NU_COARSE, pint.T_ALL)
+    q = pint.params(pint.MGRIT, N, fine, CFACTOR, coarse, 1, nrelax=1, max_iter=iters)
+    footprint = plan.workspace_query(q)
+    plan.reserve(q)
+    slices = torch.zeros((N + 1, 3, plan.ncoef, 2), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = plan.solve(q, u0, slices)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    it_s = [rep.seconds[i] for i in range(rep.iters)]
+    out = {"config": "T255 768x384, 2 days, 960 C-intervals x cfactor 4, fine 45 s, coarse 180 s "
+                     "q=4 nu=1e17, MGRIT FCF, one solve call",
+           "iterations": rep.iters, "seconds_total": el, "seconds_per_iteration": it_s,
+           "initial_sweep_s": el - sum(it_s),
+           "fine_slice_steps_per_s_in_iterations": (rep.fine_slice_steps / sum(it_s)),
+           "increments": [rep.incr[i] for i in range(rep.iters)],
+           "device_footprint_gb": footprint / 1e9, "finite": bool(torch.isfinite(slices).all())}
+    plan.close()
+    return out
 
 
 def field_errors(a, b):
@@ -596,12 +718,20 @@ def field_errors(a, b):
     return out
 
 
+_T_START = time.perf_counter()
+
+
+def progress(what):
+    """One line per finished leg on stderr (the JSON line stays on stdout)."""
+    print(f"[bench] {what} ({time.perf_counter() - _T_START:.0f} s)", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16x3"], default="fp64",
                     help="transform precision of the headline (fp32: FP32 Legendre GEMMs, "
@@ -617,6 +747,12 @@ def main():
                     help="skip the SL-SI-SETTLS coarse-step timing of the default run")
     ap.add_argument("--time-to-tol", action="store_true",
                     help="print the T127 Parareal time-to-tolerance measurement instead")
+    ap.add_argument("--no-time-to-tol", action="store_true",
+                    help="skip the T127 time-to-tolerance leg of the default run")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the bounded serving leg (20/s arrivals) of the default run")
+    ap.add_argument("--no-c3-full", action="store_true",
+                    help="skip the two-day, 960-interval MGRIT leg of the default run")
     ap.add_argument("--serve", type=float, nargs=2, metavar=("SECONDS", "RATE"),
                     help="print the continuous-batching serving measurement instead "
                          "(Poisson arrivals at RATE per second for SECONDS)")
@@ -644,6 +780,7 @@ def main():
     torch.cuda.init()
     prec = {"fp64": pint.FP64, "fp32": pint.LEG_FP32, "bf16x3": pint.LEG_BF16X3}[args.precision]
     res = measure(prec, args.steps, args.warmup)
+    progress("headline")
     prof, elapsed, fine_steps, value = res["prof"], res["elapsed"], res["fine_steps"], res["value"]
     incr = res["incr"]
     peak_mfma = {pint.FP64: PEAK_FP64, pint.LEG_FP32: PEAK_FP32,
@@ -702,6 +839,7 @@ def main():
         },
         "roofline": roof,
         "kernels": kernels,
+        "gemm_shapes": res["gemm_shapes"],
         "mgrit_increment": incr,
     }
     if prec == pint.FP64 and not args.no_mixed:
@@ -721,6 +859,7 @@ def main():
                 "iterations_compared": args.warmup + args.steps,
             }
             del rm
+            progress(name)
         out["mixed_precision"] = mixed
     if prec == pint.FP64 and not args.no_mgrit3:
         # the same slice group with three MGRIT levels: the level-1 problem by
@@ -737,6 +876,7 @@ def main():
             }
         except Exception as e:                      # reported, not fatal
             out["mgrit3"] = {"error": str(e)}
+        progress("mgrit3")
         # two levels with spatial coarsening: the coarse level at T127 (384x192)
         try:
             rc = measure(pint.FP64, args.steps, args.warmup, coarse_grid=(127, 384, 192))
@@ -749,6 +889,7 @@ def main():
             }
         except Exception as e:
             out["mgrit2_coarse_t127"] = {"error": str(e)}
+        progress("mgrit2_coarse_t127")
         try:
             rc3 = measure(pint.FP64, args.steps, args.warmup, levels=3,
                           coarse_grid=(127, 384, 192))
@@ -760,6 +901,7 @@ def main():
             }
         except Exception as e:
             out["mgrit3_coarse_t127"] = {"error": str(e)}
+        progress("mgrit3_coarse_t127")
         # two levels, coarse level at the fine truncation with FP32 transforms
         # (the fine propagator stays FP64, so the iteration converges to the
         # same FP64 fine solution)
@@ -776,18 +918,40 @@ def main():
             }
         except Exception as e:
             out["mgrit2_coarse_fp32"] = {"error": str(e)}
+        progress("mgrit2_coarse_fp32")
     if prec == pint.FP64 and not args.no_diagnostics:
         try:
             out["diagnostics"] = measure_diagnostics(res["slices"])
         except Exception as e:                      # reported, not fatal
             out["diagnostics"] = {"error": str(e)}
+        progress("diagnostics")
     if prec == pint.FP64 and not args.no_sl:
         try:
             out["sl_settls_t127"] = measure_sl()
         except Exception as e:                      # reported, not fatal
             out["sl_settls_t127"] = {"error": str(e)}
+        progress("sl_settls_t127")
+    if prec == pint.FP64 and not args.no_time_to_tol:
+        try:
+            out["time_to_tol_t127"] = time_to_tol()
+        except Exception as e:                      # reported, not fatal
+            out["time_to_tol_t127"] = {"error": str(e)}
+        progress("time_to_tol_t127")
+    if prec == pint.FP64 and not args.no_serve:
+        try:
+            out["serving_c5"] = serve_c5()
+        except Exception as e:
+            out["serving_c5"] = {"error": str(e)}
+        progress("serving_c5")
+    if prec == pint.FP64 and not args.no_c3_full:
+        try:
+            out["c3_full_horizon"] = c3_full_horizon()
+        except Exception as e:
+            out["c3_full_horizon"] = {"error": str(e)}
+        progress("c3_full_horizon")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        progress("cpu_baseline")
     print(json.dumps(out), flush=True)
     return 0
 

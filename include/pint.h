@@ -121,7 +121,10 @@ typedef struct {
                                   creation (driver scratch and factor sets)  */
   int gemm_shape[2][2];        /* Legendre GEMM launch shape in use, [synthesis,
                                   analysis][launches of few states, of many]:
-                                  0 = k-slabs of 16, 1 = of 32               */
+                                  few states: 0 = k-slabs of 16, 1 = of 32;
+                                  many, synthesis: 0 = 64-column tiles,
+                                  1 = 128; many, analysis: 0 = 64 columns,
+                                  1 = 64 with k-slabs of 32, 2 = 128 columns */
   double gemm_us[2][2];        /* the autotuner's time per launch of that shape
                                   (0 = not tuned)                            */
 } pint_info;
@@ -316,7 +319,9 @@ typedef struct {
                                     correction sweep, or the level-1 cycles
                                     with three levels); it runs beside the
                                     fine propagation, so the iteration takes
-                                    about the larger of the two               */
+                                    about the larger of the two.  For an
+                                    iteration replayed from a graph both hold
+                                    the graph's device time                  */
   long long fine_slice_steps;    /* fine IMEX steps executed (sum over slices)*/
   long long coarse_steps;        /* coarse IMEX steps executed (all coarse
                                     levels, single-state and batched)        */

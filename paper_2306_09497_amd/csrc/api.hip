@@ -1,6 +1,8 @@
 // Public C entry points, the batched IMEX propagator and the PinT drivers.
 #include <chrono>
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include "pint_internal.h"
@@ -419,13 +421,14 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
   // back into s): relaxation and batched fine propagation, the serial
   // correction sweep or level-1 cycles, and the increment sums copied to
   // pinned host memory.  Nothing in it waits or allocates, so it can be
-  // captured into a graph; `capturing` turns the phase events into
-  // external event nodes of the graph.
+  // captured into a graph; while `capturing`, the phase events are left out
+  // (the runtime does not take timed events into a capture), and a replayed
+  // iteration is timed as a whole around its graph launch.
   DevBuf Incr(p, kSlotIncr);
   PINT_TRY(Incr.alloc((size_t)8 * N));
   bool capturing = false;
   auto rec = [&](hipEvent_t ev, hipStream_t st) -> pint_status {
-    PINT_HIP(hipEventRecordWithFlags(ev, st, capturing ? hipEventRecordExternal : 0));
+    if (!capturing) PINT_HIP(hipEventRecord(ev, st));
     return PINT_OK;
   };
   auto iteration = [&](int first, hipStream_t s) -> pint_status {
@@ -528,11 +531,14 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
     // slices before `first` are already exact (Parareal); MGRIT recomputes all
     const int first = (mgrit || q->resume) ? 0 : (k < N ? k : N);
     if (first >= N) break;
+    bool replayed = false;
     if (graph.e) {
+      PINT_HIP(hipEventRecord(p.ph_ev[0], s));
       PINT_HIP(hipGraphLaunch(graph.e, s));
       r->fine_slice_steps += g_fine;
       r->coarse_steps += g_coarse;
       ++r->graph_iters;
+      replayed = true;
     } else if (graphable && k >= 1) {
       // capture (nothing runs while capturing), instantiate, launch; if the
       // runtime refuses any of it the iteration runs as plain launches and
@@ -540,20 +546,32 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
       const long long f0 = r->fine_slice_steps, c0 = r->coarse_steps;
       hipStream_t cs = p.capture_stream;
       hipGraph_t g = nullptr;
-      bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      const bool dbg = getenv("PINT_GRAPH_DEBUG") != nullptr;
+      hipError_t e0 = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      bool ok = e0 == hipSuccess;
+      if (dbg) fprintf(stderr, "[graph] begin capture: %s\n", hipGetErrorString(e0));
       if (ok) {
         capturing = true;
         const pint_status st = iteration(first, cs);
         capturing = false;
-        ok = hipStreamEndCapture(cs, &g) == hipSuccess && st == PINT_OK && g != nullptr;
+        if (dbg && st != PINT_OK) fprintf(stderr, "[graph] iteration: %s\n", last_error());
+        const hipError_t e1 = hipStreamEndCapture(cs, &g);
+        if (dbg) fprintf(stderr, "[graph] end capture: %s\n", hipGetErrorString(e1));
+        ok = e1 == hipSuccess && st == PINT_OK && g != nullptr;
       }
-      if (ok) ok = hipGraphInstantiate(&graph.e, g, nullptr, nullptr, 0) == hipSuccess;
+      if (ok) {
+        const hipError_t e2 = hipGraphInstantiate(&graph.e, g, nullptr, nullptr, 0);
+        if (dbg) fprintf(stderr, "[graph] instantiate: %s\n", hipGetErrorString(e2));
+        ok = e2 == hipSuccess;
+      }
       if (g) (void)hipGraphDestroy(g);
       if (ok) {
         g_fine = r->fine_slice_steps - f0;
         g_coarse = r->coarse_steps - c0;
+        PINT_HIP(hipEventRecord(p.ph_ev[0], s));
         PINT_HIP(hipGraphLaunch(graph.e, s));
         ++r->graph_iters;
+        replayed = true;
       } else {
         (void)hipGetLastError();
         graph.e = nullptr;
@@ -564,6 +582,10 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
       }
     } else {
       PINT_TRY(iteration(first, s));
+    }
+    if (replayed) {   // the graph's two phases as one
+      PINT_HIP(hipEventRecord(p.ph_ev[1], s));
+      PINT_HIP(hipEventRecord(p.ph_ev[2], s));
     }
     PINT_HIP(hipStreamSynchronize(s));
     rel_diff_finish(p.h_incr, incr.data(), N);

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   constexpr int LDA = TR + 2, LDB = TC + 2;
   constexpr int NA = TK * TR / 256;                  // A elements per thread per slab
   constexpr int NB = TK * TC / 256;                  // B elements per thread per slab
-  constexpr int WC = TC == 64 ? 2 : 1;               // waves across columns
+  constexpr int WC = TC >= 64 ? 2 : 1;               // waves across columns
   constexpr int WR = 4 / WC;                         // waves across rows
   constexpr int BI = TR / WR / 16, BJ = TC / WC / 16;  // MFMA blocks per wave
   static_assert(BI >= 1 && BJ >= 1 && NA >= 1 && NB >= 1, "tile shape");
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   constexpr int LDA = TR + 2, LDB = TC + 2;
   constexpr int NA = TK * TR / 256;                  // A elements per thread per slab
   constexpr int NB = TK * TC / 256;                  // G pairs per thread per slab
-  constexpr int WC = TC >= 32 ? TC / 32 : 1;         // waves across columns
+  constexpr int WC = TC >= 64 ? 2 : 1;               // waves across columns
   constexpr int WR = 4 / WC;                         // waves across rows
   constexpr int BI = TR / WR / 16, BJ = TC / WC / 16;
   static_assert(BI >= 1 && BJ >= 1 && NA >= 1 && NB >= 1 && (TR / WR) <= TR2, "tile shape");
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const float* __restrict__ T, const int* __restrict__ rowoff, const int* __restrict__ tiles,
     const float* __restrict__ S, float* __restrict__ F, int nlat, int nlat2, int ncol) {
   constexpr int TR = 64;
-  constexpr int WC = TC == 64 ? 2 : 1;               // waves across columns
+  constexpr int WC = TC >= 64 ? 2 : 1;               // waves across columns
   constexpr int WR = 4 / WC;                         // waves across rows
   constexpr int BI = TR / WR / 16, BJ = TC / WC / 16;
   static_assert(BI >= 1 && BJ >= 1 && TR * kBfKG == 256 && TC * kBfKG <= 256, "tile shape");
@@ -604,9 +604,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // Launch shapes.  Every shape consumes k in the same order (steps of 4,
 // increasing, per parity), so all give bitwise the same results and the
 // choice between them is a matter of speed only: narrow column tiles (16)
-// for launches of up to two states (synthesis) or four (analysis), 64
-// otherwise, and a k-slab depth TK of 16 or 32 per launch class, chosen per
-// plan by the autotuner (tune_legendre) or left at the default (TK 16).
+// for launches of up to two states (synthesis) or four (analysis), 64 or 128
+// otherwise, and a k-slab depth TK of 16 or 32, chosen per plan and launch
+// class by the autotuner (tune_legendre) or left at the default (variant 0).
 enum { kClassSmall = 0, kClassLarge = 1 };
 static int gemm_class(int ncol) { return ncol <= 32 ? kClassSmall : kClassLarge; }
 
@@ -622,6 +622,10 @@ static void launch_synth(Plan& p, const E* T, const E* S, E* F, int ncol, hipStr
     else
       hipLaunchKernelGGL((k_legendre_synth<E, kGemmTR, 16, kGemmTK>), grid, dim3(256), 0, s, T,
                          p.rowoff, p.syn_tiles.dev, S, F, p.nlat, p.nlat2, ncol);
+  } else if (v == 1) {
+    dim3 grid(((ncol + 127) / 128) * p.syn_tiles.count);
+    hipLaunchKernelGGL((k_legendre_synth<E, kGemmTR, 128, kGemmTK>), grid, dim3(256), 0, s, T,
+                       p.rowoff, p.syn_tiles.dev, S, F, p.nlat, p.nlat2, ncol);
   } else {
     dim3 grid(((ncol + 63) / 64) * p.syn_tiles.count);
     hipLaunchKernelGGL((k_legendre_synth<E, kGemmTR, 64, kGemmTK>), grid, dim3(256), 0, s, T,
@@ -641,6 +645,10 @@ static void launch_anal(Plan& p, const E* Tt, const E* G, E* Q, int ncol, hipStr
     else
       hipLaunchKernelGGL((k_legendre_anal<E, 16, kGemmTK>), grid, dim3(256), 0, s, Tt, p.rowoff,
                          p.ana_tiles.dev, G, Q, p.nlat, p.nlat2, ncol, p.nrows);
+  } else if (v == 2) {
+    dim3 grid(((ncol + 127) / 128) * p.ana_tiles.count);
+    hipLaunchKernelGGL((k_legendre_anal<E, 128, kGemmTK>), grid, dim3(256), 0, s, Tt, p.rowoff,
+                       p.ana_tiles.dev, G, Q, p.nlat, p.nlat2, ncol, p.nrows);
   } else {
     dim3 grid(((ncol + 63) / 64) * p.ana_tiles.count);
     if (v == 1)
@@ -652,9 +660,13 @@ static void launch_anal(Plan& p, const E* Tt, const E* G, E* Q, int ncol, hipStr
   }
 }
 
-// Variants per (transform, launch class); synthesis with 64-column tiles has
-// only TK 16 (TK 32 would need more than 64 KiB of LDS).
-static int gemm_variants(int kind, int cls) { return (kind == 0 && cls == kClassLarge) ? 1 : 2; }
+// Variants per (transform, launch class): few states -- k-slabs of 16 or 32;
+// many states -- synthesis with 64- or 128-column tiles (k-slabs of 16: 32
+// would need more than 64 KiB of LDS), analysis with 64 columns and k-slabs
+// of 16 or 32, or 128 columns (the table read half as often).
+static int gemm_variants(int kind, int cls) {
+  return cls == kClassSmall ? 2 : (kind == 0 ? 2 : 3);
+}
 
 static void launch_synth_bf3(Plan& p, int ncol, hipStream_t s) {
   const float* T = p.ptab32;

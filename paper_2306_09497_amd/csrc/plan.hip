@@ -390,8 +390,9 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
   }
   if (const char* env = getenv("PINT_GRAPHS")) p.use_graphs = atoi(env) != 0;
   if (const char* env = getenv("PINT_GEMM_VARIANT")) {   // fixed launch shapes (tests)
-    const int v = atoi(env) ? 1 : 0;
-    p.gemm_variant[0][0] = p.gemm_variant[1][0] = p.gemm_variant[1][1] = v;
+    const int v = atoi(env) < 0 ? 0 : atoi(env);
+    p.gemm_variant[0][0] = p.gemm_variant[1][0] = p.gemm_variant[0][1] = v > 1 ? 1 : v;
+    p.gemm_variant[1][1] = v > 2 ? 2 : v;
   }
   if (const char* env = getenv("PINT_SWEEP_CHUNKS")) {
     const int v = atoi(env);

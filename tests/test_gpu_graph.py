@@ -80,12 +80,14 @@ def test_graph_replay_of_a_resumed_parareal(monkeypatch):
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("B", [1, 2, 9])
-def test_every_gemm_shape_gives_the_same_step(monkeypatch, B):
-    """Launch shapes with k-slabs of 16 and of 32 (both launch classes)."""
+@pytest.mark.parametrize("B", [1, 2, 9, 16])
+@pytest.mark.parametrize("variant", [1, 2])
+def test_every_gemm_shape_gives_the_same_step(monkeypatch, B, variant):
+    """Launch shapes with k-slabs of 16 and of 32 and column tiles of 64 and
+    128 (both launch classes) give bitwise the same steps."""
     pa = plan_with(monkeypatch, {"PINT_GEMM_VARIANT": "0"}, 63, 192, 96, 16)
-    pb = plan_with(monkeypatch, {"PINT_GEMM_VARIANT": "1"}, 63, 192, 96, 16)
-    assert pb.info().gemm_shape[0][0] == 1 and pb.info().gemm_shape[1][1] == 1
+    pb = plan_with(monkeypatch, {"PINT_GEMM_VARIANT": str(variant)}, 63, 192, 96, 16)
+    assert pb.info().gemm_shape[0][0] == 1 and pb.info().gemm_shape[1][1] == variant
     U = np.stack([workloads.solid_body(63, noise=1e-3, seed=s) for s in range(B)])
     u = to_dev(U, torch)
     st = pint.stepper(240.0, 4, 1e15, pint.T_ALL)
