@@ -358,6 +358,9 @@ def measure(precision, steps, warmup, levels=2, coarse_grid=None, coarse_precisi
         v = info.gemm_shape[k][c]
         shapes[label] = {"shape": names[(k, c)][v] if v < len(names[(k, c)]) else v,
                          "tuned_us_per_launch": info.gemm_us[k][c]}
+    for c, label in ((0, "ring_1_state"), (1, "ring_64_states")):
+        shapes[label] = {"workgroup_threads": info.ring_threads[c],
+                         "tuned_us_per_launch": info.ring_us[c]}
     plan.close()
     if cplan is not None:
         cplan.close()

@@ -127,6 +127,10 @@ typedef struct {
                                   1 = 64 with k-slabs of 32, 2 = 128 columns */
   double gemm_us[2][2];        /* the autotuner's time per launch of that shape
                                   (0 = not tuned)                            */
+  int ring_threads[2];         /* ring kernel workgroup size for launches of
+                                  one or two states, of more                 */
+  double ring_us[2];           /* the autotuner's time per launch (0 = not
+                                  tuned)                                     */
 } pint_info;
 
 /* Create a plan: Gauss nodes and weights (Newton iteration), normalised
@@ -352,7 +356,8 @@ pint_status pint_solve(pint_plan* plan, const pint_pint_params* p, const double*
  * plan's Legendre GEMM launch shapes for the workload: it times every shape
  * of each transform at one state per launch (the serial sweep's launches)
  * and at min(n_intervals, max_batch) states (max_batch without q), keeps the
- * fastest (on the coarse plan too), and synchronises `stream`.  The shapes
+ * fastest (on the coarse plan too) -- likewise the ring kernel's workgroup
+ * size -- and synchronises `stream`.  The shapes
  * give bitwise the same results, so tuning never changes an answer;
  * pint_info.gemm_us reports the tuned times.  Afterwards those
  * calls allocate and free no device memory and copy nothing to or from the

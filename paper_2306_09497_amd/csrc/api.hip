@@ -686,6 +686,10 @@ pint_status pint_plan_info(const pint_plan* plan, pint_info* info) {
       info->gemm_shape[k][c] = p.gemm_variant[k][c];
       info->gemm_us[k][c] = 1e3 * p.gemm_tuned_ms[k][c];
     }
+  for (int c = 0; c < 2; ++c) {
+    info->ring_threads[c] = (c == 0) == (p.ring_variant[c] == 0) ? 256 : 128;
+    info->ring_us[c] = 1e3 * p.ring_tuned_ms[c];
+  }
   return PINT_OK;
 }
 
@@ -726,10 +730,12 @@ pint_status pint_plan_reserve(pint_plan* plan, const pint_pint_params* q,
                     : plan->p.max_batch;
   const int states[2] = {1, big};
   PINT_TRY(tune_legendre(plan->p, states, s));
+  PINT_TRY(tune_ring(plan->p, states, s));
   if (pc && pc != &plan->p) {
     const int cbig = big < pc->max_batch ? big : pc->max_batch;
     const int cstates[2] = {1, cbig};
     PINT_TRY(tune_legendre(*pc, cstates, s));
+    PINT_TRY(tune_ring(*pc, cstates, s));
   }
   return PINT_OK;
 }

@@ -130,6 +130,10 @@ struct Plan {
   // launch class), set by the autotuner; and the tuned time per launch
   int gemm_variant[2][2] = {{0, 0}, {0, 0}};
   float gemm_tuned_ms[2][2] = {{0.0f, 0.0f}, {0.0f, 0.0f}};
+  // ring workgroup size per launch class (few / many states): variant 0 is
+  // 256 threads for few states and 128 for many, variant 1 the other one
+  int ring_variant[2] = {0, 0};
+  float ring_tuned_ms[2] = {0.0f, 0.0f};
   // device scratch of the PinT drivers, kept between calls and grown on
   // demand (slot -> buffer, doubles)
   std::vector<std::pair<double*, size_t>> pool;
@@ -231,9 +235,11 @@ pint_status spec_truncate(const double* in, int Mf, double* out, int Mc, int B, 
 pint_status spec_pad(const double* in, int Mc, double* out, int Mf, int B, hipStream_t s);
 pint_status legendre_synth(Plan& p, int B, int nf, int prec, hipStream_t s);
 pint_status legendre_anal(Plan& p, int B, int nf, int prec, hipStream_t s);
-// time the launch shapes of both transforms at states[0] (small launch
-// class) and states[1] (large) states per launch, keep the fastest
+// time the launch shapes of both Legendre transforms and of the ring kernel
+// at states[0] (small launch class) and states[1] (large) states per launch,
+// keep the fastest
 pint_status tune_legendre(Plan& p, const int (&states)[2], hipStream_t s);
+pint_status tune_ring(Plan& p, const int (&states)[2], hipStream_t s);
 pint_status ring_tendency(Plan& p, int B, hipStream_t s);
 bool ring_supported(int nlon);
 size_t ring_lds_bytes(int nlon, int prec);

@@ -393,6 +393,7 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
     const int v = atoi(env) < 0 ? 0 : atoi(env);
     p.gemm_variant[0][0] = p.gemm_variant[1][0] = p.gemm_variant[0][1] = v > 1 ? 1 : v;
     p.gemm_variant[1][1] = v > 2 ? 2 : v;
+    p.ring_variant[0] = p.ring_variant[1] = v > 1 ? 1 : v;
   }
   if (const char* env = getenv("PINT_SWEEP_CHUNKS")) {
     const int v = atoi(env);

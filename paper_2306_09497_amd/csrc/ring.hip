@@ -934,7 +934,10 @@ pint_status ring_prepare(int nlon) {
 pint_status ring_tendency(Plan& p, int B, hipStream_t s) {
   ProfScope ps(p, PK_RING, B, s);
   const bool f32 = p.prec != PINT_FP64;
-  const bool small = B <= 2;
+  // workgroup size: 256 threads (one wave per signal) by default for one or
+  // two states, 128 for more; the plan's tuned variant may swap them (the
+  // arithmetic of a ring is the same in both)
+  const bool small = (B <= 2) != (p.ring_variant[B <= 2 ? 0 : 1] == 1);
   switch (p.nlon) {
 #define PINT_LAUNCH(n, T, NT, f, g, tw)                                                      \
   hipLaunchKernelGGL((k_ring_tendency<n, T, NT>), dim3(p.nlat * B), dim3(NT),                \
@@ -1202,6 +1205,44 @@ pint_status ring_sl_anal(Plan& p, const double* grid, int B, hipStream_t s) {
   }
   PINT_HIP(hipGetLastError());
   return PINT_OK;
+}
+
+// Autotuner of the ring workgroup size: for each launch class, time both
+// sizes at the class's batch on the plan's workspace and keep the faster
+// (bitwise the same results).  Synchronises `s`.
+pint_status tune_ring(Plan& p, const int (&states)[2], hipStream_t s) {
+  hipEvent_t e0, e1;
+  PINT_HIP(hipEventCreate(&e0));
+  PINT_HIP(hipEventCreate(&e1));
+  pint_status st = PINT_OK;
+  for (int cls = 0; cls < 2 && st == PINT_OK; ++cls) {
+    const int B = states[cls];
+    if (B < 1 || B > p.max_batch || ((B <= 2) != (cls == 0))) continue;
+    int best = 0;
+    float best_ms = 0.0f;
+    for (int v = 0; v < 2 && st == PINT_OK; ++v) {
+      p.ring_variant[cls] = v;
+      float ms = 0.0f;
+      for (int rep = 0; rep < 4 && st == PINT_OK; ++rep) {   // first one warms up
+        if (rep == 1 && hipEventRecord(e0, s) != hipSuccess) st = PINT_E_HIP;
+        if (st == PINT_OK) st = ring_tendency(p, B, s);
+      }
+      if (st == PINT_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                            hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = PINT_E_HIP;
+      if (st == PINT_OK && (v == 0 || ms < best_ms)) {
+        best = v;
+        best_ms = ms;
+      }
+    }
+    p.ring_variant[cls] = best;
+    p.ring_tuned_ms[cls] = best_ms / 3.0f;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == PINT_E_HIP) set_error("timing the ring kernel variants failed");
+  return st;
 }
 
 }  // namespace pint

@@ -58,7 +58,8 @@ class Info(ctypes.Structure):
                 ("ncoef", ctypes.c_int), ("max_batch", ctypes.c_int),
                 ("state_doubles", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
                 ("allocations", ctypes.c_longlong), ("gemm_shape", (ctypes.c_int * 2) * 2),
-                ("gemm_us", (ctypes.c_double * 2) * 2)]
+                ("gemm_us", (ctypes.c_double * 2) * 2), ("ring_threads", ctypes.c_int * 2),
+                ("ring_us", ctypes.c_double * 2)]
 
 
 class PintParams(ctypes.Structure):
@@ -183,10 +184,10 @@ def _ptr(t, numel=None):
     if t is None:
         return None
     import torch
-    if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
-        raise ValueError("device arrays must be contiguous float64 CUDA/HIP tensors")
     if numel is not None and t.numel() < numel:
         raise ValueError(f"device array holds {t.numel()} doubles, the call needs {numel}")
+    if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError("device arrays must be contiguous float64 CUDA/HIP tensors")
     return ctypes.c_void_p(t.data_ptr())
 
 

@@ -137,3 +137,18 @@ def test_workspace_query_rejects_bad_arguments():
     assert lib.pint_plan_workspace_bytes(None, None, None, ctypes.byref(n)) == -1
     assert b"null plan" in lib.pint_last_error()
     assert lib.pint_plan_reserve(None, None, None, None) == -1
+
+
+def test_binding_refuses_undersized_and_host_arrays():
+    """The binding checks an array's size (and that it is a contiguous
+    float64 device tensor) before the library sees its pointer, so an
+    undersized tensor raises instead of being read or written out of bounds."""
+    import torch
+    from paper_2306_09497_amd import pint
+    with pytest.raises(ValueError, match="holds 10 doubles, the call needs 12"):
+        pint._ptr(torch.zeros(10, dtype=torch.float64), 12)
+    with pytest.raises(ValueError, match="contiguous float64"):
+        pint._ptr(torch.zeros(12, dtype=torch.float64), 12)       # host memory
+    with pytest.raises(ValueError, match="contiguous float64"):
+        pint._ptr(torch.zeros(12, dtype=torch.float32), 12)
+    assert pint._ptr(None, 12) is None

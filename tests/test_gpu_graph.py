@@ -84,10 +84,12 @@ def test_graph_replay_of_a_resumed_parareal(monkeypatch):
 @pytest.mark.parametrize("variant", [1, 2])
 def test_every_gemm_shape_gives_the_same_step(monkeypatch, B, variant):
     """Launch shapes with k-slabs of 16 and of 32 and column tiles of 64 and
-    128 (both launch classes) give bitwise the same steps."""
+    128, and ring workgroups of 128 and 256 threads (both launch classes),
+    give bitwise the same steps."""
     pa = plan_with(monkeypatch, {"PINT_GEMM_VARIANT": "0"}, 63, 192, 96, 16)
     pb = plan_with(monkeypatch, {"PINT_GEMM_VARIANT": str(variant)}, 63, 192, 96, 16)
     assert pb.info().gemm_shape[0][0] == 1 and pb.info().gemm_shape[1][1] == variant
+    assert list(pb.info().ring_threads) == [128, 256]
     U = np.stack([workloads.solid_body(63, noise=1e-3, seed=s) for s in range(B)])
     u = to_dev(U, torch)
     st = pint.stepper(240.0, 4, 1e15, pint.T_ALL)
