@@ -90,11 +90,12 @@ MEASURED_TRAFFIC = {
 }
 
 
-def measured_traffic(kind, prec=0):
-    """Counter-measured HBM bytes per launch of `kind` at precision `prec`, or
-    None if absent or if its sources changed since the counters were taken."""
+def measured_traffic(kind, prec=0, states=64):
+    """Counter-measured HBM bytes per launch of `kind` at precision `prec` over
+    `states` states, or None if absent (the counters were taken on 64-state
+    launches) or if its sources changed since the counters were taken."""
     import hashlib
-    if (kind, prec) not in MEASURED_TRAFFIC:
+    if states != 64 or (kind, prec) not in MEASURED_TRAFFIC:
         return None
     byts, srcs = MEASURED_TRAFFIC[(kind, prec)]
     csrc = os.path.join(ROOT, "paper_2306_09497_amd", "csrc")
@@ -333,9 +334,9 @@ def measure(precision, steps, warmup, levels=2, coarse_grid=None, coarse_precisi
         plan.solve(it, u0, slices)
     torch.cuda.synchronize()
 
-    # timed region: exactly `steps` MGRIT iterations; the batched launches of
-    # the three transform kernels are bracketed by HIP events
-    plan.profile(["legendre_synth", "ring_tendency", "legendre_anal"], min_batch=GROUP)
+    # timed region: exactly `steps` MGRIT iterations; the batched launches (two
+    # states or more) of the three transform kernels are bracketed by HIP events
+    plan.profile(["legendre_synth", "ring_tendency", "legendre_anal"], min_batch=2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     fine_steps = 0
@@ -790,14 +791,16 @@ def main():
                  pint.LEG_BF16X3: PEAK_BF16 / 3.0}[prec]
 
     # dominant kernel of the timed region and its roofline
+    # (the largest launches of the iteration: states per batched launch)
+    bmax = max(b for (_, b) in prof)
     per_kind = {}
     for (kind, b), (n, ms) in prof.items():
-        if b == GROUP:
+        if b == bmax:
             per_kind[kind] = (n, ms)
     dom = max(per_kind, key=lambda k: per_kind[k][1])
     n_launch, tot_ms = per_kind[dom]
     avg_s = tot_ms / n_launch * 1e-3
-    flops, byts = algorithmic_work(dom, GROUP, prec)
+    flops, byts = algorithmic_work(dom, bmax, prec)
     if flops > 0:
         roof = {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": peak_mfma / 1e12,
                 "unit": "TFLOP/s"}
@@ -805,13 +808,14 @@ def main():
         roof = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": PEAK_HBM / 1e9,
                 "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(dom, prec)
+    roof["traffic"] = measured_traffic(dom, prec, bmax)
     roof["kernel"] = dom
+    roof["states_per_launch"] = bmax
     roof["avg_launch_ms"] = tot_ms / n_launch
 
     kernels = {}
     for kind, (n, ms) in sorted(per_kind.items()):
-        f, b = algorithmic_work(kind, GROUP, prec)
+        f, b = algorithmic_work(kind, bmax, prec)
         avg = ms / n * 1e-3
         kernels[kind] = {"launches": n, "avg_ms": ms / n,
                          "share_of_step": ms * 1e-3 / elapsed,

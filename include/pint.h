@@ -302,7 +302,10 @@ typedef struct {
                              runs the coarse levels directly on it, e.g. in
                              a reduced transform precision while the fine
                              propagator stays FP64 (the converged iterate
-                             is still the FP64 fine solution).
+                             is still the FP64 fine solution); one of the
+                             plan's own truncation and precision adds
+                             nothing and is ignored (the coarse levels run
+                             on the plan itself).
                              Not thread-safe with other calls on either
                              plan.                                         */
 } pint_pint_params;

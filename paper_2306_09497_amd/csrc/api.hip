@@ -103,6 +103,15 @@ static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// The plan the coarse level runs on: the coarse plan, or none (the fine
+// plan) when it has the fine plan's truncation and transform precision --
+// such a plan computes bitwise what the fine plan does.
+static Plan* coarse_plan_of(const Plan& p, const pint_pint_params* q) {
+  if (!q || !q->coarse_plan) return nullptr;
+  Plan* c = &q->coarse_plan->p;
+  return (c->M == p.M && c->prec == p.prec) ? nullptr : c;
+}
+
 pint_status check_params(const Plan& p, const pint_pint_params* q) {
   if (!q) {
     set_error("null params");
@@ -180,8 +189,8 @@ struct CoarseProp {
   explicit CoarseProp(Plan& fine)
       : p(fine), cin(fine, kSlotCin), cin_side(fine, kSlotCinSide) {}
   pint_status init(const pint_pint_params* q, int cap_states) {
-    if (!q->coarse_plan) return PINT_OK;
-    pc = &q->coarse_plan->p;
+    pc = coarse_plan_of(p, q);
+    if (!pc) return PINT_OK;
     if (same()) return PINT_OK;
     cap = cap_states;
     const size_t sdc = (size_t)3 * pc->ncoef * 2;
@@ -353,7 +362,7 @@ pint_status solve_footprint(const Plan& p, const pint_pint_params* q, Footprint&
     fp.need(kSlotG2, sd * N2);
     fp.need(kSlotGz, sd);
   }
-  const Plan* pc = q->coarse_plan ? &q->coarse_plan->p : nullptr;
+  const Plan* pc = coarse_plan_of(p, q);
   if (pc && pc->M != p.M) {
     const size_t sdc = (size_t)3 * pc->ncoef * 2;
     fp.need(kSlotCin, sdc * N);
@@ -379,7 +388,7 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
   {
     Footprint fp;
     PINT_TRY(solve_footprint(p, q, fp));
-    PINT_TRY(reserve(p, q->coarse_plan ? &q->coarse_plan->p : nullptr, fp, s));
+    PINT_TRY(reserve(p, coarse_plan_of(p, q), fp, s));
   }
   DevBuf Gold(p, kSlotGold), Fv(p, kSlotFv), Uprev(p, kSlotUprev), Gtmp(p, kSlotGtmp);
   PINT_TRY(Gold.alloc(sd * N));
@@ -712,7 +721,7 @@ pint_status pint_plan_workspace_bytes(const pint_plan* plan, const pint_pint_par
   }
   Footprint fp;
   PINT_TRY(workload_footprint(plan->p, q, sl, fp));
-  *bytes = footprint_bytes(plan->p, q && q->coarse_plan ? &q->coarse_plan->p : nullptr, fp);
+  *bytes = footprint_bytes(plan->p, coarse_plan_of(plan->p, q), fp);
   return PINT_OK;
 }
 
@@ -721,7 +730,7 @@ pint_status pint_plan_reserve(pint_plan* plan, const pint_pint_params* q,
   API_GUARD(plan);
   Footprint fp;
   PINT_TRY(workload_footprint(plan->p, q, sl, fp));
-  Plan* pc = q && q->coarse_plan ? &q->coarse_plan->p : nullptr;
+  Plan* pc = coarse_plan_of(plan->p, q);
   hipStream_t s = (hipStream_t)stream;
   PINT_TRY(reserve(plan->p, pc, fp, s));
   // launch shapes of the Legendre GEMMs for this workload: single states
