@@ -94,6 +94,10 @@ struct Plan {
   double4* cnco = nullptr;     // [ncoef] linear-operator coefficients (A/W, B/W, C/W, n(n+1)/a^2)
   std::vector<int> h_rowoff;   // host copy
   GemmTiles syn_tiles, ana_tiles;
+  // spectral kernel tasks: chains (zonal wavenumbers) of one state packed
+  // onto the lanes of one wave, kSpecTaskInts ints per task
+  int* spec_tasks = nullptr;
+  int n_spec_tasks = 0;
   // workspace (sized for max_batch)
   // GEMM and ring workspace, sized for FP64; FP32 in PINT_LEG_FP32 mode
   double* S = nullptr;         // [nrows][12 B]   synthesis GEMM input
@@ -239,6 +243,9 @@ pint_status legendre_anal(Plan& p, int B, int nf, int prec, hipStream_t s);
 // at states[0] (small launch class) and states[1] (large) states per launch,
 // keep the fastest
 pint_status tune_legendre(Plan& p, const int (&states)[2], hipStream_t s);
+// Packs the chains m = 0..M of one state onto waves for the spectral
+// kernels (a function of M only) and uploads the task table.
+pint_status spec_tasks_build(Plan& p, size_t* total);
 pint_status tune_ring(Plan& p, const int (&states)[2], hipStream_t s);
 pint_status ring_tendency(Plan& p, int B, hipStream_t s);
 bool ring_supported(int nlon);

@@ -172,7 +172,8 @@ static void free_plan(Plan& p) {
   void* ptrs[] = {p.mu, p.w, p.c2, p.ptab, p.ptabT, p.ptab32, p.ptabT32, p.twid32,
                   p.rowoff, p.rowinfo, p.coefmn, p.twid, p.cnco, p.syn_tiles.dev,
                   p.ana_tiles.dev, p.S, p.F, p.G, p.Q, p.Ua, p.N1, p.red, p.diag,
-                  p.side.S, p.side.F, p.side.G, p.side.Q, p.side.Ua, p.side.N1, p.sl_lat};
+                  p.side.S, p.side.F, p.side.G, p.side.Q, p.side.Ua, p.side.N1, p.sl_lat,
+                  p.spec_tasks};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto& b : p.pool)
@@ -336,6 +337,7 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
   PLAN_TRY(dalloc(&p.cnco, p.ncoef, &tot));
   PLAN_TRY(build_tiles(p.h_rowoff, M, p.nlat2, true, kGemmTR, &p.syn_tiles, &tot));
   PLAN_TRY(build_tiles(p.h_rowoff, M, p.nlat2, false, kGemmTRAnal, &p.ana_tiles, &tot));
+  PLAN_TRY(spec_tasks_build(p, &tot));
   const size_t B = p.max_batch;
   PLAN_TRY(dalloc(&p.S, (size_t)p.nrows * 12 * B, &tot));
   PLAN_TRY(dalloc(&p.F, (M + 1) * fourier_pitch<double>(nlat, 12 * B), &tot));

@@ -21,13 +21,19 @@ __device__ inline double2 cimul(double2 x, double s) {   // i * s * x
 
 // ---------------------------------------------------------------------------
 // Spectral kernels.  States are in the public layout [B][3][ncoef] complex.
-// Every kernel runs one 64-lane wave per (zonal wavenumber m, state b); lane l
-// owns the SEG consecutive chain positions i = l*SEG .. l*SEG+SEG-1 of m
-// (i = n - m, K = M - m + 1 positions; positions >= K hold zeros).  The
-// neighbours n-1 and n+1 that the recurrence shifts and the Crank-Nicolson
-// right-hand side need come from the adjacent lanes by shuffles.  The order
-// of every floating-point operation depends on M only, never on B, so results
-// are bitwise batch-invariant.
+// The chain of zonal wavenumber m (positions i = n - m, K = M - m + 1 of
+// them) occupies a segment of ceil(K / SEG) consecutive lanes of a 64-lane
+// wave; lane slo + l of the segment owns the SEG positions i = l*SEG ..
+// l*SEG+SEG-1 (positions >= K hold zeros).  A wave carries one state and
+// several chains on disjoint segments (a task: one long chain and the short
+// ones that fill the remaining lanes), so that the lanes of high wavenumbers
+// are not left idle.  The neighbours n-1 and n+1 that the recurrence shifts
+// and the Crank-Nicolson right-hand side need come from the adjacent lanes by
+// shuffles, and the Crank-Nicolson scans run over the segment; reads across a
+// segment's ends are masked, which gives exactly the values a wave holding
+// the chain alone has there (zeros, and identity maps, whose composition is
+// exact).  The order of every floating-point operation depends on M only,
+// never on B or on the packing, so results are bitwise batch-invariant.
 // ---------------------------------------------------------------------------
 __device__ inline double2 cfma(double2 a, double2 x, double2 b) {   // a x + b
   return cadd(cmul(a, x), b);
@@ -50,43 +56,57 @@ __device__ inline double visc_factor(int n, double a, double vdt, double nu, int
 // chain position i of chain c holds xi if (i even) == (c == 0), else delta
 __device__ inline bool xi_on_chain0(int i) { return (i & 1) == 0; }
 
-// Inclusive scan of affine maps f_l(v) = A_l v + B_l over the 64 lanes:
-// kUp: lane l gets f_l o f_{l-1} o ... o f_0; otherwise f_l o ... o f_63.
+// Inclusive scan of affine maps f_l(v) = A_l v + B_l over the lanes
+// [slo, shi) of a segment: kUp: lane l gets f_l o f_{l-1} o ... o f_slo;
+// otherwise f_l o ... o f_{shi-1}.
 template <bool kUp>
-__device__ inline void affine_scan(double2& A, double2& Bv, int lane) {
+__device__ inline void affine_scan(double2& A, double2& Bv, int lane, int slo, int shi) {
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
     const double2 Ap = kUp ? shfl_up2(A, d) : shfl_down2(A, d);
     const double2 Bp = kUp ? shfl_up2(Bv, d) : shfl_down2(Bv, d);
-    if (kUp ? lane >= d : lane + d < 64) {
+    if (kUp ? lane - d >= slo : lane + d < shi) {
       Bv = cfma(A, Bp, Bv);
       A = cmul(A, Ap);
     }
   }
 }
 
-// Where one wave sits: wavenumber m, state b, chain length K, first packed
-// index i0 of m, the lane and its first position p0.
+// Where one lane sits: its chain's wavenumber m, the wave's state b, chain
+// length K, first packed index i0 of m, the lane, its first position p0 and
+// the chain's lane segment [slo, shi).
 struct WaveAt {
-  int m, b, K, i0, lane, p0;
+  int m, b, K, i0, lane, p0, slo, shi;
 };
 
 // A workgroup holds kSpecWaves waves: the states b0 .. b0+kSpecWaves-1 of one
-// m, whose rows of S and Q are adjacent in memory.  Logical block m * nbg + bg,
-// XCD-remapped.  A wave past the last state has nothing to do (w.b >= B).
+// task, whose rows of S and Q are adjacent in memory.  Logical block
+// task * nbg + bg, XCD-remapped.  A wave past the last state has nothing to do
+// (w.b >= B).  Task record: chain count, kSpecTaskChains wavenumbers, their
+// first lanes.
 constexpr int kSpecWaves = 4;
+constexpr int kSpecTaskChains = 8;
+constexpr int kSpecTaskInts = 1 + 2 * kSpecTaskChains;
 
 template <int SEG>
-__device__ inline WaveAt wave_at(int M, int B) {
+__device__ inline WaveAt wave_at(int M, int B, const int* __restrict__ tasks) {
   WaveAt w;
   const int nbg = (B + kSpecWaves - 1) / kSpecWaves;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  w.m = lb / nbg;
-  w.b = (lb - w.m * nbg) * kSpecWaves + (int)(threadIdx.x >> 6);
+  const int t = lb / nbg;
+  w.b = (lb - t * nbg) * kSpecWaves + (int)(threadIdx.x >> 6);
+  w.lane = threadIdx.x & 63;
+  const int* tk = tasks + (size_t)t * kSpecTaskInts;
+  const int* lo = tk + 1 + kSpecTaskChains;
+  const int n = tk[0];
+  int c = 0;
+  for (int q = 1; q < n; ++q) c = w.lane >= lo[q] ? q : c;
+  w.m = tk[1 + c];
+  w.slo = lo[c];
+  w.shi = c + 1 < n ? lo[c + 1] : 64;
   w.K = M - w.m + 1;
   w.i0 = coef_idx(M, w.m, w.m);
-  w.lane = threadIdx.x & 63;
-  w.p0 = w.lane * SEG;
+  w.p0 = (w.lane - w.slo) * SEG;
   return w;
 }
 
@@ -115,16 +135,17 @@ __device__ inline void store_state(double* __restrict__ u, const WaveAt& w, int 
   }
 }
 
-// Values of the positions just before and after the lane's segment.
+// Values of the positions just before and after the lane's positions (zero
+// beyond the ends of its chain's segment).
 template <int SEG>
-__device__ inline void edge_neighbours(const double2 (&V)[SEG][3], int lane, double2 (&prev)[3],
-                                       double2 (&next)[3]) {
+__device__ inline void edge_neighbours(const double2 (&V)[SEG][3], const WaveAt& w,
+                                       double2 (&prev)[3], double2 (&next)[3]) {
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
     prev[f] = shfl_up2(V[SEG - 1][f], 1);
     next[f] = shfl_down2(V[0][f], 1);
-    if (lane == 0) prev[f] = make_double2(0.0, 0.0);
-    if (lane == 63) next[f] = make_double2(0.0, 0.0);
+    if (w.lane == w.slo) prev[f] = make_double2(0.0, 0.0);
+    if (w.lane == w.shi - 1) next[f] = make_double2(0.0, 0.0);
   }
 }
 
@@ -153,7 +174,7 @@ __device__ inline void cn_lane(double2 (&V)[SEG][3], const WaveAt& w, int ncoef,
                                const CnArgs& c) {
   const double2 zero = make_double2(0.0, 0.0), one = make_double2(1.0, 0.0);
   double2 prev[3], next[3];
-  edge_neighbours<SEG>(V, w.lane, prev, next);
+  edge_neighbours<SEG>(V, w, prev, next);
   double2 rphi[SEG], rv[2][SEG];
 #pragma unroll
   for (int k = 0; k < SEG; ++k) {
@@ -203,9 +224,9 @@ __device__ inline void cn_lane(double2 (&V)[SEG][3], const WaveAt& w, int ncoef,
       Bv = cfma(al[k], Bv, be[k]);
       A = cmul(al[k], A);
     }
-    affine_scan<true>(A, Bv, w.lane);
+    affine_scan<true>(A, Bv, w.lane, w.slo, w.shi);
     double2 v = shfl_up2(Bv, 1);
-    if (w.lane == 0) v = zero;
+    if (w.lane == w.slo) v = zero;
 #pragma unroll
     for (int k = 0; k < SEG; ++k) {
       v = cfma(al[k], v, be[k]);
@@ -218,9 +239,9 @@ __device__ inline void cn_lane(double2 (&V)[SEG][3], const WaveAt& w, int ncoef,
       Bv = cfma(ga[k], Bv, rv[ch][k]);
       A = cmul(ga[k], A);
     }
-    affine_scan<false>(A, Bv, w.lane);
+    affine_scan<false>(A, Bv, w.lane, w.slo, w.shi);
     v = shfl_down2(Bv, 1);
-    if (w.lane == 63) v = zero;
+    if (w.lane == w.shi - 1) v = zero;
 #pragma unroll
     for (int k = SEG - 1; k >= 0; --k) {
       v = cfma(ga[k], v, rv[ch][k]);
@@ -297,7 +318,7 @@ __device__ inline void prep_lane(const double2 (&V)[SEG][3], const WaveAt& w, in
                                  SE* __restrict__ S, const int* __restrict__ rowoff,
                                  double a, double phibar) {
   double2 prev[3], next[3];
-  edge_neighbours<SEG>(V, w.lane, prev, next);
+  edge_neighbours<SEG>(V, w, prev, next);
   const double2 zero3[3] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0),
                             make_double2(0.0, 0.0)};
 #pragma unroll
@@ -361,6 +382,7 @@ __device__ inline void asm_lane(const SE* __restrict__ Q, const int* __restrict_
 
 struct SpecArgs {
   const int* rowoff;
+  const int* tasks;
   int M, ncoef, B;
   double a, phibar;
 };
@@ -370,7 +392,7 @@ template <int SEG, typename SE>
 __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_cn_prep(const double* __restrict__ in,
                                                    double* __restrict__ ua, SE* __restrict__ S,
                                                    SpecArgs sa, CnArgs c) {
-  const WaveAt w = wave_at<SEG>(sa.M, sa.B);
+  const WaveAt w = wave_at<SEG>(sa.M, sa.B, sa.tasks);
   if (w.b >= sa.B) return;                            // uniform per wave
   double2 V[SEG][3];
   load_state<SEG>(in, w, sa.ncoef, V);
@@ -385,7 +407,7 @@ __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_stage1(const SE* __restr
                                                   const double* __restrict__ ua,
                                                   double* __restrict__ n1, SE* __restrict__ S,
                                                   double dt, SpecArgs sa) {
-  const WaveAt w = wave_at<SEG>(sa.M, sa.B);
+  const WaveAt w = wave_at<SEG>(sa.M, sa.B, sa.tasks);
   if (w.b >= sa.B) return;                            // uniform per wave
   double2 N[SEG][3], V[SEG][3];
   asm_lane<SEG>(Q, sa.rowoff, w, sa.B, sa.a, N);
@@ -414,7 +436,7 @@ __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_stage2(const SE* __restr
                                                   const double* __restrict__ cf,
                                                   double* __restrict__ corr,
                                                   SpecArgs sa, CnArgs c) {
-  const WaveAt w = wave_at<SEG>(sa.M, sa.B);
+  const WaveAt w = wave_at<SEG>(sa.M, sa.B, sa.tasks);
   if (w.b >= sa.B) return;                            // uniform per wave
   double2 N[SEG][3], V[SEG][3];
   asm_lane<SEG>(Q, sa.rowoff, w, sa.B, sa.a, N);
@@ -462,7 +484,7 @@ __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_stage2(const SE* __restr
 template <int SEG, typename SE>
 __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_prep(const double* __restrict__ in,
                                                 SE* __restrict__ S, SpecArgs sa) {
-  const WaveAt w = wave_at<SEG>(sa.M, sa.B);
+  const WaveAt w = wave_at<SEG>(sa.M, sa.B, sa.tasks);
   if (w.b >= sa.B) return;                            // uniform per wave
   double2 V[SEG][3];
   load_state<SEG>(in, w, sa.ncoef, V);
@@ -473,7 +495,7 @@ __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_prep(const double* __res
 template <int SEG, typename SE>
 __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_tend(const SE* __restrict__ Q,
                                                 double* __restrict__ out, SpecArgs sa) {
-  const WaveAt w = wave_at<SEG>(sa.M, sa.B);
+  const WaveAt w = wave_at<SEG>(sa.M, sa.B, sa.tasks);
   if (w.b >= sa.B) return;                            // uniform per wave
   double2 N[SEG][3];
   asm_lane<SEG>(Q, sa.rowoff, w, sa.B, sa.a, N);
@@ -486,7 +508,7 @@ template <int SEG>
 __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_cn(const double* __restrict__ in,
                                               double* __restrict__ out, int two, SpecArgs sa,
                                               CnArgs c0, CnArgs c1) {
-  const WaveAt w = wave_at<SEG>(sa.M, sa.B);
+  const WaveAt w = wave_at<SEG>(sa.M, sa.B, sa.tasks);
   if (w.b >= sa.B) return;                            // uniform per wave
   double2 V[SEG][3];
   load_state<SEG>(in, w, sa.ncoef, V);
@@ -504,11 +526,11 @@ template <int SEG>
 __global__ __launch_bounds__(64 * kSpecWaves) void k_sp_sl_solve(const double* __restrict__ Q,
                                                     double* __restrict__ out, SpecArgs sa,
                                                     CnArgs c) {
-  const WaveAt w = wave_at<SEG>(sa.M, sa.B);
+  const WaveAt w = wave_at<SEG>(sa.M, sa.B, sa.tasks);
   if (w.b >= sa.B) return;                            // uniform per wave
   double2 V[SEG][3];
   asm_lane<SEG, double>(Q, sa.rowoff, w, sa.B, sa.a, V);
-  if (w.m == 0 && w.lane == 0) V[0][0].x += sa.phibar;   // Phi = Phibar + Phi'
+  if (w.m == 0 && w.lane == w.slo) V[0][0].x += sa.phibar;   // Phi = Phibar + Phi'
   cn_lane<SEG>(V, w, sa.ncoef, c);
   store_state<SEG>(out, w, sa.ncoef, V);
 }
@@ -523,9 +545,50 @@ static int seg_of(int M) {
 // three waves of a four-state workgroup would have nothing to do.
 static unsigned spec_threads(int B) { return B == 1 ? 64u : 64u * kSpecWaves; }
 
+// Workgroups of a launch over B states: tasks x state groups.
+static unsigned spec_grid(const Plan& p, int B) {
+  return (unsigned)(p.n_spec_tasks * ((B + kSpecWaves - 1) / kSpecWaves));
+}
+
+// Tasks: the chains in order of decreasing length, each opening a task that
+// the shortest chains not yet placed then fill while their segments fit in
+// the 64 lanes (at most kSpecTaskChains chains per task).  A function of M
+// (and the lanes per chain) only.
+pint_status spec_tasks_build(Plan& p, size_t* total) {
+  const int seg = seg_of(p.M) > 0 ? seg_of(p.M) : 64;   // unsupported M: launches refuse
+  auto lanes = [&](int m) { return (p.M - m + 1 + seg - 1) / seg; };
+  std::vector<int> h;
+  for (int i = 0, j = p.M; i <= j;) {
+    int rec[kSpecTaskInts] = {};
+    int n = 0, used = 0;
+    auto add = [&](int m) {
+      rec[1 + n] = m;
+      rec[1 + kSpecTaskChains + n] = used;
+      used += lanes(m);
+      ++n;
+    };
+    add(i++);
+    while (j >= i && n < kSpecTaskChains && used + lanes(j) <= 64) add(j--);
+    rec[0] = n;
+    h.insert(h.end(), rec, rec + kSpecTaskInts);
+  }
+  p.n_spec_tasks = (int)(h.size() / kSpecTaskInts);
+  void* d = nullptr;
+  hipError_t e = hipMalloc(&d, h.size() * sizeof(int));
+  if (e != hipSuccess) {
+    set_error("hipMalloc(%zu bytes) failed: %s", h.size() * sizeof(int), hipGetErrorString(e));
+    return PINT_E_NOMEM;
+  }
+  p.spec_tasks = static_cast<int*>(d);
+  if (total) *total += h.size() * sizeof(int);
+  PINT_HIP(hipMemcpy(d, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice));
+  return PINT_OK;
+}
+
 static SpecArgs spec_args(const Plan& p, int B) {
   SpecArgs sa;
   sa.rowoff = p.rowoff;
+  sa.tasks = p.spec_tasks;
   sa.M = p.M;
   sa.ncoef = p.ncoef;
   sa.B = B;
@@ -575,7 +638,7 @@ pint_status sp_cn_prep(Plan& p, const CnFactors& f, const pint_stepper& st, cons
   ProfScope ps(p, PK_CN, B, s);
   const SpecArgs sa = spec_args(p, B);
   const CnArgs c = cn_args(p, f, st, false);
-  const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
+  const dim3 grid(spec_grid(p, B));
 #define L(SEG, SE)                                                                      \
   hipLaunchKernelGGL((k_sp_cn_prep<SEG, SE>), grid, dim3(spec_threads(B)), 0, s, in, p.Ua, \
                      reinterpret_cast<SE*>(p.S), sa, c)
@@ -588,7 +651,7 @@ pint_status sp_cn_prep(Plan& p, const CnFactors& f, const pint_stepper& st, cons
 pint_status sp_stage1(Plan& p, double dt, int B, hipStream_t s) {
   ProfScope ps(p, PK_ASSEMBLE, B, s);
   const SpecArgs sa = spec_args(p, B);
-  const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
+  const dim3 grid(spec_grid(p, B));
 #define L(SEG, SE)                                                                    \
   hipLaunchKernelGGL((k_sp_stage1<SEG, SE>), grid, dim3(spec_threads(B)), 0, s,          \
                      reinterpret_cast<const SE*>(p.Q), p.Ua, p.N1, reinterpret_cast<SE*>(p.S), \
@@ -604,7 +667,7 @@ pint_status sp_stage2(Plan& p, const CnFactors& f, const pint_stepper& st, doubl
   ProfScope ps(p, PK_ASSEMBLE, B, s);
   const SpecArgs sa = spec_args(p, B);
   const CnArgs c = cn_args(p, f, st, true);
-  const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
+  const dim3 grid(spec_grid(p, B));
 #define L(SEG, SE)                                                                    \
   hipLaunchKernelGGL((k_sp_stage2<SEG, SE>), grid, dim3(spec_threads(B)), 0, s,          \
                      reinterpret_cast<const SE*>(p.Q), p.Ua, p.N1, out,                  \
@@ -618,7 +681,7 @@ pint_status sp_stage2(Plan& p, const CnFactors& f, const pint_stepper& st, doubl
 pint_status sp_prep(Plan& p, const double* in, int B, hipStream_t s) {
   ProfScope ps(p, PK_PREP, B, s);
   const SpecArgs sa = spec_args(p, B);
-  const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
+  const dim3 grid(spec_grid(p, B));
 #define L(SEG, SE)                                                                 \
   hipLaunchKernelGGL((k_sp_prep<SEG, SE>), grid, dim3(spec_threads(B)), 0, s, in,      \
                      reinterpret_cast<SE*>(p.S), sa)
@@ -631,7 +694,7 @@ pint_status sp_prep(Plan& p, const double* in, int B, hipStream_t s) {
 pint_status sp_tend(Plan& p, double* out, int B, hipStream_t s) {
   ProfScope ps(p, PK_ASSEMBLE, B, s);
   const SpecArgs sa = spec_args(p, B);
-  const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
+  const dim3 grid(spec_grid(p, B));
 #define L(SEG, SE)                                                                 \
   hipLaunchKernelGGL((k_sp_tend<SEG, SE>), grid, dim3(spec_threads(B)), 0, s,          \
                      reinterpret_cast<const SE*>(p.Q), out, sa)
@@ -648,7 +711,7 @@ pint_status sp_cn(Plan& p, const CnFactors& f, const pint_stepper& st0, const pi
   const CnArgs c0 = cn_args(p, f, st0, st1 == nullptr);
   const CnArgs c1 = st1 ? cn_args(p, f, *st1, true) : c0;
   const int two = st1 ? 1 : 0;
-  const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
+  const dim3 grid(spec_grid(p, B));
 #define L(SEG, SE)                                                                           \
   hipLaunchKernelGGL(k_sp_cn<SEG>, grid, dim3(spec_threads(B)), 0, s, in, out, two, sa, c0, c1)
   PINT_SEG_DISPATCH(L)
@@ -858,7 +921,7 @@ pint_status sp_sl_solve(Plan& p, const CnFactors& f, double dt, int visc_order, 
   CnArgs c = cn_args(p, f, st, true);      // alpha = (2 dt) / 4 = dt / 2
   c.vdt = dt;
   c.rhs_given = 1;
-  const dim3 grid((unsigned)((p.M + 1) * ((B + kSpecWaves - 1) / kSpecWaves)));
+  const dim3 grid(spec_grid(p, B));
   switch (seg_of(p.M)) {
 #define L(SEG)                                                                              \
   case SEG:                                                                                 \
