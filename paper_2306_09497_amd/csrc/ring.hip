@@ -418,22 +418,21 @@ constexpr int ilog2c(int n) {
   return c;
 }
 // Radix plan of a half-length transform of H points: stage 0 (span H) has
-// radix 6, 5, 8 or 4; the rest is radix 4 with one radix 8 when needed.  The
-// forward transform ends with stage 0 at stride H / R_0, which is even for
-// every supported ring, so its butterflies j and S - j pair up as Z_k, Z_{H-k}.
-constexpr int hplan_first(int H) {
-  return H % 3 == 0 ? 6 : (H % 5 == 0 ? 5 : (ilog2c(H) % 2 ? 8 : 4));
+// radix 6, 5 or 8 (H divisible by 3, by 5, or a power of two); the remaining
+// power of two 2^k goes in radix-8 stages, with one radix-4 stage when
+// k = 2 (mod 3) and two when k = 1 (mod 3) -- as few passes over the LDS
+// signals as the in-register butterflies allow.  The forward transform ends
+// with stage 0 at stride H / R_0, which is even for every supported ring, so
+// its butterflies j and S - j pair up as Z_k, Z_{H-k}.
+constexpr int hplan_first(int H) { return H % 3 == 0 ? 6 : (H % 5 == 0 ? 5 : 8); }
+constexpr int hplan_restlog(int H) { return ilog2c(H / hplan_first(H)); }
+constexpr int hplan_n4(int H) {
+  return hplan_restlog(H) % 3 == 0 ? 0 : (hplan_restlog(H) % 3 == 2 ? 1 : 2);
 }
-constexpr int hplan_npass(int H) {
-  int rest = H / hplan_first(H);
-  int c = 1;
-  if (ilog2c(rest) % 2) { rest /= 8; ++c; }
-  while (rest > 1) { rest /= 4; ++c; }
-  return c;
-}
+constexpr int hplan_n8(int H) { return (hplan_restlog(H) - 2 * hplan_n4(H)) / 3; }
+constexpr int hplan_npass(int H) { return 1 + hplan_n8(H) + hplan_n4(H); }
 constexpr int hplan_radix(int H, int i) {
-  if (i == 0) return hplan_first(H);
-  return (i == 1 && ilog2c(H / hplan_first(H)) % 2) ? 8 : 4;
+  return i == 0 ? hplan_first(H) : (i <= hplan_n8(H) ? 8 : 4);
 }
 constexpr int hplan_span(int H, int i) {
   int L = H;
