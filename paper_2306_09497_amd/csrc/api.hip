@@ -337,10 +337,57 @@ static pint_status level1_cycles(Plan& p, const pint_pint_params* q, Level1Bufs&
   return PINT_OK;
 }
 
+// Pipelined relaxation (two-level MGRIT with one CF pass, two iterations or
+// more): the next iteration's C-relaxation FvR[n] = Phi_0^m(U_n) runs on the
+// relax stream, chunk by chunk as soon as the serial sweep has written the
+// chunk's slice states, beside the rest of the sweep; in the next iteration
+// each chunk of the fine propagation first sets its C-points U_{n+1} =
+// FvR[n], waiting only for the relaxation chunks it reads (U_N is not set:
+// the sweep overwrites it unread).  Same inputs and kernels as the
+// relaxation at the start of the iteration, so the same values.  FvR holds
+// two generations (iteration parity), so that making the next one never
+// overwrites values the current iteration still reads.  It needs its own
+// transform workspace (the chunks of the fine propagation and the sweep use
+// the plan's two): relax_cap states in six pool slots.
+static bool relax_pipelined(const Plan& p, const pint_pint_params* q) {
+  return p.pipeline_relax && q->method == 1 && q->levels != 3 && q->nrelax == 1 &&
+         q->max_iter >= 2;
+}
+static int relax_chunk(const Plan& p, int N) { return (N + p.sweep_chunks - 1) / p.sweep_chunks; }
+static int relax_cap(const Plan& p, int N) {
+  const int cs = relax_chunk(p, N);
+  return cs < p.max_batch ? cs : p.max_batch;
+}
+// doubles of the workspace buffers S, F, G, Q, Ua, N1 for `cap` states (as
+// the plan's own at max_batch)
+static void relax_work_sizes(const Plan& p, int cap, size_t (&n)[6]) {
+  n[0] = (size_t)p.nrows * 12 * cap;
+  n[1] = (size_t)(p.M + 1) * fourier_pitch<double>(p.nlat, 12 * cap);
+  n[2] = (size_t)(p.M + 1) * fourier_pitch<double>(p.nlat, 8 * cap);
+  n[3] = (size_t)p.nrows * 8 * cap;
+  n[4] = n[5] = (size_t)p.ncoef * cap * 3 * 2;
+}
+
+// Points the plan's transform workspace (and its batch limit) at the
+// relaxation workspace while in scope (kernels capture the pointers current
+// at their enqueue).
+struct RelaxWork {
+  Plan& p;
+  double *S, *F, *G, *Q, *Ua, *N1;
+  int mb;
+  RelaxWork(Plan& pl, double* const (&w)[6], int cap) : p(pl) {
+    S = p.S, F = p.F, G = p.G, Q = p.Q, Ua = p.Ua, N1 = p.N1, mb = p.max_batch;
+    p.S = w[0], p.F = w[1], p.G = w[2], p.Q = w[3], p.Ua = w[4], p.N1 = w[5];
+    p.max_batch = cap;
+  }
+  ~RelaxWork() { p.S = S, p.F = F, p.G = G, p.Q = Q, p.Ua = Ua, p.N1 = N1, p.max_batch = mb; }
+};
+
 // Device memory pint_solve(q) needs on plan p (the coarse plan's factor sets
 // separately): the driver scratch of its pool slots and the Crank-Nicolson
 // factors of its steppers.  Every buffer solve() uses is sized here.
-pint_status solve_footprint(const Plan& p, const pint_pint_params* q, Footprint& fp) {
+pint_status solve_footprint(const Plan& p, const pint_pint_params* q, Footprint& fp,
+                            bool pipelined) {
   if (!q) return PINT_OK;
   PINT_TRY(check_params(p, q));
   const size_t N = (size_t)q->n_intervals;
@@ -351,6 +398,12 @@ pint_status solve_footprint(const Plan& p, const pint_pint_params* q, Footprint&
   fp.need(kSlotGtmp, sd);
   fp.need(kSlotIncr, 8 * N);                 // increment sums, one iteration
   fp.host_doubles = 8 * N;
+  if (pipelined && relax_pipelined(p, q)) {
+    fp.need(kSlotFvR, 2 * sd * N);
+    size_t n[6];
+    relax_work_sizes(p, relax_cap(p, (int)N), n);
+    for (int i = 0; i < 6; ++i) fp.need(kSlotRS + i, n[i]);
+  }
   const bool three = q->method == 1 && q->levels == 3;
   if (three) {
     const size_t m1 = (size_t)q->cfactor1, N2 = N / m1, rows = m1 * (N2 + 1);
@@ -400,6 +453,33 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
   const bool mgrit = q->method == 1;
   const int nrelax = mgrit ? q->nrelax : 0;
   const bool three = mgrit && q->levels == 3;
+  const bool pipe = relax_pipelined(p, q);
+  DevBuf FvR(p, kSlotFvR);
+  double* rwork[6] = {};
+  const int rcs = relax_chunk(p, N), rcap = relax_cap(p, N);
+  if (pipe) {
+    PINT_TRY(FvR.alloc(2 * sd * N));
+    size_t n[6];
+    relax_work_sizes(p, rcap, n);
+    for (int i = 0; i < 6; ++i) {
+      DevBuf b(p, kSlotRS + i);
+      PINT_TRY(b.alloc(n[i]));
+      rwork[i] = b.p;
+    }
+  }
+  bool prerelaxed = false;   // this iteration's relaxation is waiting in FvR
+  int kit = 0;               // the iteration being enqueued (FvR generation)
+  // work on the relax stream not yet ordered before later work on s: joined
+  // into s when the solve returns, whichever way it does
+  struct RelaxJoin {
+    Plan& p;
+    hipStream_t s;
+    bool pending = false;
+    ~RelaxJoin() {
+      if (pending && hipEventRecord(p.relax_join_ev, p.relax_stream) == hipSuccess)
+        (void)hipStreamWaitEvent(s, p.relax_join_ev, 0);
+    }
+  } rjoin{p, s};
   Level1Bufs l1(p);
   if (three) PINT_TRY(l1.alloc(sd, q->cfactor1, N / q->cfactor1));
   CoarseProp coarse(p);
@@ -440,17 +520,26 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
     if (!capturing) PINT_HIP(hipEventRecord(ev, st));
     return PINT_OK;
   };
-  auto iteration = [&](int first, hipStream_t s) -> pint_status {
+  // speculate: also run the next iteration's relaxation beside the sweep
+  auto iteration = [&](int first, hipStream_t s, bool speculate) -> pint_status {
     PINT_TRY(rec(p.ph_ev[0], s));
     PINT_HIP(hipMemcpyAsync(Uprev.p, U, sb * (N + 1), hipMemcpyDeviceToDevice, s));
     const double* src = U;   // C-points the fine propagation starts from
-    if (nrelax > 0) {
+    const size_t gen = (size_t)N * sd;
+    double* fvr_use = FvR.p + (size_t)(kit & 1) * gen;         // made beside the last sweep
+    double* fvr_make = FvR.p + (size_t)((kit + 1) & 1) * gen;  // for the next iteration
+    if (nrelax > 0 && prerelaxed) {
+      // the CF pass made beside the previous sweep, set chunk by chunk below
+      r->fine_slice_steps += (long long)N * q->fine_steps;
+    } else if (nrelax > 0) {
       // F(CF)^nu: each CF pass replaces C-point i+1 by Phi_0^m of C-point i
       for (int it = 0; it < nrelax; ++it) {
         PINT_TRY(propagate(p, q->fine, U, Fv.p, N, q->fine_steps, s));
         PINT_HIP(hipMemcpyAsync(U + sd, Fv.p, sb * N, hipMemcpyDeviceToDevice, s));
         r->fine_slice_steps += (long long)N * q->fine_steps;
       }
+    }
+    if (nrelax > 0) {
       // coarse values of the relaxed C-points, Phi_1(v_i): all of them now
       // for three levels; with two levels chunk by chunk below, so that the
       // sweep can start after the first chunk
@@ -480,6 +569,18 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
       for (int c = 0; c < nchunk; ++c) {
         const int n0 = first + c * cs;
         const int nb = cs < N - n0 ? cs : N - n0;
+        if (nrelax > 0 && prerelaxed) {
+          // C-points U_n = FvR[n-1] of this chunk, once the relaxation chunks
+          // (of rcs slices) that make them, and those that still read the
+          // U_n they overwrite, are done
+          const int lo = n0 > 1 ? n0 : 1, hi = n0 + nb;
+          if (hi > lo) {
+            for (int rc = (lo - 1) / rcs; rc <= (hi - 1) / rcs; ++rc)
+              PINT_HIP(hipStreamWaitEvent(s, p.relax_done_ev[rc], 0));
+            PINT_HIP(hipMemcpyAsync(U + (size_t)lo * sd, fvr_use + (size_t)(lo - 1) * sd,
+                                    sb * (hi - lo), hipMemcpyDeviceToDevice, s));
+          }
+        }
         if (nrelax > 0) {
           PINT_TRY(coarse.run(q->coarse, q->coarse_steps, src + n0 * sd, Gold.p + n0 * sd, nb, s,
                               false));
@@ -488,6 +589,11 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
         PINT_TRY(propagate(p, q->fine, src + n0 * sd, Fv.p + n0 * sd, nb, q->fine_steps, s));
         PINT_HIP(hipEventRecord(p.chunk_ev[c], s));
       }
+      if (nrelax > 0 && prerelaxed) {
+        // the last relaxation chunk (whose last value, U_N, was not used)
+        PINT_HIP(hipStreamWaitEvent(s, p.relax_done_ev[(N - 1) / rcs], 0));
+        rjoin.pending = false;
+      }
       PINT_TRY(rec(p.ph_ev[1], s));
       r->fine_slice_steps += (long long)nact * q->fine_steps;
       // serial correction sweep U_{n+1} = (G(U_n^new) - G(U_n^old)) + F(U_n^old)
@@ -495,13 +601,34 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
       // reads F(U_n^old) (chunk (n-first)/cs) and overwrites U_{n+1}, the start
       // of chunk (n+1-first)/cs when it begins one: it waits for both.
       {
-        hipStream_t ss = p.side_stream;
+        hipStream_t ss = p.side_stream, rs = p.relax_stream;
         int waited = -1;
         bool prepped = false;   // this step's first half step was made by the previous one
+        // relaxation chunk c (slices c rcs .. ) once slice states 0..`done`
+        // are final on the sweep stream
+        const int nrc = speculate ? (N + rcs - 1) / rcs : 0;
+        int next_rc = 0;
+        auto relax_ready = [&](int done) -> pint_status {
+          for (; next_rc < nrc; ++next_rc) {
+            const int a = next_rc * rcs, cnt = rcs < N - a ? rcs : N - a;
+            if (a + cnt - 1 > done) break;
+            PINT_HIP(hipEventRecord(p.relax_ev[next_rc], ss));
+            PINT_HIP(hipStreamWaitEvent(rs, p.relax_ev[next_rc], 0));
+            {
+              RelaxWork rw(p, rwork, rcap);
+              PINT_TRY(propagate(p, q->fine, U + (size_t)a * sd, fvr_make + (size_t)a * sd, cnt,
+                                 q->fine_steps, rs));
+            }
+            PINT_HIP(hipEventRecord(p.relax_done_ev[next_rc], rs));
+            rjoin.pending = true;
+          }
+          return PINT_OK;
+        };
         for (int n = first; n < N; ++n) {
           int need = (n + 1 - first) / cs;
           if (need > nchunk - 1) need = nchunk - 1;
           while (waited < need) PINT_HIP(hipStreamWaitEvent(ss, p.chunk_ev[++waited], 0));
+          PINT_TRY(relax_ready(n));   // U_0 .. U_n are final
           if (n == first) {   // unchanged input: G_new = G_old
             PINT_TRY(pr_update(p, Gold.p + n * sd, Gold.p + n * sd, Fv.p + n * sd,
                                U + (n + 1) * sd, sd, ss));
@@ -514,6 +641,7 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
             r->coarse_steps += q->coarse_steps;
           }
         }
+        PINT_TRY(relax_ready(N));
         PINT_TRY(rec(p.ph_ev[2], ss));
         PINT_HIP(hipEventRecord(p.join_ev, ss));
       }
@@ -532,14 +660,19 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
     }
   } graph;
   long long g_fine = 0, g_coarse = 0;   // counters of one replayed iteration
+  // (not with the pipelined relaxation: its iterations leave work running
+  // on the relax stream, which a graph launch would have to wait for)
   bool graphable = (mgrit || q->resume) && p.use_graphs && !p.prof_on &&
-                   !(coarse.pc && coarse.pc->prof_on);
+                   !(coarse.pc && coarse.pc->prof_on) && !pipe;
   pint_status result = PINT_OK;
   for (int k = 0; k < q->max_iter; ++k) {
     const double t0 = now_s();
     // slices before `first` are already exact (Parareal); MGRIT recomputes all
     const int first = (mgrit || q->resume) ? 0 : (k < N ? k : N);
     if (first >= N) break;
+    // pipelined relaxation: every iteration but the last makes the next one's
+    const bool speculate = pipe && k + 1 < q->max_iter;
+    kit = k;
     bool replayed = false;
     if (graph.e) {
       PINT_HIP(hipEventRecord(p.ph_ev[0], s));
@@ -561,7 +694,7 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
       if (dbg) fprintf(stderr, "[graph] begin capture: %s\n", hipGetErrorString(e0));
       if (ok) {
         capturing = true;
-        const pint_status st = iteration(first, cs);
+        const pint_status st = iteration(first, cs, speculate);
         capturing = false;
         if (dbg && st != PINT_OK) fprintf(stderr, "[graph] iteration: %s\n", last_error());
         const hipError_t e1 = hipStreamEndCapture(cs, &g);
@@ -587,11 +720,12 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
         graphable = false;
         r->fine_slice_steps = f0;
         r->coarse_steps = c0;
-        PINT_TRY(iteration(first, s));
+        PINT_TRY(iteration(first, s, speculate));
       }
     } else {
-      PINT_TRY(iteration(first, s));
+      PINT_TRY(iteration(first, s, speculate));
     }
+    prerelaxed = speculate;
     if (replayed) {   // the graph's two phases as one
       PINT_HIP(hipEventRecord(p.ph_ev[1], s));
       PINT_HIP(hipEventRecord(p.ph_ev[2], s));

@@ -117,6 +117,13 @@ struct Plan {
   bool use_graphs = true;                // replay repeating iterations from a graph
   std::vector<hipEvent_t> chunk_ev;  // one per fine-propagation chunk
   hipEvent_t join_ev = nullptr;      // end of a sweep on side_stream
+  // the next iteration's relaxation runs on relax_stream beside the sweep
+  // (two-level MGRIT, one CF pass): relax_ev[c] releases its chunk c,
+  // relax_done_ev[c] marks it done, relax_join_ev ends the relax stream's work
+  hipStream_t relax_stream = nullptr;
+  std::vector<hipEvent_t> relax_ev, relax_done_ev;
+  hipEvent_t relax_join_ev = nullptr;
+  bool pipeline_relax = true;
   int sweep_chunks = 4;
   double* red = nullptr;       // reduction scratch
   double* diag = nullptr;      // L2-error partial sums [3 max_batch][nlat][2]
@@ -305,7 +312,8 @@ struct DevBuf {
 enum PoolSlot { kSlotGold, kSlotFv, kSlotUprev, kSlotGtmp, kSlotCin, kSlotCinSide, kSlotW,
                 kSlotFl, kSlotGl, kSlotTmp, kSlotF2, kSlotG2, kSlotGz, kSlotSlGrid, kSlotSlF,
                 kSlotSlO, kSlotPsGold, kSlotPsFv, kSlotPsG, kSlotPsCin, kSlotPsCout,
-                kSlotPsPrev, kSlotPsPold, kSlotIncr, kSlotCount };
+                kSlotPsPrev, kSlotPsPold, kSlotIncr, kSlotFvR, kSlotRS, kSlotRF, kSlotRG,
+                kSlotRQ, kSlotRUa, kSlotRN1, kSlotCount };
 
 // Device memory a workload needs on one plan: doubles per pool slot and the
 // Crank-Nicolson factor keys (dt, terms) it uses.  Filled by the drivers'
@@ -328,7 +336,10 @@ struct Footprint {
 size_t cn_factor_bytes(const Plan& p);
 // footprint of pint_solve(q) (q may be NULL) and of pint_sl_steps with
 // stepper sl (may be NULL) on plan p
-pint_status solve_footprint(const Plan& p, const pint_pint_params* q, Footprint& fp);
+// (pipelined: with the buffers of the relaxation pipelined beside the sweep
+// when the solve uses it; the server does not)
+pint_status solve_footprint(const Plan& p, const pint_pint_params* q, Footprint& fp,
+                            bool pipelined = true);
 void sl_footprint(const Plan& p, const pint_sl_stepper& st, Footprint& fp);
 pint_status sl_check(const Plan& p, const pint_sl_stepper& st, int B, int nsteps);
 size_t footprint_bytes(const Plan& p, const Plan* pc, const Footprint& fp);

@@ -181,6 +181,14 @@ static void free_plan(Plan& p) {
   p.pool.clear();
   for (hipEvent_t e : p.chunk_ev) (void)hipEventDestroy(e);
   p.chunk_ev.clear();
+  for (hipEvent_t e : p.relax_ev) (void)hipEventDestroy(e);
+  p.relax_ev.clear();
+  for (hipEvent_t e : p.relax_done_ev) (void)hipEventDestroy(e);
+  p.relax_done_ev.clear();
+  if (p.relax_join_ev) (void)hipEventDestroy(p.relax_join_ev);
+  p.relax_join_ev = nullptr;
+  if (p.relax_stream) (void)hipStreamDestroy(p.relax_stream);
+  p.relax_stream = nullptr;
   if (p.join_ev) (void)hipEventDestroy(p.join_ev);
   p.join_ev = nullptr;
   for (hipEvent_t& e : p.ph_ev) {
@@ -367,7 +375,9 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
   // ordering against the caller's stream is by events only
   if (hipStreamCreateWithFlags(&p.side_stream, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&p.capture_stream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&p.join_ev, hipEventDisableTiming) != hipSuccess) {
+      hipStreamCreateWithFlags(&p.relax_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&p.join_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p.relax_join_ev, hipEventDisableTiming) != hipSuccess) {
     free_plan(p);
     delete pp;
     set_error("hipStreamCreateWithFlags / hipEventCreateWithFlags failed");
@@ -382,6 +392,17 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
     }
   }
   p.chunk_ev.assign(kMaxSweepChunks, nullptr);
+  p.relax_ev.assign(kMaxSweepChunks, nullptr);
+  p.relax_done_ev.assign(kMaxSweepChunks, nullptr);
+  for (auto* v : {&p.relax_ev, &p.relax_done_ev})
+    for (hipEvent_t& e : *v) {
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        free_plan(p);
+        delete pp;
+        set_error("hipEventCreateWithFlags failed");
+        return PINT_E_HIP;
+      }
+    }
   for (hipEvent_t& e : p.chunk_ev) {
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
       free_plan(p);
@@ -391,6 +412,7 @@ pint_status create(const pint_config* cfg, hipStream_t s, pint_plan** out) {
     }
   }
   if (const char* env = getenv("PINT_GRAPHS")) p.use_graphs = atoi(env) != 0;
+  if (const char* env = getenv("PINT_PIPELINE")) p.pipeline_relax = atoi(env) != 0;
   if (const char* env = getenv("PINT_GEMM_VARIANT")) {   // fixed launch shapes (tests)
     const int v = atoi(env) < 0 ? 0 : atoi(env);
     p.gemm_variant[0][0] = p.gemm_variant[1][0] = p.gemm_variant[0][1] = v > 1 ? 1 : v;

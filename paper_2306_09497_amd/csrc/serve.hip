@@ -511,7 +511,7 @@ pint_status pint_server_submit(pint_server* S, const pint_request* req, long lon
   // of its slice states
   const int N = q.n_intervals;
   Footprint fp;
-  PINT_TRY(solve_footprint(p, &q, fp));
+  PINT_TRY(solve_footprint(p, &q, fp, false));
   size_t scratch = 0;
   for (int i = 0; i < kSlotCount; ++i) scratch += fp.slot[i];
   const size_t bytes = (scratch + ((size_t)N + 1) * state_doubles(p)) * sizeof(double);

@@ -44,7 +44,7 @@ def c1(method, k, **kw):
 
 
 @pytest.mark.parametrize("q", [
-    c1(pint.MGRIT, 5, nrelax=1),
+    c1(pint.MGRIT, 5, nrelax=1),       # (relaxation not pipelined: PINT_PIPELINE=0 below)
     c1(pint.MGRIT, 4, nrelax=0),
     pint.params(pint.MGRIT, 8, pint.stepper(60.0, 2, 0.0, pint.T_ALL), 180,
                 pint.stepper(3600.0, 2, 1e5, pint.T_ALL), 3, nrelax=1, max_iter=4, levels=3,
@@ -52,8 +52,8 @@ def c1(method, k, **kw):
 ], ids=["mgrit_fcf", "mgrit_f", "mgrit3"])
 def test_graph_replay_is_bitwise_the_plain_launches(monkeypatch, q):
     U0 = workloads.solid_body(M, noise=1e-3, seed=4)
-    a, ra = solve(plan_with(monkeypatch, {"PINT_GRAPHS": "0"}), q, U0)
-    b, rb = solve(plan_with(monkeypatch, {}), q, U0)
+    a, ra = solve(plan_with(monkeypatch, {"PINT_GRAPHS": "0", "PINT_PIPELINE": "0"}), q, U0)
+    b, rb = solve(plan_with(monkeypatch, {"PINT_PIPELINE": "0"}), q, U0)
     print(f"graph iterations {rb.graph_iters} of {rb.iters}; seconds plain "
           f"{list(ra.seconds[:ra.iters])} graph {list(rb.seconds[:rb.iters])}", flush=True)
     assert ra.graph_iters == 0 and rb.graph_iters == q.max_iter - 1

@@ -1,0 +1,104 @@
+"""Two-level MGRIT FCF (Sec. 3.2) with one CF pass: the C-relaxation of
+iteration k+1, U_{i+1} = Phi_0^m(U_i), only needs the slice states the serial
+sweep of iteration k has already written, so it runs chunk by chunk beside
+the rest of that sweep.  Same inputs, same kernels: the iterates, increments
+and step counts are bitwise those of the relaxation at the start of each
+iteration, for every chunking, with and without graph replay, with spatial
+coarsening, a tolerance stop, and chunks larger than the relaxation
+workspace."""
+
+import numpy as np
+import pytest
+
+from gpu_util import to_dev
+from paper_2306_09497_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2306_09497_amd import pint  # noqa: E402
+
+PB = 2.94e4
+
+
+def plan_with(monkeypatch, env, M=21, nlon=64, nlat=32, max_batch=8):
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    pl = pint.Plan(M, nlon, nlat, phibar=PB, max_batch=max_batch)
+    for k in env:
+        monkeypatch.delenv(k)
+    return pl
+
+
+def solve(pl, q, U0):
+    u0 = to_dev(U0, torch)
+    us = torch.zeros((q.n_intervals + 1, 3, pl.ncoef, 2), dtype=torch.float64, device="cuda")
+    rep = pl.solve(q, u0, us)
+    torch.cuda.synchronize()
+    return us, rep
+
+
+def same(ra, rb):
+    return (ra.iters == rb.iters and ra.fine_slice_steps == rb.fine_slice_steps
+            and ra.coarse_steps == rb.coarse_steps
+            and [ra.incr[i] for i in range(ra.iters)] == [rb.incr[i] for i in range(rb.iters)])
+
+
+def fcf(N, k, M=21, **kw):
+    return pint.params(pint.MGRIT, N, pint.stepper(300.0, 2, 0.0, pint.T_ALL), 4,
+                       pint.stepper(1200.0, 4, 1e15, pint.T_ALL), 1, nrelax=1, max_iter=k, **kw)
+
+
+@pytest.mark.parametrize("chunks,graphs", [("4", "1"), ("1", "1"), ("3", "0"), ("8", "1")])
+def test_pipelined_relaxation_is_bitwise_the_plain_one(monkeypatch, chunks, graphs):
+    U0 = workloads.solid_body(21, noise=1e-3, seed=11)
+    q = fcf(8, 5)
+    env = {"PINT_SWEEP_CHUNKS": chunks, "PINT_GRAPHS": graphs}
+    a, ra = solve(plan_with(monkeypatch, {**env, "PINT_PIPELINE": "0"}), q, U0)
+    b, rb = solve(plan_with(monkeypatch, env), q, U0)
+    print(f"chunks {chunks} graphs {graphs}: graph iterations {rb.graph_iters}, seconds "
+          f"plain {list(ra.seconds[:ra.iters])} pipelined {list(rb.seconds[:rb.iters])}",
+          flush=True)
+    assert torch.equal(a, b) and same(ra, rb)
+    assert rb.fine_slice_steps == 5 * 2 * 8 * 4
+
+
+def test_pipelined_with_coarse_plan_and_tolerance(monkeypatch):
+    """Spatial coarsening (coarse level at T10) and a tolerance that stops
+    the iteration early (the relaxation made for the iteration that does not
+    run is discarded)."""
+    U0 = workloads.solid_body(21, noise=1e-3, seed=12)
+    pc = pint.Plan(10, 64, 32, phibar=PB, max_batch=8)
+    runs = []
+    for env in ({"PINT_PIPELINE": "0"}, {}):
+        pl = plan_with(monkeypatch, env)
+        q = fcf(8, 8, coarse_plan=pc, tol=1e-5)
+        us = torch.zeros((9, 3, pl.ncoef, 2), dtype=torch.float64, device="cuda")
+        st, rep, _ = pl.solve_status(q, to_dev(U0, torch), us)
+        torch.cuda.synchronize()
+        runs.append((st, us, rep))
+    (sa, a, ra), (sb, b, rb) = runs
+    print(f"status {sa} {sb} iterations {ra.iters} {rb.iters} increments "
+          f"{[rb.incr[i] for i in range(rb.iters)]}", flush=True)
+    assert sa == sb and sa in (0, -5)
+    assert torch.equal(a, b) and same(ra, rb)
+    pc.close()
+
+
+def test_pipelined_chunks_larger_than_the_workspace(monkeypatch):
+    """T63, 20 intervals in 4 chunks of 5 slices on a plan of max_batch 4:
+    the relaxation propagates each chunk in pieces of at most 4 states."""
+    U0 = workloads.solid_body(63, noise=1e-3, seed=13)
+    q = pint.params(pint.MGRIT, 20, pint.stepper(240.0, 2, 0.0, pint.T_ALL), 4,
+                    pint.stepper(960.0, 4, 1e15, pint.T_ALL), 1, nrelax=1, max_iter=3)
+    env = {"PINT_SWEEP_CHUNKS": "4"}
+    a, ra = solve(plan_with(monkeypatch, {**env, "PINT_PIPELINE": "0"}, 63, 192, 96, 4), q, U0)
+    pb = plan_with(monkeypatch, env, 63, 192, 96, 4)
+    pb.reserve(q)
+    n0 = pb.info().allocations
+    b, rb = solve(pb, q, U0)
+    assert pb.info().allocations == n0          # the reservation covered the pipeline
+    assert torch.equal(a, b) and same(ra, rb)
