@@ -351,27 +351,52 @@ __device__ inline void asm_lane(const SE* __restrict__ Q, const int* __restrict_
     const int row = rowoff[2 * m + par] + ((k - m - par) >> 1);
     return Q + ((size_t)row * B + w.b) * 8;
   };
+  // each row once: (N_Phi, K, A, B) of the lane's positions; A and B of the
+  // neighbouring positions n - 1, n + 1 come from the lane itself or from
+  // the adjacent lanes of the chain's segment, and the row after the chain's
+  // last position (n = M + 1) is read by the lane that holds that position
+  double2 q[SEG][4];
+  double2 extA = zero, extB = zero;
+#pragma unroll
+  for (int k = 0; k < SEG; ++k) {
+    const int i = w.p0 + k;
+    q[k][0] = q[k][1] = q[k][2] = q[k][3] = zero;
+    if (i < w.K) {
+      const SE* r = qrow(m + i);
+#pragma unroll
+      for (int f = 0; f < 4; ++f) q[k][f] = get_c(r + 2 * f);
+      if (i + 1 == w.K) {
+        const SE* rn = qrow(m + w.K);
+        extA = get_c(rn + 4);
+        extB = get_c(rn + 6);
+      }
+    }
+  }
+  double2 pvA = shfl_up2(q[SEG - 1][2], 1), pvB = shfl_up2(q[SEG - 1][3], 1);
+  double2 nxA = shfl_down2(q[0][2], 1), nxB = shfl_down2(q[0][3], 1);
+  if (w.lane == w.slo) pvA = pvB = zero;
+  if (w.lane == w.shi - 1) nxA = nxB = zero;
   const double ha = 0.5 / a;
 #pragma unroll
   for (int k = 0; k < SEG; ++k) {
     const int i = w.p0 + k, n = m + i;
     N[k][0] = N[k][1] = N[k][2] = zero;
     if (i < w.K) {
-      const SE* q0 = qrow(n);
-      const SE* qp = qrow(n + 1);
-      double2 qAm = zero, qBm = zero;
-      if (n > m) {
-        const SE* qm = qrow(n - 1);
-        qAm = get_c(qm + 4);
-        qBm = get_c(qm + 6);
+      const double2 qAm = k > 0 ? q[k - 1][2] : pvA;        // zero at n = m
+      const double2 qBm = k > 0 ? q[k - 1][3] : pvB;
+      double2 qAp = k + 1 < SEG ? q[k + 1][2] : nxA;
+      double2 qBp = k + 1 < SEG ? q[k + 1][3] : nxB;
+      if (i + 1 == w.K) {
+        qAp = extA;
+        qBp = extB;
       }
       const double e0 = eps_nm(n, m), e1 = eps_nm(n + 1, m);
-      const double2 Kc = cscale(get_c(q0 + 2), 0.5);
-      const double2 hB = cadd(cscale(get_c(qp + 6), -n * e1), cscale(qBm, (n + 1) * e0));
-      const double2 hA = cadd(cscale(get_c(qp + 4), -n * e1), cscale(qAm, (n + 1) * e0));
-      const double2 div = cscale(csub(cimul(get_c(q0 + 4), (double)m), hB), ha);
-      const double2 curl = cscale(cadd(cimul(get_c(q0 + 6), (double)m), hA), ha);
-      N[k][0] = cscale(get_c(q0), 0.5);
+      const double2 Kc = cscale(q[k][1], 0.5);
+      const double2 hB = cadd(cscale(qBp, -n * e1), cscale(qBm, (n + 1) * e0));
+      const double2 hA = cadd(cscale(qAp, -n * e1), cscale(qAm, (n + 1) * e0));
+      const double2 div = cscale(csub(cimul(q[k][2], (double)m), hB), ha);
+      const double2 curl = cscale(cadd(cimul(q[k][3], (double)m), hA), ha);
+      N[k][0] = cscale(q[k][0], 0.5);
       if (!(m == 0 && n == 0)) {
         N[k][1] = cscale(div, -1.0);
         N[k][2] = cadd(curl, cscale(Kc, (double)n * (n + 1) / (a * a)));
