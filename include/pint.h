@@ -308,6 +308,25 @@ typedef struct {
                              on the plan itself).
                              Not thread-safe with other calls on either
                              plan.                                         */
+  const pint_sl_stepper* coarse_sl; /* NULL: coarse level IMEX (`coarse`).
+                             Otherwise two-level MGRIT (method 1, levels 2)
+                             with an SL-SI-SETTLS coarse level (Sec. 2.3.2)
+                             of one step of this stepper per C-interval
+                             (coarse_steps = 1, coarse_sl->dt = fine.dt *
+                             fine_steps; `coarse` is not used), on the plan
+                             itself (coarse_plan NULL; PINT_FP64 plan with
+                             max_batch >= 2).  The coarse level is the
+                             coarsest, so every coarse step is the two-step
+                             scheme (Sec. 3.2.4): its history is the
+                             previous point of the coarse sequence it
+                             continues (the relaxed C-point i-1 for the
+                             coarse value of C-point i, the corrected point
+                             i-1 in the serial solve), and only the first
+                             point of the horizon takes the one-step
+                             variant.  A converged prefix then stays exact
+                             (finite termination holds).  The iteration
+                             runs on `stream` alone (no overlap of the
+                             sweep with the fine propagation).             */
 } pint_pint_params;
 
 typedef struct {

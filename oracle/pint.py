@@ -181,6 +181,51 @@ def mgrit2(u0, n_coarse, m, phi0, phi1, nu, n_iter, record=False,
     return C, (history, incrs)
 
 
+def mgrit2_sl(u0, n_coarse, m, phi0, coarse2, nu, n_iter, record=False):
+    """Two-level MGRIT, F(CF)^nu relaxation, with a two-step coarse scheme
+    (SL-SI-SETTLS, Sec. 2.3.2) of one step per C-interval: coarse2(u, p) is
+    that step from u with p the state one coarse step earlier (None: the
+    one-step variant).  The coarse level is the coarsest one, so the
+    two-step scheme runs in all its steps (Sec. 3.2.4; one device: no
+    processor boundaries).  Reading: the history of a coarse step from a
+    point of a coarse sequence is the sequence's previous point -- v_{i-1}
+    for Phi_1(v_i) in the FAS term, w_{i-1} for Phi_1(w_i) in the serial
+    solve, u_{i-1} in the initial coarse sweep -- and the first point has
+    none.  With w = v on a prefix both steps are the same step, so the
+    correction vanishes there exactly and the finite termination of the
+    two-level iteration holds.  Returns C-point states as ``mgrit2``."""
+    N1 = n_coarse
+    C = [u0] + [None] * N1
+    for i in range(N1):
+        C[i + 1] = coarse2(C[i], C[i - 1] if i > 0 else None)
+    history = [list(C)] if record else None
+
+    def f_relax(Cpts):
+        last = [None] * N1
+        for i in range(N1):
+            u = Cpts[i]
+            for _ in range(m - 1):
+                u = phi0(u)
+            last[i] = u
+        return last
+
+    for _ in range(n_iter):
+        last = f_relax(C)
+        for _ in range(nu):
+            C = [C[0]] + [phi0(last[i]) for i in range(N1)]
+            last = f_relax(C)
+        Fv = [phi0(last[i]) for i in range(N1)]
+        Gv = [coarse2(C[i], C[i - 1] if i > 0 else None) for i in range(N1)]
+        W = [C[0]] + [None] * N1
+        for i in range(N1):
+            Gw = Gv[i] if i == 0 else coarse2(W[i], W[i - 1])
+            W[i + 1] = (Gw - Gv[i]) + Fv[i]
+        C = W
+        if record:
+            history.append(list(C))
+    return C, (history, [])
+
+
 def _two_level_on_level1(W, psi, phi2, m1, nu, cycles):
     """`cycles` two-level MGRIT iterations on levels (1, 2) of the level-1
     problem w_i = psi(i, w_{i-1}) (i = 1..N1), starting from the list W

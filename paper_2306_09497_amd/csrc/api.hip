@@ -118,7 +118,7 @@ pint_status check_params(const Plan& p, const pint_pint_params* q) {
     return PINT_E_INVAL;
   }
   PINT_TRY(check_stepper(p, &q->fine));
-  PINT_TRY(check_stepper(p, &q->coarse));
+  if (!q->coarse_sl) PINT_TRY(check_stepper(p, &q->coarse));
   if (q->method != 0 && q->method != 1) {
     set_error("method must be 0 (Parareal) or 1 (MGRIT)");
     return PINT_E_INVAL;
@@ -130,7 +130,16 @@ pint_status check_params(const Plan& p, const pint_pint_params* q) {
               "0 <= nrelax <= 8, tol >= 0, resume in {0, 1}");
     return PINT_E_INVAL;
   }
-  const double DTf = q->fine.dt * q->fine_steps, DTc = q->coarse.dt * q->coarse_steps;
+  if (q->coarse_sl) {
+    if (q->method != 1 || q->levels == 3 || q->coarse_steps != 1 || q->coarse_plan) {
+      set_error("an SL-SI-SETTLS coarse level needs two-level MGRIT (method 1, levels 2), "
+                "coarse_steps = 1 and no coarse_plan");
+      return PINT_E_INVAL;
+    }
+    PINT_TRY(sl_check(p, *q->coarse_sl, 1, 1));
+  }
+  const double DTf = q->fine.dt * q->fine_steps,
+               DTc = (q->coarse_sl ? q->coarse_sl->dt : q->coarse.dt) * q->coarse_steps;
   if (fabs(DTf - DTc) > 1e-9 * DTf) {
     set_error("fine (%g s) and coarse (%g s) propagators must span the same interval", DTf, DTc);
     return PINT_E_INVAL;
@@ -351,7 +360,7 @@ static pint_status level1_cycles(Plan& p, const pint_pint_params* q, Level1Bufs&
 // the plan's two): relax_cap states in six pool slots.
 static bool relax_pipelined(const Plan& p, const pint_pint_params* q) {
   return p.pipeline_relax && q->method == 1 && q->levels != 3 && q->nrelax == 1 &&
-         q->max_iter >= 2;
+         q->max_iter >= 2 && !q->coarse_sl;
 }
 static int relax_chunk(const Plan& p, int N) { return (N + p.sweep_chunks - 1) / p.sweep_chunks; }
 static int relax_cap(const Plan& p, int N) {
@@ -422,6 +431,10 @@ pint_status solve_footprint(const Plan& p, const pint_pint_params* q, Footprint&
     fp.need(kSlotCinSide, sdc);
   }
   fp.factors(fp.cn, q->fine.dt, q->fine.terms);
+  if (q->coarse_sl) {
+    sl_footprint(p, *q->coarse_sl, fp);
+    return PINT_OK;
+  }
   auto& cc = pc && pc != &p ? fp.cn_coarse : fp.cn;
   fp.factors(cc, q->coarse.dt, q->coarse.terms);
   if (three) fp.factors(cc, q->coarse2.dt, q->coarse2.terms);
@@ -488,20 +501,28 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
   // goes to the sweep stream
   const CnFactors* cf = nullptr;
   PINT_TRY(cn_factors(p, q->fine.dt, q->fine.terms, s, &cf));
-  PINT_TRY(cn_factors(coarse.stepping(), q->coarse.dt, q->coarse.terms, s, &cf));
+  const pint_sl_stepper* csl = q->coarse_sl;
+  if (csl) PINT_TRY(cn_factors(p, 2.0 * csl->dt, PINT_T_ALL, s, &cf));   // (I - dt/2 L)
+  else PINT_TRY(cn_factors(coarse.stepping(), q->coarse.dt, q->coarse.terms, s, &cf));
   if (three) PINT_TRY(cn_factors(coarse.stepping(), q->coarse2.dt, q->coarse2.terms, s, &cf));
   if (q->resume) {
     // continue from the iterate held in U; the coarse values of its slice
     // starts are recomputed (bitwise what the previous sweep produced)
-    if (nrelax == 0 && !three) {
+    if (nrelax == 0 && !three && !csl) {   // (the SL iteration makes its own)
       PINT_TRY(coarse.run(q->coarse, q->coarse_steps, U, Gold.p, N, s, false));
       r->coarse_steps += (long long)N * q->coarse_steps;
     }
   } else {
     if (U != u0) PINT_HIP(hipMemcpyAsync(U, u0, sb, hipMemcpyDeviceToDevice, s));
     // iteration 0: serial coarse sweep, G_n = phi_c(U_n), U_{n+1} = G_n
+    // (SL: the history of the step from U_n is U_{n-1})
     for (int n = 0; n < N; ++n) {
-      PINT_TRY(coarse.run(q->coarse, q->coarse_steps, U + n * sd, Gold.p + n * sd, 1, s, false));
+      if (csl)
+        PINT_TRY(sl_steps(p, *csl, n > 0 ? U + (n - 1) * sd : nullptr, U + n * sd,
+                          Gold.p + n * sd, nullptr, 1, 1, s));
+      else
+        PINT_TRY(coarse.run(q->coarse, q->coarse_steps, U + n * sd, Gold.p + n * sd, 1, s,
+                            false));
       PINT_HIP(hipMemcpyAsync(U + (n + 1) * sd, Gold.p + n * sd, sb, hipMemcpyDeviceToDevice, s));
       r->coarse_steps += q->coarse_steps;
     }
@@ -538,6 +559,25 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
         PINT_HIP(hipMemcpyAsync(U + sd, Fv.p, sb * N, hipMemcpyDeviceToDevice, s));
         r->fine_slice_steps += (long long)N * q->fine_steps;
       }
+    }
+    if (csl) {
+      // two-level MGRIT with an SL-SI-SETTLS coarse level, on s alone:
+      // Gold_i = Phi_1(v_i; v_{i-1}), F_i = Phi_0^m(v_i), then the serial
+      // solve U_{i+1} = (Phi_1(U_i; U_{i-1}) - Gold_i) + F_i
+      PINT_TRY(sl_steps(p, *csl, nullptr, U, Gold.p, nullptr, 1, 1, s));
+      if (N > 1) PINT_TRY(sl_steps(p, *csl, U, U + sd, Gold.p + sd, nullptr, N - 1, 1, s));
+      r->coarse_steps += N;
+      PINT_TRY(propagate(p, q->fine, U, Fv.p, N, q->fine_steps, s));
+      r->fine_slice_steps += (long long)N * q->fine_steps;
+      PINT_TRY(rec(p.ph_ev[1], s));
+      PINT_TRY(pr_update(p, Gold.p, Gold.p, Fv.p, U + sd, sd, s));
+      for (int n = 1; n < N; ++n) {
+        PINT_TRY(sl_steps(p, *csl, U + (n - 1) * sd, U + n * sd, Gtmp.p, nullptr, 1, 1, s));
+        PINT_TRY(pr_update(p, Gtmp.p, Gold.p + n * sd, Fv.p + n * sd, U + (n + 1) * sd, sd, s));
+        r->coarse_steps += 1;
+      }
+      PINT_TRY(rec(p.ph_ev[2], s));
+      return rel_diff_enqueue(p, U + sd, Uprev.p + sd, Incr.p, p.h_incr, N, s);
     }
     if (nrelax > 0) {
       // coarse values of the relaxed C-points, Phi_1(v_i): all of them now
@@ -663,7 +703,7 @@ static pint_status solve(Plan& p, const pint_pint_params* q, const double* u0, d
   // (not with the pipelined relaxation: its iterations leave work running
   // on the relax stream, which a graph launch would have to wait for)
   bool graphable = (mgrit || q->resume) && p.use_graphs && !p.prof_on &&
-                   !(coarse.pc && coarse.pc->prof_on) && !pipe;
+                   !(coarse.pc && coarse.pc->prof_on) && !pipe && !csl;
   pint_status result = PINT_OK;
   for (int k = 0; k < q->max_iter; ++k) {
     const double t0 = now_s();

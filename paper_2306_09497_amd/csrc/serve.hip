@@ -497,7 +497,7 @@ pint_status pint_server_submit(pint_server* S, const pint_request* req, long lon
   Plan& p = *S->plans[req->plan];
   const pint_pint_params& q = req->params;
   PINT_TRY(check_params(p, &q));
-  if ((q.levels != 0 && q.levels != 2) || q.coarse_plan || q.resume) {
+  if ((q.levels != 0 && q.levels != 2) || q.coarse_plan || q.resume || q.coarse_sl) {
     set_error("the server runs two-level solves on the plan's truncation "
               "(levels 2, no coarse_plan, resume 0)");
     return PINT_E_INVAL;

@@ -69,7 +69,7 @@ class PintParams(ctypes.Structure):
                 ("nrelax", ctypes.c_int), ("max_iter", ctypes.c_int), ("tol", ctypes.c_double),
                 ("resume", ctypes.c_int), ("levels", ctypes.c_int), ("cfactor1", ctypes.c_int),
                 ("coarse2", Stepper), ("coarse2_steps", ctypes.c_int), ("cycles1", ctypes.c_int),
-                ("coarse_plan", ctypes.c_void_p)]
+                ("coarse_plan", ctypes.c_void_p), ("coarse_sl", ctypes.POINTER(SlStepper))]
 
 
 class ProfEntry(ctypes.Structure):
@@ -391,14 +391,18 @@ class Plan:
 
 def params(method, n_intervals, fine, fine_steps, coarse, coarse_steps, nrelax=0, max_iter=1,
            tol=0.0, resume=False, levels=2, cfactor1=0, coarse2=None, coarse2_steps=1,
-           cycles1=1, coarse_plan=None):
+           cycles1=1, coarse_plan=None, coarse_sl=None):
     """Parameters of Plan.solve; coarse_plan (a Plan at a truncation <= this
-    plan's) runs the coarse levels with spatial coarsening."""
+    plan's) runs the coarse levels with spatial coarsening; coarse_sl (an
+    sl_stepper) makes the coarse level of two-level MGRIT SL-SI-SETTLS, one
+    step per C-interval (then `coarse` is not used: pass None)."""
     c2 = coarse2 if coarse2 is not None else Stepper(0.0, 2, 0.0, 0)
+    c1 = coarse if coarse is not None else Stepper(0.0, 2, 0.0, 0)
     cp = coarse_plan._h.value if coarse_plan is not None else None
-    return PintParams(int(method), int(n_intervals), fine, int(fine_steps), coarse,
+    csl = ctypes.pointer(coarse_sl) if coarse_sl is not None else None
+    return PintParams(int(method), int(n_intervals), fine, int(fine_steps), c1,
                       int(coarse_steps), int(nrelax), int(max_iter), float(tol), int(resume),
-                      int(levels), int(cfactor1), c2, int(coarse2_steps), int(cycles1), cp)
+                      int(levels), int(cfactor1), c2, int(coarse2_steps), int(cycles1), cp, csl)
 
 
 class Server:

@@ -216,3 +216,60 @@ def test_largest_ring_rest_and_steady_flow():
     ref[0, 0, 0] -= PHIBAR
     assert float(torch.linalg.vector_norm(d)) < 1e-6 * float(torch.linalg.vector_norm(ref))
     plan.close()
+
+
+@pytest.mark.parametrize("key,nu", [("T21", 1), ("T42", 0), ("T42", 1)])
+def test_mgrit_with_sl_coarse_level(key, nu):
+    """Two-level MGRIT (Sec. 3.2) with the fine IMEX propagator and an
+    SL-SI-SETTLS coarse level of one step per C-interval, through pint_solve,
+    against the oracle's ``mgrit2_sl`` (the coarse level is the coarsest, so
+    every coarse step is the two-step scheme with the previous point of its
+    coarse sequence as history, Sec. 3.2.4): every C-point after 3
+    iterations, and iterate 0 (the initial two-step coarse sweep)."""
+    from oracle import pint as opint
+    md, plan = setup(key)
+    N, m, dtf = 4, 8, 225.0
+    U0 = states(md, 1, 80)[0]
+    ost = sl.SLStepper(md, m * dtf, nu=1e6, q=2, iters=2)
+    fine_ref = lambda U: md.propagate(U, dtf, 1, nu=1e5, q=2)
+    for k in (0, 3):
+        want, _ = opint.mgrit2_sl(U0, N, m, fine_ref, ost.step, nu, k)
+        q = pint.params(pint.MGRIT, N, pint.stepper(dtf, 2, 1e5, pint.T_ALL), m, None, 1,
+                        nrelax=nu, max_iter=k, coarse_sl=pint.sl_stepper(m * dtf, 2, 2, 1e6))
+        got = torch.zeros((N + 1, 3, md.grid.nc, 2), dtype=torch.float64, device="cuda")
+        rep = plan.solve(q, to_dev(U0, torch), got)
+        torch.cuda.synchronize()
+        got = from_dev(got)
+        assert rep.iters == k and rep.coarse_steps == N + k * (2 * N - 1)
+        for i in range(N + 1):
+            assert_parity(got[i], want[i], md.M, "sl")
+
+
+def test_mgrit_sl_coarse_checks_and_reservation():
+    """The SL coarse level is refused with three levels, a coarse plan or
+    more than one coarse step per interval; a reserved SL solve allocates
+    nothing; with nu = 0 it is the carried-state Parareal of pint_parareal_sl
+    (one coarse step per slice), bitwise."""
+    md, plan = setup("T21")
+    N, m, dtf = 4, 8, 225.0
+    fine = pint.stepper(dtf, 2, 1e5, pint.T_ALL)
+    csl = pint.sl_stepper(m * dtf, 2, 2, 1e6)
+    U0 = states(md, 1, 81)[0]
+    u0 = to_dev(U0, torch)
+    out = torch.zeros((N + 1, 3, md.grid.nc, 2), dtype=torch.float64, device="cuda")
+    for kw in (dict(coarse_steps=2), dict(levels=3, cfactor1=2, coarse2=fine)):
+        cs = kw.pop("coarse_steps", 1)
+        q = pint.params(pint.MGRIT, N, fine, m, None, cs, nrelax=1, max_iter=1, coarse_sl=csl,
+                        **kw)
+        with pytest.raises(pint.PintError):
+            plan.solve(q, u0, out)
+    q = pint.params(pint.MGRIT, N, fine, m, None, 1, nrelax=0, max_iter=3, coarse_sl=csl)
+    plan.reserve(q)
+    n0 = plan.info().allocations
+    plan.solve(q, u0, out)
+    torch.cuda.synchronize()
+    assert plan.info().allocations == n0
+    pr = torch.zeros((N + 1, 1, 3, md.grid.nc, 2), dtype=torch.float64, device="cuda")
+    plan.parareal_sl(fine, m, csl, 1, N, 3, u0[None], pr, n_inst=1, restart=False)
+    torch.cuda.synchronize()
+    assert torch.equal(out, pr[:, 0])

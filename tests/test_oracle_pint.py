@@ -296,3 +296,58 @@ def test_parareal_carry_without_history_is_parareal():
     G = _ab2_coarse(lam, 0.1, 5)
     U, _ = pint.parareal_carry(1.0 + 0j, N, fine, G, N)
     assert U == pint.serial(1.0 + 0j, N, fine)
+
+
+def _ab2_step(lam, h):
+    """One step of the two-step scheme of _ab2_coarse: (u, p) -> u'."""
+    def g(u, p):
+        prev = u if p is None else p
+        return u + h * lam * (1.5 * u - 0.5 * prev)
+    return g
+
+
+def test_mgrit2_sl_without_history_is_mgrit2():
+    """A coarse step that ignores its history gives the two-level MGRIT
+    iterates bitwise (nu = 0, 1)."""
+    lam, N, m = -0.4 + 0.8j, 6, 3
+    phi0 = lambda u: u * np.exp(lam * 0.1)
+    g1 = lambda u: u * (1.0 + lam * 0.3)
+    for nu in (0, 1):
+        a, _ = pint.mgrit2(1.0 + 0.2j, N, m, phi0, g1, nu, 3)
+        b, _ = pint.mgrit2_sl(1.0 + 0.2j, N, m, phi0, lambda u, p: g1(u), nu, 3)
+        assert a == b
+
+
+def test_mgrit2_sl_initial_sweep_and_nu0_carried_parareal():
+    """Iterate 0 is the uninterrupted two-step run; with nu = 0 the
+    iteration is Parareal whose coarse runs carry the previous slice state
+    (one step per slice), bitwise."""
+    lam, N, m, h = 0.3 - 1.2j, 6, 4, 0.05
+    g = _ab2_step(lam, h)
+    phi0 = lambda u: u * np.exp(lam * h / m)
+    C, _ = pint.mgrit2_sl(1.0 + 0.5j, N, m, phi0, g, 0, 0)
+    u, prev = 1.0 + 0.5j, None
+    for n in range(N):
+        u, prev = g(u, prev), u
+        assert C[n + 1] == u
+    G = lambda u, p: (g(u, p), u)
+    for k in range(1, 4):
+        a, _ = pint.mgrit2_sl(1.0 + 0.5j, N, m, phi0, g, 0, k)
+        b, _ = pint.parareal_carry(1.0 + 0.5j, N, lambda u: pint.serial(u, m, phi0)[-1], G, k)
+        assert a == b
+
+
+@pytest.mark.parametrize("nu", [0, 1, 2])
+def test_mgrit2_sl_finite_termination(nu):
+    """With the history taken from the same coarse sequence, a converged
+    prefix stays bitwise exact: after ceil(N/(nu+1)) iterations every
+    C-point is the serial fine solution bitwise (Sec. 3.2.3)."""
+    lam, N, m, h = -0.2 + 0.9j, 7, 3, 0.2
+    g = _ab2_step(lam, h)
+    phi0 = lambda u: u * np.exp(lam * h / m)
+    ref = pint.serial(1.0 - 0.3j, N * m, phi0)
+    k = -(-N // (nu + 1))
+    C, _ = pint.mgrit2_sl(1.0 - 0.3j, N, m, phi0, g, nu, k)
+    assert C == [ref[i * m] for i in range(N + 1)]
+    C1, _ = pint.mgrit2_sl(1.0 - 0.3j, N, m, phi0, g, nu, 1)
+    assert C1[N] != ref[N * m]                  # not converged after one iteration
