@@ -102,3 +102,29 @@ def test_pipelined_chunks_larger_than_the_workspace(monkeypatch):
     b, rb = solve(pb, q, U0)
     assert pb.info().allocations == n0          # the reservation covered the pipeline
     assert torch.equal(a, b) and same(ra, rb)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_pipelined_short_horizons(monkeypatch, N):
+    """One to three C-intervals (chunks of one slice; with N = 1 the only
+    relaxed value is never used), four iterations."""
+    U0 = workloads.solid_body(21, noise=1e-3, seed=20 + N)
+    q = fcf(N, 4)
+    a, ra = solve(plan_with(monkeypatch, {"PINT_PIPELINE": "0"}), q, U0)
+    b, rb = solve(plan_with(monkeypatch, {}), q, U0)
+    assert torch.equal(a, b) and same(ra, rb)
+
+
+def test_pipelined_tolerance_after_the_first_iteration(monkeypatch):
+    """A tolerance reached after one iteration: the relaxation made for the
+    second iteration is discarded, the returned iterate is the first one,
+    and a later solve on the same plan and stream is unaffected."""
+    U0 = workloads.solid_body(21, noise=1e-3, seed=30)
+    pa, pb = plan_with(monkeypatch, {"PINT_PIPELINE": "0"}), plan_with(monkeypatch, {})
+    q = fcf(8, 5, tol=1.0)
+    a, ra = solve(pa, q, U0)
+    b, rb = solve(pb, q, U0)
+    assert rb.iters == 1 and torch.equal(a, b) and same(ra, rb)
+    a, ra = solve(pa, fcf(8, 3), U0)
+    b, rb = solve(pb, fcf(8, 3), U0)
+    assert torch.equal(a, b) and same(ra, rb)
