@@ -226,7 +226,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
     for (int j = 0; j < BJ; ++j) acc[i][j] = MM::zero();
 
-  E ra[NA], rbe[NB], rbo[NB];
+  // the next slab's loads stay in flight across the current slab's matrix
+  // products: fetch only issues them (raw north and south values), and the
+  // parity sums are formed when the slab is stashed
+  E ra[NA], rgn[NB], rgs[NB];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int e4 = 0; e4 < NA; ++e4) {
@@ -245,15 +248,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       const int e = tid + e4 * 256;
       const int kk = e / TC, cc = e % TC;
       const int k = k0 + kk, c = col0 + cc;
-      E ve = E(0), vo = E(0);
+      E gn = E(0), gs = E(0);
       if (k < nlat2 && c < ncol) {
-        const E gn = G[gbase + (size_t)k * ncol + c];
-        const E gs = G[gbase + (size_t)(nlat - 1 - k) * ncol + c];
-        ve = gn + gs;
-        vo = gn + E(-1) * gs;
+        gn = G[gbase + (size_t)k * ncol + c];
+        gs = G[gbase + (size_t)(nlat - 1 - k) * ncol + c];
       }
-      rbe[e4] = ve;
-      rbo[e4] = vo;
+      rgn[e4] = gn;
+      rgs[e4] = gs;
     }
   };
   auto stash = [&]() {
@@ -265,8 +266,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
     for (int e4 = 0; e4 < NB; ++e4) {
       const int e = tid + e4 * 256;
-      Bs[0][(e / TC) * LDB + (e % TC)] = rbe[e4];
-      Bs[1][(e / TC) * LDB + (e % TC)] = rbo[e4];
+      Bs[0][(e / TC) * LDB + (e % TC)] = rgn[e4] + rgs[e4];
+      Bs[1][(e / TC) * LDB + (e % TC)] = rgn[e4] + E(-1) * rgs[e4];
     }
   };
   const int nslab = (nlat2 + TK - 1) / TK;
@@ -520,7 +521,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int a_off = (a_odd ? roffO : roffE) + a_row;
   const bool bload = tid < TC * kBfKG;
   const int rb_c = tid % TC, rb_g = tid / TC;
-  float xa[8], xe[8], xo[8];
+  float xa[8], xn[8], xs[8];   // raw north / south values: sums formed at stash
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -532,15 +533,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int k = k0 + 8 * rb_g + e;
-        float ve = 0.0f, vo = 0.0f;
+        float gn = 0.0f, gs = 0.0f;
         if (k < nlat2 && c < ncol) {
-          const float gn = G[gbase + (size_t)k * ncol + c];
-          const float gs = G[gbase + (size_t)(nlat - 1 - k) * ncol + c];
-          ve = gn + gs;
-          vo = gn - gs;
+          gn = G[gbase + (size_t)k * ncol + c];
+          gs = G[gbase + (size_t)(nlat - 1 - k) * ncol + c];
         }
-        xe[e] = ve;
-        xo[e] = vo;
+        xn[e] = gn;
+        xs[e] = gs;
       }
     }
   };
@@ -550,6 +549,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     Ah[ra_r * kBfLD + ra_g] = h;
     Al[ra_r * kBfLD + ra_g] = l;
     if (bload) {
+      float xe[8], xo[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        xe[e] = xn[e] + xs[e];
+        xo[e] = xn[e] - xs[e];
+      }
       split8(xe, h, l);
       Bh[0][rb_c * kBfLD + rb_g] = h;
       Bl[0][rb_c * kBfLD + rb_g] = l;
