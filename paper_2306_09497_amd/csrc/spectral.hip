@@ -79,6 +79,12 @@ struct WaveAt {
   int m, b, K, i0, lane, p0, slo, shi;
 };
 
+// Position i of the lane clamped to its chain (K >= 1): every load a lane
+// makes is then in bounds and issued unconditionally, beside the others of
+// its phase, and the value of a position past the chain's end is replaced by
+// what it stands for (zero, or an identity map) afterwards.
+__device__ inline int clamp_pos(int i, const WaveAt& w) { return i < w.K ? i : w.K - 1; }
+
 // A workgroup holds kSpecWaves waves: the states b0 .. b0+kSpecWaves-1 of one
 // task, whose rows of S and Q are adjacent in memory.  Logical block
 // task * nbg + bg, XCD-remapped.  A wave past the last state has nothing to do
@@ -115,10 +121,12 @@ __device__ inline void load_state(const double* __restrict__ u, const WaveAt& w,
                                   double2 (&V)[SEG][3]) {
 #pragma unroll
   for (int k = 0; k < SEG; ++k) {
-    const int i = w.p0 + k;
+    const int i = w.p0 + k, ic = clamp_pos(i, w);
 #pragma unroll
-    for (int f = 0; f < 3; ++f)
-      V[k][f] = i < w.K ? ld2(u, ((size_t)w.b * 3 + f) * ncoef + w.i0 + i) : make_double2(0.0, 0.0);
+    for (int f = 0; f < 3; ++f) {
+      const double2 v = ld2(u, ((size_t)w.b * 3 + f) * ncoef + w.i0 + ic);
+      V[k][f] = i < w.K ? v : make_double2(0.0, 0.0);
+    }
   }
 }
 
@@ -185,8 +193,8 @@ __device__ inline void cn_lane(double2 (&V)[SEG][3], const WaveAt& w, int ncoef,
     const double2 xim = k > 0 ? V[k - 1][1] : prev[1], dem = k > 0 ? V[k - 1][2] : prev[2];
     const double2 xip = k + 1 < SEG ? V[k + 1][1] : next[1];
     const double2 dep = k + 1 < SEG ? V[k + 1][2] : next[2];
+    const double4 cf = c.co[w.i0 + clamp_pos(i, w)];
     if (i < w.K) {
-      const double4 cf = c.co[w.i0 + i];
       const double A = c.W * cf.x, Bc = c.W * cf.y, C = c.W * cf.z, lap = c.lgf * cf.w;
       const double2 yphi = V[k][0], yxi = V[k][1], yde = V[k][2];
       double2 axi = cimul(yxi, Bc), ade = cadd(cscale(yphi, lap), cimul(yde, Bc));
@@ -213,10 +221,11 @@ __device__ inline void cn_lane(double2 (&V)[SEG][3], const WaveAt& w, int ncoef,
     double2 al[SEG], be[SEG], ga[SEG];
 #pragma unroll
     for (int k = 0; k < SEG; ++k) {
-      const int i = w.p0 + k;
-      al[k] = i < w.K ? c.alph[fb + i] : one;
-      ga[k] = i < w.K ? c.gam[fb + i] : one;
-      be[k] = i < w.K ? cmul(c.invpiv[fb + i], rv[ch][k]) : zero;
+      const int i = w.p0 + k, ic = clamp_pos(i, w);
+      const double2 a0 = c.alph[fb + ic], g0 = c.gam[fb + ic], p0 = c.invpiv[fb + ic];
+      al[k] = i < w.K ? a0 : one;
+      ga[k] = i < w.K ? g0 : one;
+      be[k] = i < w.K ? cmul(p0, rv[ch][k]) : zero;
     }
     double2 A = one, Bv = zero;
 #pragma unroll
@@ -354,22 +363,19 @@ __device__ inline void asm_lane(const SE* __restrict__ Q, const int* __restrict_
   // each row once: (N_Phi, K, A, B) of the lane's positions; A and B of the
   // neighbouring positions n - 1, n + 1 come from the lane itself or from
   // the adjacent lanes of the chain's segment, and the row after the chain's
-  // last position (n = M + 1) is read by the lane that holds that position
+  // last position (n = M + 1) is read by every lane (one address per chain)
+  // and used by the lane that holds that position
   double2 q[SEG][4];
-  double2 extA = zero, extB = zero;
+  const SE* rn = qrow(m + w.K);
+  const double2 extA = get_c(rn + 4), extB = get_c(rn + 6);
 #pragma unroll
   for (int k = 0; k < SEG; ++k) {
     const int i = w.p0 + k;
-    q[k][0] = q[k][1] = q[k][2] = q[k][3] = zero;
-    if (i < w.K) {
-      const SE* r = qrow(m + i);
+    const SE* r = qrow(m + clamp_pos(i, w));
 #pragma unroll
-      for (int f = 0; f < 4; ++f) q[k][f] = get_c(r + 2 * f);
-      if (i + 1 == w.K) {
-        const SE* rn = qrow(m + w.K);
-        extA = get_c(rn + 4);
-        extB = get_c(rn + 6);
-      }
+    for (int f = 0; f < 4; ++f) {
+      const double2 v = get_c(r + 2 * f);
+      q[k][f] = i < w.K ? v : zero;
     }
   }
   double2 pvA = shfl_up2(q[SEG - 1][2], 1), pvB = shfl_up2(q[SEG - 1][3], 1);
