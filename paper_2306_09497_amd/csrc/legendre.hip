@@ -230,44 +230,48 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   // products: fetch only issues them (raw north and south values), and the
   // parity sums are formed when the slab is stashed
   E ra[NA], rgn[NB], rgs[NB];
+  bool pa[NA], pb[NB];
+  // loads at clamped indices, issued without branches (32-bit offsets within
+  // the table and within m's Fourier rows), out-of-tile elements zeroed
+  static_assert(256 % TR == 0 && 256 % TC == 0, "a thread keeps its row and column");
+  const int ri = tid % TR;
+  const bool odd = ri >= TR2;
+  const int ar = row0 + (odd ? ri - TR2 : ri), acnt = odd ? cntO : cntE;
+  const bool aok = ar < acnt;
+  const int acol = (odd ? roffO : roffE) + (aok ? ar : acnt - 1);
+  const int bc = col0 + tid % TC;
+  const bool bok = bc < ncol;
+  const int bcl = bok ? bc : ncol - 1;
+  const E* Gm = G + gbase;
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int e4 = 0; e4 < NA; ++e4) {
-      const int e = tid + e4 * 256;
-      const int kk = e / TR, ri = e % TR;
-      const int k = k0 + kk;
-      const bool odd = ri >= TR2;
-      const int r = row0 + (odd ? ri - TR2 : ri);
-      E v = E(0);
-      if (k < nlat2 && r < (odd ? cntO : cntE))
-        v = Tt[(size_t)k * nrows + (odd ? roffO : roffE) + r];
-      ra[e4] = v;
+      const int k = k0 + (tid + e4 * 256) / TR;
+      const int kc = k < nlat2 ? k : nlat2 - 1;
+      ra[e4] = Tt[kc * nrows + acol];
+      pa[e4] = k < nlat2 && aok;
     }
 #pragma unroll
     for (int e4 = 0; e4 < NB; ++e4) {
-      const int e = tid + e4 * 256;
-      const int kk = e / TC, cc = e % TC;
-      const int k = k0 + kk, c = col0 + cc;
-      E gn = E(0), gs = E(0);
-      if (k < nlat2 && c < ncol) {
-        gn = G[gbase + (size_t)k * ncol + c];
-        gs = G[gbase + (size_t)(nlat - 1 - k) * ncol + c];
-      }
-      rgn[e4] = gn;
-      rgs[e4] = gs;
+      const int k = k0 + (tid + e4 * 256) / TC;
+      const int kc = k < nlat2 ? k : nlat2 - 1;
+      rgn[e4] = Gm[kc * ncol + bcl];
+      rgs[e4] = Gm[(nlat - 1 - kc) * ncol + bcl];
+      pb[e4] = k < nlat2 && bok;
     }
   };
   auto stash = [&]() {
 #pragma unroll
     for (int e4 = 0; e4 < NA; ++e4) {
       const int e = tid + e4 * 256;
-      As[(e / TR) * LDA + (e % TR)] = ra[e4];
+      As[(e / TR) * LDA + (e % TR)] = pa[e4] ? ra[e4] : E(0);
     }
 #pragma unroll
     for (int e4 = 0; e4 < NB; ++e4) {
       const int e = tid + e4 * 256;
-      Bs[0][(e / TC) * LDB + (e % TC)] = rgn[e4] + rgs[e4];
-      Bs[1][(e / TC) * LDB + (e % TC)] = rgn[e4] + E(-1) * rgs[e4];
+      const E gn = pb[e4] ? rgn[e4] : E(0), gs = pb[e4] ? rgs[e4] : E(0);
+      Bs[0][(e / TC) * LDB + (e % TC)] = gn + gs;
+      Bs[1][(e / TC) * LDB + (e % TC)] = gn + E(-1) * gs;
     }
   };
   const int nslab = (nlat2 + TK - 1) / TK;
