@@ -5,7 +5,11 @@ with q = 4, nu = 1e17, two-level MGRIT FCF over 64 C-intervals x 4.
 * One batched fine step of 64 states against the oracle on sampled states.
 * The MGRIT iteration pint_solve runs (chunked fine propagation, serial sweep
   on a second stream) against the same iteration composed here from single
-  pint_step calls and elementwise updates: bitwise, on every slice."""
+  pint_step calls and elementwise updates: bitwise, on every slice.
+* Batch invariance at this size in every precision: a state stepped in a
+  shuffled 64-state launch, in a 16-state launch and alone gives bitwise the
+  same result (64- and 16-column GEMM tiles, both ring workgroup shapes,
+  packed spectral tasks at four waves and at one wave per workgroup)."""
 
 import numpy as np
 import pytest
@@ -116,3 +120,31 @@ def test_bench_iteration_composed_bitwise(model, plan):
         W[n + 1] = (gnew[0] - Gold[n]) + Fv[n]
     torch.cuda.synchronize()
     assert torch.equal(W, slices)
+
+
+@pytest.mark.parametrize("precision", [pint.FP64, pint.LEG_FP32, pint.LEG_BF16X3])
+def test_batch_invariance_bench_size_bitwise(model, precision):
+    """Two coarse IMEX steps of T255 states: in a shuffled 64-state launch,
+    a 16-state launch and alone, bitwise the same in each precision."""
+    Us = batch_states(model, GROUP)
+    st = pint.stepper(DT_C, Q_C, NU_C, pint.T_ALL)
+    pl = pint.Plan(M, NLON, NLAT, phibar=PHIBAR, max_batch=GROUP, precision=precision)
+    try:
+        order = np.random.default_rng(3).permutation(GROUP)
+        u64 = to_dev(np.stack([Us[i] for i in order]), torch)
+        pl.step(st, u64, u64, GROUP, 2)
+        u16 = to_dev(np.stack(Us[:16]), torch)
+        pl.step(st, u16, u16, 16, 2)
+        alone = {}
+        for i in (0, 5, 37, 63):
+            u1 = to_dev(Us[i], torch)
+            pl.step(st, u1, u1, 1, 2)
+            alone[i] = u1
+        torch.cuda.synchronize()
+        pos = {int(b): k for k, b in enumerate(order)}
+        for i in range(16):
+            assert torch.equal(u16[i], u64[pos[i]]), i
+        for i, u1 in alone.items():
+            assert torch.equal(u1[0], u64[pos[i]]), i
+    finally:
+        pl.close()
